@@ -1,0 +1,160 @@
+/*
+ * fr.h -- C ABI of the MI355X flux-reconstruction residual / RK4 library (libfrmi.so).
+ *
+ * The library evaluates the explicit FR residual of the compressible Navier-Stokes
+ * (or Euler) equations -- conservation law Eq. (1), conserved variables Eq. (2),
+ * fluxes Eqs. (3)-(7) of the governing-equations subsection -- with the flux
+ * reconstruction scheme named in the flow-solver subsection (Gauss-Legendre
+ * solution/flux points, g_DG correction, Rusanov + LDG common fluxes, adiabatic
+ * no-slip walls and Riemann-invariant far field as in the computational-details
+ * paragraphs), advances it with classical RK4, and accumulates the probe-pressure
+ * and wall-force statistics that feed Eqs. (8)-(12).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: FR_OK (0) or a negative fr_status.  No C++ exception crosses the
+ *    ABI.  fr_last_error() gives a thread-local message for the last failure.
+ *  - Arguments are validated before any launch; an invalid argument launches nothing.
+ *  - "device" pointers are HIP device memory (e.g. torch CUDA tensors on ROCm);
+ *    "host" pointers are ordinary CPU memory.  The caller owns every buffer it passes;
+ *    the solver handle owns operators, metrics, connectivity, work arrays, HIP graphs
+ *    and the FP64 accumulators.
+ *  - State layout: element-major  u[n_elem][nv][Ns], contiguous, nv = dim + 2
+ *    (rho, rho u_1..rho u_dim, rho E), Ns = (p+1)^dim solution points in lexicographic
+ *    order (first reference coordinate fastest).  Element type: double for FR_FP64,
+ *    float for FR_FP32 (the accumulators are always double).
+ *  - `stream` is a hipStream_t (NULL = default stream).  All work is ordered on it;
+ *    only fr_probe_oaspl / fr_probe_series / fr_solpt_coords synchronise it.
+ *    Device faults surface as FR_ERR_HIP at the next synchronising call.
+ *  - A handle is not thread safe; calls on one handle must not overlap.
+ */
+#ifndef FRMI_FR_H
+#define FRMI_FR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fr_status;
+#define FR_OK                0
+#define FR_ERR_ARG          -1  /* null pointer, bad size / enum / range               */
+#define FR_ERR_MESH         -2  /* non-positive Jacobian, unmatched face, probe outside */
+#define FR_ERR_UNSUPPORTED  -3  /* (dim, p) combination not compiled                    */
+#define FR_ERR_HIP          -4  /* HIP runtime error (launch, copy, device fault)       */
+#define FR_ERR_NONFINITE    -5  /* a sampled probe pressure was NaN / Inf               */
+#define FR_ERR_OOM          -6  /* device allocation failed                             */
+
+/* face tags (per element face) */
+#define FR_FACE_AUTO     0   /* matched geometrically with another face (conforming or periodic) */
+#define FR_BC_WALL       1   /* adiabatic no-slip wall                                            */
+#define FR_BC_FARFIELD   2   /* Riemann-invariant (characteristic) far field                      */
+
+#define FR_EULER          0
+#define FR_NAVIER_STOKES  1
+#define FR_FP64           0
+#define FR_FP32           1
+
+typedef struct fr_solver fr_solver;  /* opaque, library-owned */
+
+/*
+ * Mesh description (host pointers, read during fr_build_operators only).
+ *  dim 2|3; p 1..4 (solution degree); geom_q 1..4 geometry degree.
+ *  node_xyz[n_node][dim]: physical node coordinates.
+ *  elem_nodes[n_elem][(geom_q+1)^dim]: node ids at the tensor Gauss-Lobatto-Legendre
+ *      points of degree geom_q of [-1,1]^dim, first reference coordinate fastest;
+ *      elements must be right-handed (positive Jacobian) -> else FR_ERR_MESH.
+ *  face_bc[n_elem][2*dim]: face f lies on reference coordinate f/2 at -1 (f even) or
+ *      +1 (f odd); tag FR_FACE_AUTO / FR_BC_WALL / FR_BC_FARFIELD.
+ *  periodic_vec[n_periodic][dim]: translations identifying FR_FACE_AUTO faces (nullable
+ *      when n_periodic = 0).
+ *  mesh_elem_begin[n_mesh+1]: disjoint element ranges of independent meshes advanced
+ *      together (batched designs); NULL means one mesh [0, n_elem).
+ */
+typedef struct {
+  int32_t dim, p, geom_q, n_periodic;
+  int64_t n_elem, n_node;
+  const double  *node_xyz;
+  const int64_t *elem_nodes;
+  const int32_t *face_bc;
+  const double  *periodic_vec;
+  int32_t        n_mesh;
+  int32_t        reserved0;
+  const int64_t *mesh_elem_begin;
+} fr_mesh_desc;
+
+/*
+ * Physical and run parameters (host pointers, copied during fr_build_operators).
+ *  equations FR_EULER | FR_NAVIER_STOKES; precision FR_FP64 | FR_FP32 (state, operators
+ *  and fluxes; probe / force accumulators are FP64 in both).
+ *  gamma (1.4), prandtl (0.71), ldg_beta (0.5), ldg_tau (penalty, 0.1).
+ *  Per mesh m: rho_inf[m], vel_inf[m*dim + j], p_inf[m], mu[m] (constant viscosity).
+ *  Probes: probe_xyz[n_probe][dim] located (lowest-index element containing it) in mesh
+ *  probe_mesh[n_probe] (NULL -> mesh 0); FR_ERR_MESH if outside.  max_samples = capacity
+ *  of the per-probe FP64 pressure series kept on the device.
+ *  forces != 0 accumulates the wall force per mesh at each sample (NS only).
+ */
+typedef struct {
+  int32_t equations, precision;
+  double  gamma, prandtl, ldg_beta, ldg_tau;
+  const double *rho_inf, *vel_inf, *p_inf, *mu;
+  int32_t n_probe, max_samples;
+  const double  *probe_xyz;
+  const int32_t *probe_mesh;
+  int32_t forces;
+  int32_t reserved0;
+} fr_params;
+
+/* Build operators (Gauss-Legendre points, Lagrange derivative, interpolation and
+ * g_DG correction-derivative tables), curved-element metrics at solution and flux
+ * points, face connectivity (conforming, periodic, wall, far field), probe tables, and
+ * allocate the device work arrays.  *out receives the handle (NULL on failure). */
+fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *params, fr_solver **out);
+
+/* shape[0..2] = {n_elem, nv, Ns} of a state array. */
+fr_status fr_state_shape(const fr_solver *s, int64_t shape[3]);
+
+/* Physical coordinates of the solution points, host out xyz[n_elem][Ns][dim] (FP64). */
+fr_status fr_solpt_coords(const fr_solver *s, double *xyz);
+
+/* r = R(u) = -(1/J)[div F~ + correction], the FR residual (du/dt).  u, r: device state
+ * arrays (may not alias). */
+fr_status fr_rhs(fr_solver *s, const void *u, void *r, void *stream);
+
+/* Advance u (device state, in place) by n_steps classical RK4 steps with dt[m] (device,
+ * FP64, per mesh).  When sample_every > 0, before every step whose index since the last
+ * fr_reset_accumulators is a multiple of sample_every, the probe pressures (and wall forces
+ * when enabled) of the current state are accumulated in FP64.  The step sequence is
+ * replayed from a captured HIP graph. */
+fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, int32_t sample_every,
+                     void *stream);
+
+/* Synchronise, then per probe (host out arrays, nullable): prms[a] = RMS of the sampled
+ * pressure about its mean (Eqs. (10)-(12): last element of the cumulative vector),
+ * oaspl[a] = 20 log10(prms / p_ref) (Eq. (9); -inf when prms = 0), mean_force[m*dim + j] =
+ * time-mean wall force of mesh m, n_samples = samples taken.  FR_ERR_NONFINITE if a
+ * sampled pressure is not finite. */
+fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl, double *mean_force,
+                         int64_t *n_samples, void *stream);
+
+/* Synchronise and copy the FP64 pressure series series[a*cap + k] (k < min(n, cap)). */
+fr_status fr_probe_series(fr_solver *s, double *series, int64_t cap, int64_t *n, void *stream);
+
+/* Zero the sample counter, probe sums / series and force sums (kernel fill, graph safe). */
+fr_status fr_reset_accumulators(fr_solver *s, void *stream);
+
+/* Vector-Jacobian product of fr_rhs: u_bar += (dR/du)^T r_bar (device state arrays, same
+ * dtype as the state).  x_bar: device FP64 [n_node][dim] accumulating the sensitivity to
+ * the mesh node coordinates, or NULL.  Returns FR_ERR_UNSUPPORTED for forms not built. */
+fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream);
+
+/* Release everything the handle owns (NULL is a no-op). */
+void fr_destroy(fr_solver *s);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *fr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRMI_FR_H */

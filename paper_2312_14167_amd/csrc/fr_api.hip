@@ -1,0 +1,411 @@
+// C ABI of libfrmi: argument validation, device allocation / upload, RK4 step sequencing with
+// HIP graph replay, and the host-side OASPL arithmetic of Eqs. (9)-(12).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_solver.hpp"
+
+namespace frmi {
+struct Dispatch {
+  void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
+  void (*step)(const fr_solver *, void *, const double *, bool, hipStream_t);
+};
+bool get_dispatch(int dim, int p, int precision, Dispatch &out);
+void launch_fill(double *p, int64_t n, double v, hipStream_t st);
+void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st);
+}  // namespace frmi
+
+using namespace frmi;
+
+namespace {
+thread_local std::string g_err;
+
+fr_status fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw FrError(e_ == hipErrorOutOfMemory ? FR_ERR_OOM : FR_ERR_HIP,                     \
+                    std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+void *dalloc(fr_solver *s, size_t bytes) {
+  void *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw FrError(FR_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  s->owned.push_back(p);
+  return p;
+}
+
+template <typename T>
+void *upload(fr_solver *s, const std::vector<T> &h) {
+  void *d = dalloc(s, h.size() * sizeof(T));
+  if (!h.empty()) HIP_OK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+// upload FP64 host data in the state precision
+void *upload_real(fr_solver *s, const std::vector<double> &h) {
+  if (s->precision == FR_FP64) return upload(s, h);
+  std::vector<float> f(h.begin(), h.end());
+  return upload(s, f);
+}
+
+template <typename T>
+void *upload_flow(fr_solver *s) {
+  std::vector<FlowDev<T>> f(s->n_mesh);
+  for (int m = 0; m < s->n_mesh; ++m) {
+    f[m].rho = (T)s->h_rho[m];
+    for (int j = 0; j < 3; ++j) f[m].v[j] = j < s->dim ? (T)s->h_vel[m * s->dim + j] : T(0);
+    f[m].p = (T)s->h_p[m];
+    f[m].mu = (T)s->h_mu[m];
+  }
+  return upload(s, f);
+}
+
+void free_graphs(fr_solver *s) {
+  for (int k = 0; k < 2; ++k) {
+    if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
+    s->graph[k] = nullptr;
+    s->graph_u[k] = nullptr;
+    s->graph_dt[k] = nullptr;
+  }
+}
+
+void destroy(fr_solver *s) {
+  if (!s) return;
+  free_graphs(s);
+  for (void *p : s->owned) (void)hipFree(p);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  delete s;
+}
+
+Dispatch dispatch_of(const fr_solver *s) {
+  Dispatch d{};
+  if (!get_dispatch(s->dim, s->p, s->precision, d)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+  return d;
+}
+}  // namespace
+
+extern "C" {
+
+const char *fr_last_error(void) { return g_err.c_str(); }
+
+fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_solver **out) {
+  if (!out) return fail(FR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!mesh || !prm) return fail(FR_ERR_ARG, "mesh or params is NULL");
+  if (mesh->dim != 2 && mesh->dim != 3) return fail(FR_ERR_ARG, "dim must be 2 or 3");
+  if (mesh->p < 1 || mesh->p > 4) return fail(FR_ERR_UNSUPPORTED, "p must be in 1..4");
+  if (mesh->geom_q < 1 || mesh->geom_q > 4) return fail(FR_ERR_UNSUPPORTED, "geom_q must be in 1..4");
+  if (mesh->n_elem <= 0 || mesh->n_node <= 0 || !mesh->node_xyz || !mesh->elem_nodes || !mesh->face_bc)
+    return fail(FR_ERR_ARG, "empty mesh or NULL mesh array");
+  if (mesh->n_periodic < 0 || (mesh->n_periodic > 0 && !mesh->periodic_vec))
+    return fail(FR_ERR_ARG, "bad periodic vectors");
+  const int n_mesh = mesh->n_mesh <= 0 ? 1 : mesh->n_mesh;
+  if (mesh->n_mesh > 1 && !mesh->mesh_elem_begin) return fail(FR_ERR_ARG, "mesh_elem_begin is NULL");
+  if (prm->equations != FR_EULER && prm->equations != FR_NAVIER_STOKES) return fail(FR_ERR_ARG, "bad equations");
+  if (prm->precision != FR_FP64 && prm->precision != FR_FP32) return fail(FR_ERR_ARG, "bad precision");
+  if (!prm->rho_inf || !prm->vel_inf || !prm->p_inf || !prm->mu) return fail(FR_ERR_ARG, "NULL free-stream array");
+  if (!(prm->gamma > 1.0) || !(prm->prandtl > 0.0)) return fail(FR_ERR_ARG, "bad gamma / prandtl");
+  if (prm->n_probe < 0 || (prm->n_probe > 0 && (!prm->probe_xyz || prm->max_samples <= 0)))
+    return fail(FR_ERR_ARG, "bad probe arguments");
+  fr_solver *s = new (std::nothrow) fr_solver();
+  if (!s) return fail(FR_ERR_OOM, "host allocation failed");
+  try {
+    s->dim = mesh->dim;
+    s->p = mesh->p;
+    s->P = mesh->p + 1;
+    s->NV = mesh->dim + 2;
+    s->Ns = mesh->dim == 2 ? s->P * s->P : s->P * s->P * s->P;
+    s->Nfp = mesh->dim == 2 ? s->P : s->P * s->P;
+    s->Nf = 2 * mesh->dim * s->Nfp;
+    s->Ne = mesh->n_elem;
+    s->n_mesh = n_mesh;
+    s->equations = prm->equations;
+    s->precision = prm->precision;
+    s->tsize = prm->precision == FR_FP64 ? 8 : 4;
+    s->gamma = prm->gamma;
+    s->prandtl = prm->prandtl;
+    s->beta = prm->ldg_beta;
+    s->tau = prm->ldg_tau;
+    Dispatch dsp;
+    if (!get_dispatch(s->dim, s->p, s->precision, dsp)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+    MeshIn m;
+    m.dim = mesh->dim;
+    m.p = mesh->p;
+    m.q = mesh->geom_q;
+    m.n_elem = mesh->n_elem;
+    m.n_node = mesh->n_node;
+    m.node_xyz = mesh->node_xyz;
+    m.elem_nodes = mesh->elem_nodes;
+    m.face_bc = mesh->face_bc;
+    m.n_periodic = mesh->n_periodic;
+    m.periodic_vec = mesh->periodic_vec;
+    m.n_mesh = n_mesh;
+    if (mesh->n_mesh > 1 || mesh->mesh_elem_begin) {
+      m.mesh_begin.assign(mesh->mesh_elem_begin, mesh->mesh_elem_begin + n_mesh + 1);
+      if (m.mesh_begin[0] != 0 || m.mesh_begin[n_mesh] != mesh->n_elem) throw FrError(FR_ERR_ARG, "bad mesh ranges");
+      for (int k = 0; k < n_mesh; ++k)
+        if (m.mesh_begin[k + 1] <= m.mesh_begin[k]) throw FrError(FR_ERR_ARG, "empty or unordered mesh range");
+    } else {
+      m.mesh_begin = {0, mesh->n_elem};
+    }
+    s->mesh_begin = m.mesh_begin;
+    for (int k = 0; k < n_mesh; ++k) {
+      if (!(prm->rho_inf[k] > 0.0) || !(prm->p_inf[k] > 0.0) || prm->mu[k] < 0.0)
+        throw FrError(FR_ERR_ARG, "bad free stream");
+      s->h_rho.push_back(prm->rho_inf[k]);
+      s->h_p.push_back(prm->p_inf[k]);
+      s->h_mu.push_back(prm->mu[k]);
+      for (int j = 0; j < s->dim; ++j) s->h_vel.push_back(prm->vel_inf[k * s->dim + j]);
+    }
+    s->ops = build_ops_1d(s->p);
+    Geometry g = build_geometry(m, s->ops);
+    Connectivity c = build_connectivity(m, s->ops, g);
+    // probes (located before any device allocation)
+    s->n_probe = prm->n_probe;
+    s->cap = prm->n_probe > 0 ? prm->max_samples : 1;
+    s->forces = (prm->forces && s->equations == FR_NAVIER_STOKES) ? 1 : 0;
+    std::vector<int64_t> pe;
+    std::vector<double> pw, pinf;
+    for (int a = 0; a < prm->n_probe; ++a) {
+      int pm = prm->probe_mesh ? prm->probe_mesh[a] : 0;
+      if (pm < 0 || pm >= n_mesh) throw FrError(FR_ERR_ARG, "probe mesh out of range");
+      Probe pr = locate_probe(m, s->ops, prm->probe_xyz + (size_t)a * s->dim, pm);
+      pe.push_back(pr.elem);
+      pw.insert(pw.end(), pr.weights.begin(), pr.weights.end());
+      pinf.push_back(prm->p_inf[pm]);
+    }
+    s->xsol = std::move(g.xsol);
+    s->metric = upload_real(s, g.metric);
+    g.metric.clear();
+    g.metric.shrink_to_fit();
+    s->npair = (int64_t)c.pairL.size();
+    s->nbnd = (int64_t)c.bnd.size();
+    s->n_wall = c.n_wall;
+    s->pairL = (int32_t *)upload(s, c.pairL);
+    s->pairR = (int32_t *)upload(s, c.pairR);
+    s->bnd = (int32_t *)upload(s, c.bnd);
+    s->pair_nrm = upload_real(s, c.pair_nrm);
+    s->bnd_nrm = upload_real(s, c.bnd_nrm);
+    s->bnd_w = (double *)upload(s, c.bnd_w);
+    s->elem_mesh = (int32_t *)upload(s, c.elem_mesh);
+    s->h_wall_mesh_begin = c.wall_mesh_begin;
+    s->wall_mesh_begin = (int64_t *)upload(s, c.wall_mesh_begin);
+    s->flow = s->precision == FR_FP64 ? upload_flow<double>(s) : upload_flow<float>(s);
+    const size_t T = s->tsize;
+    const size_t nsol = (size_t)s->Ne * s->NV * s->Ns, nf = (size_t)s->Ne * s->NV * s->Nf;
+    s->uf = dalloc(s, nf * T);
+    s->fhat = dalloc(s, nf * T);
+    s->acc = dalloc(s, nsol * T);
+    s->ustage = dalloc(s, nsol * T);
+    if (s->equations == FR_NAVIER_STOKES) {
+      s->du = dalloc(s, nf * T);
+      s->gradf = dalloc(s, nf * s->dim * T);
+      s->vol = dalloc(s, nsol * T);
+    }
+    s->h_probe_pinf = pinf;
+    s->probe_elem = (int64_t *)upload(s, pe);
+    s->probe_w = (double *)upload(s, pw);
+    s->probe_pinf = (double *)upload(s, pinf);
+    s->series = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * s->cap * sizeof(double));
+    s->sums = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * 2 * sizeof(double));
+    s->force_acc = (double *)dalloc(s, (size_t)n_mesh * s->dim * sizeof(double));
+    s->count = (unsigned long long *)dalloc(s, sizeof(unsigned long long));
+    s->nonfinite = (int *)dalloc(s, sizeof(int));
+    HIP_OK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    const char *ng = std::getenv("FRMI_NO_GRAPH");
+    s->use_graphs = (ng && ng[0] == '1') ? 0 : 1;
+    fr_status st = fr_reset_accumulators(s, nullptr);
+    if (st != FR_OK) throw FrError(st, g_err);
+    HIP_OK(hipDeviceSynchronize());
+  } catch (const FrError &e) {
+    destroy(s);
+    return fail(e.code, e.what());
+  } catch (const std::exception &e) {
+    destroy(s);
+    return fail(FR_ERR_OOM, e.what());
+  }
+  *out = s;
+  g_err.clear();
+  return FR_OK;
+}
+
+fr_status fr_state_shape(const fr_solver *s, int64_t shape[3]) {
+  if (!s || !shape) return fail(FR_ERR_ARG, "NULL argument");
+  shape[0] = s->Ne;
+  shape[1] = s->NV;
+  shape[2] = s->Ns;
+  return FR_OK;
+}
+
+fr_status fr_solpt_coords(const fr_solver *s, double *xyz) {
+  if (!s || !xyz) return fail(FR_ERR_ARG, "NULL argument");
+  std::memcpy(xyz, s->xsol.data(), s->xsol.size() * sizeof(double));
+  return FR_OK;
+}
+
+fr_status fr_rhs(fr_solver *s, const void *u, void *r, void *stream) {
+  if (!s || !u || !r) return fail(FR_ERR_ARG, "NULL argument");
+  if (u == r) return fail(FR_ERR_ARG, "u and r must not alias");
+  try {
+    Dispatch d = dispatch_of(s);
+    d.rhs(s, u, r, (hipStream_t)stream);
+    HIP_OK(hipGetLastError());
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, int32_t sample_every, void *stream) {
+  if (!s || !u || !dt) return fail(FR_ERR_ARG, "NULL argument");
+  if (n_steps < 0 || sample_every < 0) return fail(FR_ERR_ARG, "negative step count / sampling interval");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Dispatch d = dispatch_of(s);
+    for (int32_t n = 0; n < n_steps; ++n) {
+      const bool sample = sample_every > 0 && (s->steps_since_reset % sample_every) == 0;
+      const int gi = sample ? 1 : 0;
+      if (s->use_graphs) {
+        if (!s->graph[gi] || s->graph_u[gi] != u || s->graph_dt[gi] != dt) {
+          if (s->graph[gi]) (void)hipGraphExecDestroy(s->graph[gi]);
+          s->graph[gi] = nullptr;
+          hipGraph_t g = nullptr;
+          HIP_OK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+          d.step(s, u, dt, sample, s->cap_stream);
+          hipError_t le = hipGetLastError();
+          hipError_t ce = hipStreamEndCapture(s->cap_stream, &g);
+          if (le != hipSuccess) throw FrError(FR_ERR_HIP, std::string("launch during capture: ") + hipGetErrorString(le));
+          HIP_OK(ce);
+          hipGraphExec_t ex = nullptr;
+          hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          HIP_OK(ie);
+          s->graph[gi] = ex;
+          s->graph_u[gi] = u;
+          s->graph_dt[gi] = dt;
+        }
+        HIP_OK(hipGraphLaunch(s->graph[gi], st));
+      } else {
+        d.step(s, u, dt, sample, st);
+        HIP_OK(hipGetLastError());
+      }
+      s->steps_since_reset++;
+    }
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_reset_accumulators(fr_solver *s, void *stream) {
+  if (!s) return fail(FR_ERR_ARG, "NULL solver");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    launch_fill(s->series, (int64_t)std::max(1, s->n_probe) * s->cap, 0.0, st);
+    launch_fill(s->sums, (int64_t)std::max(1, s->n_probe) * 2, 0.0, st);
+    launch_fill(s->force_acc, (int64_t)s->n_mesh * s->dim, 0.0, st);
+    launch_reset_counters(s->count, s->nonfinite, st);
+    HIP_OK(hipGetLastError());
+    s->steps_since_reset = 0;
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_probe_series(fr_solver *s, double *series, int64_t cap, int64_t *n, void *stream) {
+  if (!s || !n) return fail(FR_ERR_ARG, "NULL argument");
+  if (cap < 0 || (cap > 0 && !series)) return fail(FR_ERR_ARG, "bad series buffer");
+  try {
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    unsigned long long cnt = 0;
+    HIP_OK(hipMemcpy(&cnt, s->count, sizeof(cnt), hipMemcpyDeviceToHost));
+    *n = (int64_t)cnt;
+    const int64_t k = std::min<int64_t>({(int64_t)cnt, (int64_t)s->cap, cap});
+    std::vector<double> h((size_t)std::max(1, s->n_probe) * s->cap);
+    if (s->n_probe > 0 && k > 0) {
+      HIP_OK(hipMemcpy(h.data(), s->series, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int a = 0; a < s->n_probe; ++a)
+        for (int64_t j = 0; j < k; ++j) series[a * cap + j] = h[(size_t)a * s->cap + j];
+    }
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl, double *mean_force,
+                         int64_t *n_samples, void *stream) {
+  if (!s) return fail(FR_ERR_ARG, "NULL solver");
+  if (oaspl && !(p_ref > 0.0)) return fail(FR_ERR_ARG, "p_ref must be positive");
+  try {
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    unsigned long long cnt = 0;
+    int nf = 0;
+    HIP_OK(hipMemcpy(&cnt, s->count, sizeof(cnt), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&nf, s->nonfinite, sizeof(int), hipMemcpyDeviceToHost));
+    if (n_samples) *n_samples = (int64_t)cnt;
+    const int np = std::max(1, s->n_probe);
+    std::vector<double> sums((size_t)np * 2), ser((size_t)np * s->cap), frc((size_t)s->n_mesh * s->dim);
+    HIP_OK(hipMemcpy(sums.data(), s->sums, sums.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(frc.data(), s->force_acc, frc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const bool whole = cnt > 0 && cnt <= (unsigned long long)s->cap;
+    if (whole && s->n_probe > 0)
+      HIP_OK(hipMemcpy(ser.data(), s->series, ser.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int a = 0; a < s->n_probe; ++a) {
+      double r = 0.0;
+      if (cnt > 0) {
+        if (whole) {  // two-pass over the stored FP64 series: population RMS about the mean
+          double m1 = 0.0;
+          for (unsigned long long k = 0; k < cnt; ++k) m1 += ser[(size_t)a * s->cap + k];
+          m1 /= (double)cnt;
+          double m2 = 0.0;
+          for (unsigned long long k = 0; k < cnt; ++k) {
+            const double dp = ser[(size_t)a * s->cap + k] - m1;
+            m2 += dp * dp;
+          }
+          r = std::sqrt(m2 / (double)cnt);
+        } else {  // from the FP64 sums of (p - p_inf)
+          const double m1 = sums[2 * a] / (double)cnt, m2 = sums[2 * a + 1] / (double)cnt;
+          r = std::sqrt(std::max(0.0, m2 - m1 * m1));
+        }
+      }
+      if (prms) prms[a] = r;
+      if (oaspl) oaspl[a] = r > 0.0 ? 20.0 * std::log10(r / p_ref) : -INFINITY;
+    }
+    if (mean_force)
+      for (size_t k = 0; k < frc.size(); ++k) mean_force[k] = cnt > 0 ? frc[k] / (double)cnt : 0.0;
+    if (nf) return fail(FR_ERR_NONFINITE, "a sampled probe pressure is not finite");
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream) {
+  (void)stream;
+  (void)x_bar;
+  if (!s || !u || !r_bar || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
+  return fail(FR_ERR_UNSUPPORTED, "the vector-Jacobian product is not built for this form");
+}
+
+void fr_destroy(fr_solver *s) { destroy(s); }
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Host-side construction of the FR operators, curved-element metrics, face connectivity and
+// probe tables.  Plain C++17 (no HIP types); results are uploaded by the API layer.
+#pragma once
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace frmi {
+
+// Thrown by host construction; mapped to an fr_status at the ABI.
+struct FrError : std::runtime_error {
+  int code;
+  FrError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+// 1-D operators on P = p+1 Gauss-Legendre points (all FP64).
+struct Ops1D {
+  int P = 0;
+  std::vector<double> xi, w;   // nodes, weights
+  std::vector<double> D;       // D[a*P + b] = l_b'(xi_a)
+  std::vector<double> lm, lp;  // l_b(-1), l_b(+1)
+  std::vector<double> gp, gm;  // g_R'(xi_a), g_R'(-xi_a) for the g_DG correction function
+};
+
+Ops1D build_ops_1d(int p);
+
+// Gauss-Lobatto-Legendre nodes of degree q (q+1 points, q in 1..4).
+std::vector<double> gll_nodes(int q);
+
+struct MeshIn {
+  int dim = 0, p = 0, q = 0;
+  int64_t n_elem = 0, n_node = 0;
+  const double *node_xyz = nullptr;
+  const int64_t *elem_nodes = nullptr;
+  const int32_t *face_bc = nullptr;
+  int n_periodic = 0;
+  const double *periodic_vec = nullptr;
+  int n_mesh = 1;
+  std::vector<int64_t> mesh_begin;  // n_mesh + 1
+};
+
+struct Geometry {
+  int dim = 0, P = 0, Ns = 0, Nfp = 0, Nf = 0;
+  int64_t n_elem = 0;
+  std::vector<double> metric;  // [Ne][dim*dim + 1][Ns]: S[k][j] (k*dim + j), then 1/J
+  std::vector<double> J;       // [Ne][Ns]
+  std::vector<double> xsol;    // [Ne][Ns][dim]
+  std::vector<double> xf;      // [Ne][Nf][dim]
+  std::vector<double> Nvec;    // [Ne][Nf][dim] scaled outward normal s_f S[k_f, :]
+};
+
+Geometry build_geometry(const MeshIn &m, const Ops1D &ops);
+
+struct Connectivity {
+  // interior / periodic flux-point pairs, sorted by the L code; code = e * Nf + fpt
+  std::vector<int32_t> pairL, pairR;
+  std::vector<double> pair_nrm;   // [npair][dim + 1]: unit normal of the L side, |N|
+  // boundary flux points: walls first [0, n_wall), then far field
+  std::vector<int32_t> bnd;
+  std::vector<double> bnd_nrm;    // [nbnd][dim + 1]
+  std::vector<double> bnd_w;      // face quadrature weight of the flux point (walls: force integral)
+  int64_t n_wall = 0;
+  std::vector<int64_t> wall_mesh_begin;  // [n_mesh + 1] ranges into the wall list
+  std::vector<int32_t> elem_mesh;        // [Ne]
+};
+
+Connectivity build_connectivity(const MeshIn &m, const Ops1D &ops, const Geometry &g);
+
+struct Probe {
+  int64_t elem = -1;
+  int mesh = 0;
+  std::vector<double> xi;       // reference coordinates
+  std::vector<double> weights;  // [Ns] tensor Lagrange weights
+};
+
+Probe locate_probe(const MeshIn &m, const Ops1D &ops, const double *xp, int mesh);
+
+}  // namespace frmi

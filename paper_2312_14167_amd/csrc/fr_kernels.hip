@@ -1,0 +1,890 @@
+// HIP kernels for CDNA4 (gfx950): FR residual stages, RK4 update, probe and force accumulators.
+//
+// Data layout (element-major, per-element blocks are contiguous so a workgroup's tile of
+// elements is one contiguous range of HBM):
+//   state / residual      [Ne][NV][Ns]
+//   flux-point arrays     [Ne][NV][Nf]          (u_f, u^ - u_f, common flux)
+//   flux-point gradients  [Ne][dim][NV][Nf]
+//   metrics               [Ne][dim*dim + 1][Ns] (S = adj(dx/dxi) row-major, then 1/J)
+// Element operators are applied in sum-factorised (tensor-product) form along the P points of
+// each reference line: every operator is a P x P contraction per line, so the whole stage is
+// bound by HBM traffic, not by arithmetic.  Volume kernels stage their element tile in LDS
+// once and read all line operands from LDS.
+//
+// Stage pipeline (Navier-Stokes), one launch each:
+//   interp      u_f = M0 u                                  (only before the first stage of a call;
+//                                                            later stages get u_f from div_rk)
+//   common_sol  u^ - u_f on both sides of every flux point (LDG u^ = (1/2+b) u_L + (1/2-b) u_R,
+//               boundary states for walls / far field)
+//   ns_grad     corrected gradient grad_xi u = D_k u + s_f g_R'(s_f xi) (u^ - u_f); grad_x u =
+//               J^-1 S^T grad_xi u; grad u_f = M0 grad_x u; F = F_inv - F_vis; F~_k = S_k . F;
+//               vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f})
+//   face_flux   common normal flux (Rusanov - LDG viscous + penalty) x |N|, + on L, - on R
+//   div_rk      R = -(1/J) (vol + Lift F^_n); RK4 stage update; u_f of the new stage state
+// Euler drops common_sol / ns_grad and computes F~ and vol inside div_rk (euler_vol_rk).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fr_solver.hpp"
+
+namespace frmi {
+
+template <int D_, int P_>
+struct Shape {
+  static constexpr int D = D_, P = P_;
+  static constexpr int Ns = (D == 2) ? P * P : P * P * P;
+  static constexpr int Nfp = (D == 2) ? P : P * P;
+  static constexpr int Nf = 2 * D * Nfp;
+  static constexpr int NV = D + 2;
+  static constexpr int NM = D * D + 1;
+};
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int round64(int x) { return (x + 63) / 64 * 64; }
+
+// elements per workgroup for an LDS footprint of `vals` values of `bytes` each
+template <int Ns>
+constexpr int tile_elems(int vals, int bytes) {
+  return cmax(1, cmin(512 / Ns, (60 * 1024) / (vals * bytes)));
+}
+
+// line through solution point i along reference coordinate k: first point and stride
+template <int D, int P>
+__device__ __forceinline__ void line_of_sol(int i, int k, int &base, int &stride, int &ik, int &t) {
+  const int i0 = i % P, i1 = (i / P) % P, i2 = i / (P * P);
+  if (k == 0) { stride = 1; ik = i0; t = (D == 2) ? i1 : i1 + P * i2; }
+  else if (k == 1) { stride = P; ik = i1; t = (D == 2) ? i0 : i0 + P * i2; }
+  else { stride = P * P; ik = i2; t = i0 + P * i1; }
+  base = i - ik * stride;
+}
+
+// line of flux point fp (face f = fp / Nfp): first solution point, stride, side (0: -1, 1: +1)
+template <int D, int P>
+__device__ __forceinline__ void line_of_fpt(int fp, int &base, int &stride, int &side) {
+  constexpr int Nfp = (D == 2) ? P : P * P;
+  const int f = fp / Nfp, t = fp % Nfp, k = f >> 1;
+  side = f & 1;
+  if (D == 2) {
+    if (k == 0) { base = P * t; stride = 1; }
+    else { base = t; stride = P; }
+  } else {
+    if (k == 0) { base = P * t; stride = 1; }
+    else if (k == 1) { base = (t % P) + P * P * (t / P); stride = P; }
+    else { base = t; stride = P * P; }
+  }
+}
+
+// ------------------------------------------------------------------------------------ physics
+template <int D, typename T>
+__device__ __forceinline__ void primitives(const T *u, T gm1, T &rho, T *v, T &p) {
+  rho = u[0];
+  const T ir = T(1) / rho;
+  T ke = T(0);
+  for (int j = 0; j < D; ++j) { v[j] = u[1 + j] * ir; ke += v[j] * u[1 + j]; }
+  p = gm1 * (u[D + 1] - T(0.5) * ke);
+}
+
+// inviscid flux (Eq. (3)) dotted with a vector m (unit normal, or a metric row S_k)
+template <int D, typename T>
+__device__ __forceinline__ void finv_dot(const T *u, const T *m, T gm1, T *out) {
+  T rho, v[D], p;
+  primitives<D>(u, gm1, rho, v, p);
+  T vm = T(0);
+  for (int j = 0; j < D; ++j) vm += v[j] * m[j];
+  out[0] = u[0] * vm;
+  for (int i = 0; i < D; ++i) out[1 + i] = u[1 + i] * vm + p * m[i];
+  out[D + 1] = (u[D + 1] + p) * vm;
+}
+
+// viscous quantities at a point from the state u and conserved gradient g[j*NV + v]
+template <int D, typename T>
+struct Visc {
+  T v[D];
+  T tau[D][D];
+  T q[D];
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void visc_state(const T *u, const T *g, T mu, const PhysDev<T> &ph, bool heat,
+                                           Visc<D, T> &o) {
+  constexpr int NV = D + 2;
+  const T ir = T(1) / u[0];
+  const T Es = u[D + 1] * ir;
+  T dv[D][D], dth[D];
+  for (int i = 0; i < D; ++i) o.v[i] = u[1 + i] * ir;
+  for (int j = 0; j < D; ++j) {
+    const T gr = g[j * NV + 0];
+    T s = T(0);
+    for (int i = 0; i < D; ++i) {
+      dv[i][j] = (g[j * NV + 1 + i] - o.v[i] * gr) * ir;
+      s += o.v[i] * dv[i][j];
+    }
+    const T de = (g[j * NV + D + 1] - Es * gr) * ir;
+    dth[j] = ph.gm1 * (de - s);
+  }
+  T div = T(0);
+  for (int i = 0; i < D; ++i) div += dv[i][i];
+  const T c23 = T(2) / T(3);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j)
+      o.tau[i][j] = mu * (dv[i][j] + dv[j][i] - (i == j ? c23 * div : T(0)));
+  const T kappa = heat ? mu * ph.gamma / (ph.prandtl * ph.gm1) : T(0);
+  for (int j = 0; j < D; ++j) o.q[j] = -kappa * dth[j];
+}
+
+// viscous flux (0, tau_ij, u_i tau_ij - q_j) dotted with m
+template <int D, typename T>
+__device__ __forceinline__ void fvis_dot(const Visc<D, T> &o, const T *m, T *out) {
+  out[0] = T(0);
+  T en = T(0);
+  for (int i = 0; i < D; ++i) {
+    T s = T(0);
+    for (int j = 0; j < D; ++j) s += o.tau[i][j] * m[j];
+    out[1 + i] = s;
+    en += o.v[i] * s;
+  }
+  for (int j = 0; j < D; ++j) en -= o.q[j] * m[j];
+  out[D + 1] = en;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void rusanov(const T *uL, const T *uR, const T *n, T gamma, T gm1, T *F) {
+  constexpr int NV = D + 2;
+  T fL[NV], fR[NV];
+  finv_dot<D>(uL, n, gm1, fL);
+  finv_dot<D>(uR, n, gm1, fR);
+  T rL, vL[D], pL, rR, vR[D], pR;
+  primitives<D>(uL, gm1, rL, vL, pL);
+  primitives<D>(uR, gm1, rR, vR, pR);
+  T vnL = T(0), vnR = T(0);
+  for (int j = 0; j < D; ++j) { vnL += vL[j] * n[j]; vnR += vR[j] * n[j]; }
+  const T aL = fabs(vnL) + sqrt(gamma * pL / rL);
+  const T aR = fabs(vnR) + sqrt(gamma * pR / rR);
+  const T lam = aL >= aR ? aL : aR;
+  for (int v = 0; v < NV; ++v) F[v] = T(0.5) * (fL[v] + fR[v]) - T(0.5) * lam * (uR[v] - uL[v]);
+}
+
+// Riemann-invariant far-field state
+template <int D, typename T>
+__device__ __forceinline__ void farfield(const T *uL, const T *n, const FlowDev<T> &fl, T gamma, T gm1, T *ub) {
+  T rL, vL[D], pL;
+  primitives<D>(uL, gm1, rL, vL, pL);
+  const T cL = sqrt(gamma * pL / rL);
+  const T ci = sqrt(gamma * fl.p / fl.rho);
+  T vnL = T(0), vni = T(0);
+  for (int j = 0; j < D; ++j) { vnL += vL[j] * n[j]; vni += fl.v[j] * n[j]; }
+  const T Rp = vnL + T(2) * cL / gm1;
+  const T Rm = vni - T(2) * ci / gm1;
+  const T vn = T(0.5) * (Rp + Rm);
+  const T c = T(0.25) * gm1 * (Rp - Rm);
+  const bool out = vn > T(0);
+  const T s = out ? pL / pow(rL, gamma) : fl.p / pow(fl.rho, gamma);
+  const T rho = pow(c * c / (gamma * s), T(1) / gm1);
+  const T p = rho * c * c / gamma;
+  T ke = T(0);
+  ub[0] = rho;
+  for (int j = 0; j < D; ++j) {
+    const T vt = out ? vL[j] - vnL * n[j] : fl.v[j] - vni * n[j];
+    const T vj = vt + vn * n[j];
+    ub[1 + j] = rho * vj;
+    ke += vj * vj;
+  }
+  ub[D + 1] = p / gm1 + T(0.5) * rho * ke;
+}
+
+// ------------------------------------------------------------------------------------ kernels
+// u_f = M0 u for every (element, flux point)
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_interp(const T *__restrict__ u, T *__restrict__ uf, OpsDev<T, P> ops,
+                                                int64_t Ne) {
+  using S = Shape<D, P>;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Ne * S::Nf) return;
+  const int64_t e = gid / S::Nf;
+  const int fp = (int)(gid % S::Nf);
+  int base, stride, side;
+  line_of_fpt<D, P>(fp, base, stride, side);
+  const T *lv = side ? ops.lp : ops.lm;
+  for (int v = 0; v < S::NV; ++v) {
+    const T *ue = u + (e * S::NV + v) * S::Ns + base;
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) s += lv[a] * ue[a * stride];
+    uf[(e * S::NV + v) * S::Nf + fp] = s;
+  }
+}
+
+// LDG common solution: writes u^ - u_f on both sides (interior) or for the boundary point
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_common_sol(const T *__restrict__ uf, const int32_t *__restrict__ pairL,
+                                                    const int32_t *__restrict__ pairR, int64_t npair,
+                                                    const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
+                                                    int64_t n_wall, int64_t nbnd, const int32_t *__restrict__ elem_mesh,
+                                                    const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
+                                                    T *__restrict__ du) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Nf = S::Nf;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < npair) {
+    const int32_t cL = pairL[gid], cR = pairR[gid];
+    const int64_t eL = cL / Nf, eR = cR / Nf;
+    const int fL = cL % Nf, fR = cR % Nf;
+    const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
+    for (int v = 0; v < NV; ++v) {
+      const T a = uf[(eL * NV + v) * Nf + fL];
+      const T b = uf[(eR * NV + v) * Nf + fR];
+      const T h = wl * a + wr * b;
+      du[(eL * NV + v) * Nf + fL] = h - a;
+      du[(eR * NV + v) * Nf + fR] = h - b;
+    }
+  } else if (gid < npair + nbnd) {
+    const int64_t b = gid - npair;
+    const int32_t c = bnd[b];
+    const int64_t e = c / Nf;
+    const int fp = c % Nf;
+    T uB[NV], ug[NV];
+    for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
+    if (b < n_wall) {
+      T ke = T(0);
+      for (int j = 0; j < D; ++j) ke += uB[1 + j] * uB[1 + j];
+      ug[0] = uB[0];
+      for (int j = 0; j < D; ++j) ug[1 + j] = T(0);
+      ug[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
+    } else {
+      T n[D];
+      for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+      farfield<D>(uB, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, ug);
+    }
+    for (int v = 0; v < NV; ++v) du[(e * NV + v) * Nf + fp] = ug[v] - uB[v];
+  }
+}
+
+// common normal flux x |N| at every flux point (Rusanov; NS: minus LDG viscous flux + penalty)
+template <int D, int P, typename T, bool NS>
+__global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, const T *__restrict__ gradf,
+                                                   const int32_t *__restrict__ pairL, const int32_t *__restrict__ pairR,
+                                                   const T *__restrict__ pnrm, int64_t npair,
+                                                   const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
+                                                   int64_t n_wall, int64_t nbnd, const int32_t *__restrict__ elem_mesh,
+                                                   const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
+                                                   T *__restrict__ fhat) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Nf = S::Nf;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < npair) {
+    const int32_t cL = pairL[gid], cR = pairR[gid];
+    const int64_t eL = cL / Nf, eR = cR / Nf;
+    const int fL = cL % Nf, fR = cR % Nf;
+    T uL[NV], uR[NV], n[D], F[NV];
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = uf[(eL * NV + v) * Nf + fL];
+      uR[v] = uf[(eR * NV + v) * Nf + fR];
+    }
+    for (int j = 0; j < D; ++j) n[j] = pnrm[gid * (D + 1) + j];
+    const T mag = pnrm[gid * (D + 1) + D];
+    rusanov<D>(uL, uR, n, ph.gamma, ph.gm1, F);
+    if (NS) {
+      T gL[D * NV], gR[D * NV];
+      for (int j = 0; j < D; ++j)
+        for (int v = 0; v < NV; ++v) {
+          gL[j * NV + v] = gradf[((eL * D + j) * NV + v) * Nf + fL];
+          gR[j * NV + v] = gradf[((eR * D + j) * NV + v) * Nf + fR];
+        }
+      const T mu = flow[elem_mesh[eL]].mu;
+      Visc<D, T> vs;
+      T fv[NV];
+      const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
+      visc_state<D>(uL, gL, mu, ph, true, vs);
+      fvis_dot<D>(vs, n, fv);
+      for (int v = 0; v < NV; ++v) F[v] -= wl * fv[v];
+      visc_state<D>(uR, gR, mu, ph, true, vs);
+      fvis_dot<D>(vs, n, fv);
+      for (int v = 0; v < NV; ++v) F[v] -= wr * fv[v] - ph.tau * (uL[v] - uR[v]);
+    }
+    for (int v = 0; v < NV; ++v) {
+      fhat[(eL * NV + v) * Nf + fL] = F[v] * mag;
+      fhat[(eR * NV + v) * Nf + fR] = -F[v] * mag;
+    }
+  } else if (gid < npair + nbnd) {
+    const int64_t b = gid - npair;
+    const int32_t c = bnd[b];
+    const int64_t e = c / Nf;
+    const int fp = c % Nf;
+    T uB[NV], ug[NV], n[D], F[NV];
+    for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
+    for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+    const T mag = bnrm[b * (D + 1) + D];
+    const bool wall = b < n_wall;
+    const FlowDev<T> fl = flow[elem_mesh[e]];
+    if (wall) {
+      ug[0] = uB[0];
+      for (int j = 0; j < D; ++j) ug[1 + j] = -uB[1 + j];
+      ug[D + 1] = uB[D + 1];
+    } else {
+      farfield<D>(uB, n, fl, ph.gamma, ph.gm1, ug);
+    }
+    rusanov<D>(uB, ug, n, ph.gamma, ph.gm1, F);
+    if (NS) {
+      T g[D * NV];
+      for (int j = 0; j < D; ++j)
+        for (int v = 0; v < NV; ++v) g[j * NV + v] = gradf[((e * D + j) * NV + v) * Nf + fp];
+      if (wall) {  // no-slip state: zero velocity, same density and internal energy
+        T ke = T(0);
+        for (int j = 0; j < D; ++j) ke += uB[1 + j] * uB[1 + j];
+        ug[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
+        for (int j = 0; j < D; ++j) ug[1 + j] = T(0);
+      }
+      Visc<D, T> vs;
+      T fv[NV];
+      visc_state<D>(ug, g, fl.mu, ph, !wall, vs);
+      fvis_dot<D>(vs, n, fv);
+      for (int v = 0; v < NV; ++v) F[v] -= fv[v];
+    }
+    for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = F[v] * mag;
+  }
+}
+
+// tile sizes of the LDS-staged volume kernels
+template <int D, int P, typename T>
+struct GradTile {
+  using S = Shape<D, P>;
+  static constexpr int LE = cmax(S::NV * S::Ns + S::NV * S::Nf, D * S::NV * S::Ns);
+  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int BS = round64(E * S::Ns);
+};
+
+template <int D, int P, typename T>
+struct DivTile {
+  using S = Shape<D, P>;
+  static constexpr int LE = S::NV * cmax(S::Nf, S::Ns);
+  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int BS = round64(E * S::Ns);
+};
+
+template <int D, int P, typename T>
+struct EulerTile {
+  using S = Shape<D, P>;
+  static constexpr int LE = D * S::NV * S::Ns + S::NV * S::Nf;
+  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int BS = round64(E * S::Ns);
+};
+
+// NS volume kernel: corrected gradient, gradient at flux points, fluxes and volume divergence
+template <int D, int P, typename T>
+__global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
+    const T *__restrict__ u, const T *__restrict__ du, const T *__restrict__ metric,
+    const int32_t *__restrict__ elem_mesh, const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops, PhysDev<T> ph,
+    T *__restrict__ gradf, T *__restrict__ vol, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = GradTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  __shared__ T lds[E * TL::LE];
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  T *lu = lds;
+  T *ldu = lds + E * NV * Ns;
+  for (int idx = threadIdx.x; idx < ne * NV * Ns; idx += blockDim.x) lu[idx] = u[e0 * NV * Ns + idx];
+  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) ldu[idx] = du[e0 * NV * Nf + idx];
+  __syncthreads();
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  const bool act = el < ne;
+  const int64_t e = e0 + el;
+  T uv[NV], Sm[D][D], gx[D][NV];
+  if (act) {
+    for (int k = 0; k < D; ++k)
+      for (int j = 0; j < D; ++j) Sm[k][j] = metric[(e * NM + k * D + j) * Ns + i];
+    const T invJ = metric[(e * NM + D * D) * Ns + i];
+    for (int v = 0; v < NV; ++v) uv[v] = lu[(el * NV + v) * Ns + i];
+    T gr[D][NV];
+    for (int k = 0; k < D; ++k) {
+      int base, stride, ik, t;
+      line_of_sol<D, P>(i, k, base, stride, ik, t);
+      const T cm = -ops.gm[ik], cp = ops.gp[ik];
+      for (int v = 0; v < NV; ++v) {
+        const T *lin = lu + (el * NV + v) * Ns + base;
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) s += ops.D[ik * P + a] * lin[a * stride];
+        const T *ld = ldu + (el * NV + v) * Nf;
+        s += cm * ld[(2 * k) * Nfp + t] + cp * ld[(2 * k + 1) * Nfp + t];
+        gr[k][v] = s;
+      }
+    }
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) {
+        T s = T(0);
+        for (int k = 0; k < D; ++k) s += Sm[k][j] * gr[k][v];
+        gx[j][v] = invJ * s;
+      }
+  }
+  __syncthreads();
+  T *lg = lds;  // [E][D][NV][Ns]
+  if (act)
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) lg[((el * D + j) * NV + v) * Ns + i] = gx[j][v];
+  __syncthreads();
+  // gradient at flux points for the whole tile (contiguous output range)
+  for (int idx = threadIdx.x; idx < ne * D * NV * Nf; idx += blockDim.x) {
+    const int fp = idx % Nf, rest = idx / Nf;
+    int base, stride, side;
+    line_of_fpt<D, P>(fp, base, stride, side);
+    const T *lv = side ? ops.lp : ops.lm;
+    const T *lin = lg + rest * Ns + base;
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+    gradf[e0 * D * NV * Nf + idx] = s;
+  }
+  // transformed flux F~_k = S_k . (F_inv - F_vis) at this solution point
+  T ft[D][NV];
+  if (act) {
+    Visc<D, T> vs;
+    T gflat[D * NV];
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) gflat[j * NV + v] = gx[j][v];
+    visc_state<D>(uv, gflat, flow[elem_mesh[e]].mu, ph, true, vs);
+    for (int k = 0; k < D; ++k) {
+      T fi[NV], fv[NV];
+      finv_dot<D>(uv, Sm[k], ph.gm1, fi);
+      fvis_dot<D>(vs, Sm[k], fv);
+      for (int v = 0; v < NV; ++v) ft[k][v] = fi[v] - fv[v];
+    }
+  }
+  __syncthreads();
+  if (act)
+    for (int k = 0; k < D; ++k)
+      for (int v = 0; v < NV; ++v) lg[((el * D + k) * NV + v) * Ns + i] = ft[k][v];
+  __syncthreads();
+  if (act) {
+    for (int v = 0; v < NV; ++v) {
+      T accv = T(0);
+      for (int k = 0; k < D; ++k) {
+        int base, stride, ik, t;
+        line_of_sol<D, P>(i, k, base, stride, ik, t);
+        const T *lin = lg + ((el * D + k) * NV + v) * Ns + base;
+        T ds = T(0), fm = T(0), fpv = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          const T val = lin[a * stride];
+          ds += ops.D[ik * P + a] * val;
+          fm += ops.lm[a] * val;
+          fpv += ops.lp[a] * val;
+        }
+        accv += ds + ops.gm[ik] * fm - ops.gp[ik] * fpv;
+      }
+      vol[(e * NV + v) * Ns + i] = accv;
+    }
+  }
+}
+
+// RK epilogue arguments
+template <typename T>
+struct RKArgs {
+  T *r_out;          // residual output (rhs mode) or nullptr
+  T *u0;             // base state (read; written on the last stage)
+  T *acc;            // RK accumulator
+  T *ustage;         // next stage state (not last)
+  const double *dt;  // per mesh
+  T cA, cB;          // u_next = u0 + cA dt R ; acc += cB dt R
+  int first, last;
+  T *uf_next;        // flux-point values of the new stage state, or nullptr
+};
+
+// shared epilogue: R at (el, i) for all variables -> rhs output or RK update; the new stage
+// state goes to LDS `lw` ([E][NV][Ns]) when uf_next is requested
+template <int D, int P, typename T>
+__device__ __forceinline__ void rk_epilogue(const T *R, int64_t e, int i, const RKArgs<T> &rk,
+                                            const int32_t *__restrict__ elem_mesh, T *w) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns;
+  if (rk.r_out) {
+    for (int v = 0; v < NV; ++v) rk.r_out[(e * NV + v) * Ns + i] = R[v];
+    return;
+  }
+  const T dt = (T)rk.dt[elem_mesh[e]];
+  for (int v = 0; v < NV; ++v) {
+    const int64_t o = (e * NV + v) * Ns + i;
+    const T a = rk.first ? T(0) : rk.acc[o];
+    const T u0 = rk.u0[o];
+    if (!rk.last) {
+      rk.acc[o] = a + rk.cB * dt * R[v];
+      w[v] = u0 + rk.cA * dt * R[v];
+      rk.ustage[o] = w[v];
+    } else {
+      w[v] = u0 + (a + rk.cB * dt * R[v]);
+      rk.u0[o] = w[v];
+    }
+  }
+}
+
+template <int D, int P, typename T>
+__device__ __forceinline__ void tile_interp(const T *lw, int ne, const OpsDev<T, P> &ops, T *uf_tile) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns, Nf = S::Nf;
+  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) {
+    const int fp = idx % Nf, rest = idx / Nf;
+    int base, stride, side;
+    line_of_fpt<D, P>(fp, base, stride, side);
+    const T *lv = side ? ops.lp : ops.lm;
+    const T *lin = lw + rest * Ns + base;
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+    uf_tile[idx] = s;
+  }
+}
+
+// NS: R = -(1/J)(vol + Lift F^), RK update, u_f of the new stage state
+template <int D, int P, typename T>
+__global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_div_rk(const T *__restrict__ vol, const T *__restrict__ fhat,
+                                                                const T *__restrict__ metric,
+                                                                const int32_t *__restrict__ elem_mesh,
+                                                                OpsDev<T, P> ops, RKArgs<T> rk, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = DivTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  __shared__ T lds[E * TL::LE];
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) lds[idx] = fhat[e0 * NV * Nf + idx];
+  __syncthreads();
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  const bool act = el < ne;
+  const int64_t e = e0 + el;
+  T w[NV];
+  if (act) {
+    const T invJ = metric[(e * NM + D * D) * Ns + i];
+    T R[NV];
+    for (int v = 0; v < NV; ++v) R[v] = vol[(e * NV + v) * Ns + i];
+    for (int k = 0; k < D; ++k) {
+      int base, stride, ik, t;
+      line_of_sol<D, P>(i, k, base, stride, ik, t);
+      const T gm = ops.gm[ik], gp = ops.gp[ik];
+      for (int v = 0; v < NV; ++v) {
+        const T *lf = lds + (el * NV + v) * Nf;
+        R[v] += gm * lf[(2 * k) * Nfp + t] + gp * lf[(2 * k + 1) * Nfp + t];
+      }
+    }
+    for (int v = 0; v < NV; ++v) R[v] = -invJ * R[v];
+    rk_epilogue<D, P>(R, e, i, rk, elem_mesh, w);
+  }
+  if (rk.uf_next) {
+    __syncthreads();
+    if (act)
+      for (int v = 0; v < NV; ++v) lds[(el * NV + v) * Ns + i] = w[v];
+    __syncthreads();
+    tile_interp<D, P>(lds, ne, ops, rk.uf_next + e0 * NV * Nf);
+  }
+}
+
+// Euler: F~ at solution points, volume divergence with interior correction, lifting of the
+// common flux, RK update and u_f of the new stage state, in one kernel
+template <int D, int P, typename T>
+__global__ __launch_bounds__((EulerTile<D, P, T>::BS)) void k_euler_vol_rk(
+    const T *u,  // may alias rk.ustage: every thread reads its own point before writing it
+    const T *__restrict__ fhat, const T *__restrict__ metric,
+    const int32_t *__restrict__ elem_mesh, OpsDev<T, P> ops, PhysDev<T> ph, RKArgs<T> rk, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = EulerTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  __shared__ T lds[E * TL::LE];
+  T *lF = lds;                  // [E][D][NV][Ns]
+  T *lf = lds + E * D * NV * Ns;  // [E][NV][Nf]
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) lf[idx] = fhat[e0 * NV * Nf + idx];
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  const bool act = el < ne;
+  const int64_t e = e0 + el;
+  T invJ = T(0);
+  if (act) {
+    T uv[NV], Sm[D];
+    for (int v = 0; v < NV; ++v) uv[v] = u[(e * NV + v) * Ns + i];
+    for (int k = 0; k < D; ++k) {
+      for (int j = 0; j < D; ++j) Sm[j] = metric[(e * NM + k * D + j) * Ns + i];
+      T fi[NV];
+      finv_dot<D>(uv, Sm, ph.gm1, fi);
+      for (int v = 0; v < NV; ++v) lF[((el * D + k) * NV + v) * Ns + i] = fi[v];
+    }
+    invJ = metric[(e * NM + D * D) * Ns + i];
+  }
+  __syncthreads();
+  T w[NV];
+  if (act) {
+    T R[NV];
+    for (int v = 0; v < NV; ++v) {
+      T accv = T(0);
+      for (int k = 0; k < D; ++k) {
+        int base, stride, ik, t;
+        line_of_sol<D, P>(i, k, base, stride, ik, t);
+        const T *lin = lF + ((el * D + k) * NV + v) * Ns + base;
+        T ds = T(0), fm = T(0), fpv = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          const T val = lin[a * stride];
+          ds += ops.D[ik * P + a] * val;
+          fm += ops.lm[a] * val;
+          fpv += ops.lp[a] * val;
+        }
+        const T *lfv = lf + (el * NV + v) * Nf;
+        accv += ds + ops.gm[ik] * (fm + lfv[(2 * k) * Nfp + t]) + ops.gp[ik] * (lfv[(2 * k + 1) * Nfp + t] - fpv);
+      }
+      R[v] = -invJ * accv;
+    }
+    rk_epilogue<D, P>(R, e, i, rk, elem_mesh, w);
+  }
+  if (rk.uf_next) {
+    __syncthreads();
+    if (act)
+      for (int v = 0; v < NV; ++v) lds[(el * NV + v) * Ns + i] = w[v];
+    __syncthreads();
+    tile_interp<D, P>(lds, ne, ops, rk.uf_next + e0 * NV * Nf);
+  }
+}
+
+// probe pressure samples (FP64): one workgroup handles every probe in a fixed order
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_probe(const T *__restrict__ u, const int64_t *__restrict__ pelem,
+                                               const double *__restrict__ pw, const double *__restrict__ pinf,
+                                               int n_probe, double gm1, double *series, int cap, double *sums,
+                                               unsigned long long *count, int *nonfinite) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns;
+  __shared__ double red[256];
+  __shared__ double uval[NV];
+  const unsigned long long n = *count;
+  for (int a = 0; a < n_probe; ++a) {
+    const int64_t e = pelem[a];
+    for (int v = 0; v < NV; ++v) {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < Ns; i += blockDim.x)
+        s += pw[(int64_t)a * Ns + i] * (double)u[(e * NV + v) * Ns + i];
+      red[threadIdx.x] = s;
+      __syncthreads();
+      for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) uval[v] = red[0];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double ke = 0.0;
+      for (int j = 0; j < D; ++j) ke += uval[1 + j] * uval[1 + j];
+      const double p = gm1 * (uval[D + 1] - 0.5 * ke / uval[0]);
+      if (n < (unsigned long long)cap) series[(int64_t)a * cap + (int64_t)n] = p;
+      const double dp = p - pinf[a];
+      sums[2 * a] += dp;
+      sums[2 * a + 1] += dp * dp;
+      if (!isfinite(p)) *nonfinite = 1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = n + 1;
+}
+
+// wall force per mesh (FP64): sum over wall flux points of w |N| (p n - tau n); one workgroup
+// per mesh, fixed reduction order
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_wall_force(const T *__restrict__ uf, const T *__restrict__ gradf,
+                                                    const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
+                                                    const double *__restrict__ bw,
+                                                    const int64_t *__restrict__ wall_begin,
+                                                    const int32_t *__restrict__ elem_mesh,
+                                                    const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
+                                                    double *force_acc) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Nf = S::Nf;
+  __shared__ double red[256][D];
+  const int m = blockIdx.x;
+  double f[D];
+  for (int j = 0; j < D; ++j) f[j] = 0.0;
+  for (int64_t b = wall_begin[m] + threadIdx.x; b < wall_begin[m + 1]; b += blockDim.x) {
+    const int32_t c = bnd[b];
+    const int64_t e = c / Nf;
+    const int fp = c % Nf;
+    T uB[NV], g[D * NV], n[D];
+    for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) g[j * NV + v] = gradf[((e * D + j) * NV + v) * Nf + fp];
+    for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+    const double mag = (double)bnrm[b * (D + 1) + D];
+    T rho, vel[D], p;
+    primitives<D>(uB, ph.gm1, rho, vel, p);
+    T ke = T(0);
+    for (int j = 0; j < D; ++j) ke += uB[1 + j] * uB[1 + j];
+    T uw[NV];
+    uw[0] = uB[0];
+    for (int j = 0; j < D; ++j) uw[1 + j] = T(0);
+    uw[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
+    Visc<D, T> vs;
+    T fv[NV];
+    visc_state<D>(uw, g, flow[elem_mesh[e]].mu, ph, false, vs);
+    fvis_dot<D>(vs, n, fv);
+    const double wm = bw[b] * mag;
+    for (int j = 0; j < D; ++j) f[j] += wm * ((double)p * (double)n[j] - (double)fv[1 + j]);
+  }
+  for (int j = 0; j < D; ++j) red[threadIdx.x][j] = f[j];
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int j = 0; j < D; ++j) red[threadIdx.x][j] += red[threadIdx.x + st][j];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int j = 0; j < D; ++j) force_acc[m * D + j] += red[0][j];
+}
+
+// fill kernel (graph-safe replacement for memset)
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_reset_counters(unsigned long long *count, int *nonfinite) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) { *count = 0ull; *nonfinite = 0; }
+}
+
+// ------------------------------------------------------------------------------------ engine
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int D, int P, typename T>
+struct Engine {
+  using S = Shape<D, P>;
+
+  static OpsDev<T, P> ops(const fr_solver *s) {
+    OpsDev<T, P> o;
+    for (int i = 0; i < P * P; ++i) o.D[i] = (T)s->ops.D[i];
+    for (int i = 0; i < P; ++i) {
+      o.lm[i] = (T)s->ops.lm[i];
+      o.lp[i] = (T)s->ops.lp[i];
+      o.gp[i] = (T)s->ops.gp[i];
+      o.gm[i] = (T)s->ops.gm[i];
+    }
+    return o;
+  }
+  static PhysDev<T> phys(const fr_solver *s) {
+    PhysDev<T> p;
+    p.gamma = (T)s->gamma;
+    p.gm1 = (T)(s->gamma - 1.0);
+    p.prandtl = (T)s->prandtl;
+    p.beta = (T)s->beta;
+    p.tau = (T)s->tau;
+    return p;
+  }
+
+  static void interp(const fr_solver *s, const T *u, T *uf, hipStream_t st) {
+    k_interp<D, P, T><<<nblk(s->Ne * S::Nf, 256), 256, 0, st>>>(u, uf, ops(s), s->Ne);
+  }
+
+  // one residual evaluation of `u` whose flux-point values are already in s->uf; the epilogue
+  // `rk` decides what is written
+  static void stage(const fr_solver *s, const T *u, const RKArgs<T> &rk, hipStream_t st, bool force_sample) {
+    const OpsDev<T, P> o = ops(s);
+    const PhysDev<T> ph = phys(s);
+    const int64_t nface = s->npair + s->nbnd;
+    T *uf = (T *)s->uf, *fhat = (T *)s->fhat;
+    const T *metric = (const T *)s->metric;
+    const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
+    if (s->equations == 1) {
+      T *du = (T *)s->du, *gradf = (T *)s->gradf, *vol = (T *)s->vol;
+      k_common_sol<D, P, T><<<nblk(nface, 256), 256, 0, st>>>(uf, s->pairL, s->pairR, s->npair, s->bnd,
+                                                               (const T *)s->bnd_nrm, s->n_wall, s->nbnd,
+                                                               s->elem_mesh, fl, ph, du);
+      using TL = GradTile<D, P, T>;
+      k_ns_grad<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, du, metric, s->elem_mesh, fl, o, ph, gradf, vol,
+                                                                 s->Ne);
+      if (force_sample && s->forces && s->n_wall > 0)
+        k_wall_force<D, P, T><<<s->n_mesh, 256, 0, st>>>(uf, gradf, s->bnd, (const T *)s->bnd_nrm, s->bnd_w,
+                                                          s->wall_mesh_begin, s->elem_mesh, fl, ph, s->force_acc);
+      k_face_flux<D, P, T, true><<<nblk(nface, 256), 256, 0, st>>>(
+          uf, gradf, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm, s->n_wall,
+          s->nbnd, s->elem_mesh, fl, ph, fhat);
+      using TD = DivTile<D, P, T>;
+      k_div_rk<D, P, T><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk, s->Ne);
+    } else {
+      k_face_flux<D, P, T, false><<<nblk(nface, 256), 256, 0, st>>>(
+          uf, nullptr, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
+      using TE = EulerTile<D, P, T>;
+      k_euler_vol_rk<D, P, T><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh, o, ph, rk,
+                                                                      s->Ne);
+    }
+  }
+
+  static void rhs(const fr_solver *s, const T *u, T *r, hipStream_t st) {
+    interp(s, u, (T *)s->uf, st);
+    RKArgs<T> rk{};
+    rk.r_out = r;
+    stage(s, u, rk, st, false);
+  }
+
+  static void probe(const fr_solver *s, const T *u, hipStream_t st) {
+    k_probe<D, P, T><<<1, 256, 0, st>>>(u, s->probe_elem, s->probe_w, s->probe_pinf, s->n_probe, s->gamma - 1.0,
+                                        s->series, s->cap, s->sums, s->count, s->nonfinite);
+  }
+
+  // one classical RK4 step of u in place
+  static void step(const fr_solver *s, T *u, const double *dt, bool sample, hipStream_t st) {
+    static const double cA[4] = {0.5, 0.5, 1.0, 0.0};
+    static const double cB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    if (sample) probe(s, u, st);
+    interp(s, u, (T *)s->uf, st);
+    for (int k = 0; k < 4; ++k) {
+      RKArgs<T> rk{};
+      rk.u0 = u;
+      rk.acc = (T *)s->acc;
+      rk.ustage = (T *)s->ustage;
+      rk.dt = dt;
+      rk.cA = (T)cA[k];
+      rk.cB = (T)cB[k];
+      rk.first = k == 0;
+      rk.last = k == 3;
+      rk.uf_next = k < 3 ? (T *)s->uf : nullptr;
+      const T *ust = k == 0 ? u : (const T *)s->ustage;
+      stage(s, ust, rk, st, sample && k == 0);
+    }
+  }
+};
+
+// ------------------------------------------------------------------------------------ dispatch
+struct Dispatch {
+  void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
+  void (*step)(const fr_solver *, void *, const double *, bool, hipStream_t);
+};
+
+template <int D, int P, typename T>
+Dispatch make_dispatch() {
+  Dispatch d;
+  d.rhs = [](const fr_solver *s, const void *u, void *r, hipStream_t st) {
+    Engine<D, P, T>::rhs(s, (const T *)u, (T *)r, st);
+  };
+  d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, hipStream_t st) {
+    Engine<D, P, T>::step(s, (T *)u, dt, sample, st);
+  };
+  return d;
+}
+
+bool get_dispatch(int dim, int p, int precision, Dispatch &out) {
+#define FR_CASE(DD, PP)                                                              \
+  if (dim == DD && p + 1 == PP) {                                                    \
+    out = precision == 0 ? make_dispatch<DD, PP, double>() : make_dispatch<DD, PP, float>(); \
+    return true;                                                                     \
+  }
+  FR_CASE(2, 2) FR_CASE(2, 3) FR_CASE(2, 4) FR_CASE(2, 5)
+  FR_CASE(3, 2) FR_CASE(3, 3) FR_CASE(3, 4) FR_CASE(3, 5)
+#undef FR_CASE
+  return false;
+}
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t st) {
+  if (n > 0) k_fill_f64<<<nblk(n, 256), 256, 0, st>>>(p, n, v);
+}
+
+void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st) {
+  k_reset_counters<<<1, 64, 0, st>>>(count, nonfinite);
+}
+
+}  // namespace frmi

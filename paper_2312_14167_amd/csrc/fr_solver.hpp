@@ -1,0 +1,90 @@
+// Internal solver handle shared by the API layer and the kernel engines.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fr_host.hpp"
+
+namespace frmi {
+
+// per-mesh free stream and viscosity in the state precision
+template <typename T>
+struct FlowDev {
+  T rho, v[3], p, mu;
+};
+
+template <typename T, int P>
+struct OpsDev {
+  T D[P * P];   // D[a*P + b] = l_b'(xi_a)
+  T lm[P], lp[P];
+  T gp[P], gm[P];  // g_R'(xi_a), g_R'(-xi_a)
+};
+
+template <typename T>
+struct PhysDev {
+  T gamma, gm1, prandtl, beta, tau;
+};
+
+}  // namespace frmi
+
+struct fr_solver {
+  int dim = 0, p = 0, P = 0, Ns = 0, Nfp = 0, Nf = 0, NV = 0;
+  int equations = 0, precision = 0;
+  int64_t Ne = 0;
+  int n_mesh = 1;
+  size_t tsize = 8;
+  double gamma = 1.4, prandtl = 0.71, beta = 0.5, tau = 0.1;
+
+  // host copies
+  frmi::Ops1D ops;
+  std::vector<double> xsol;           // [Ne][Ns][dim]
+  std::vector<double> h_rho, h_vel, h_p, h_mu;
+  std::vector<int64_t> mesh_begin;
+  std::vector<int64_t> h_wall_mesh_begin;
+  std::vector<double> h_probe_pinf;
+
+  // device arrays (precision T unless noted)
+  void *metric = nullptr;   // [Ne][dim*dim+1][Ns]
+  void *uf = nullptr;       // [Ne][NV][Nf]
+  void *du = nullptr;       // [Ne][NV][Nf]   (NS)
+  void *gradf = nullptr;    // [Ne][dim][NV][Nf] (NS)
+  void *vol = nullptr;      // [Ne][NV][Ns]   (NS)
+  void *fhat = nullptr;     // [Ne][NV][Nf]
+  void *acc = nullptr;      // [Ne][NV][Ns]
+  void *ustage = nullptr;   // [Ne][NV][Ns]
+  void *pair_nrm = nullptr; // [npair][dim+1]
+  void *bnd_nrm = nullptr;  // [nbnd][dim+1]
+  void *flow = nullptr;     // FlowDev<T>[n_mesh]
+  int32_t *pairL = nullptr, *pairR = nullptr, *bnd = nullptr, *elem_mesh = nullptr;
+  int64_t npair = 0, nbnd = 0, n_wall = 0;
+  double *bnd_w = nullptr;          // FP64 [nbnd]
+  int64_t *wall_mesh_begin = nullptr;  // device [n_mesh+1]
+
+  // probes and accumulators (FP64)
+  int n_probe = 0, cap = 0, forces = 0;
+  int64_t *probe_elem = nullptr;  // [n_probe]
+  double *probe_w = nullptr;      // [n_probe][Ns]
+  double *probe_pinf = nullptr;   // [n_probe]
+  double *series = nullptr;       // [n_probe][cap]
+  double *sums = nullptr;         // [n_probe][2]
+  double *force_acc = nullptr;    // [n_mesh][dim]
+  unsigned long long *count = nullptr;  // samples taken
+  int *nonfinite = nullptr;
+
+  // time stepping / graphs
+  int64_t steps_since_reset = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  void *graph_u[2] = {nullptr, nullptr};
+  const double *graph_dt[2] = {nullptr, nullptr};
+  int use_graphs = 1;
+
+  // VJP work arrays (allocated on first use)
+  void *vjp_work = nullptr;
+  size_t vjp_bytes = 0;
+
+  std::vector<void *> owned;  // everything hipMalloc'ed
+};

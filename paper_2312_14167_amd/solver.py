@@ -1,0 +1,146 @@
+"""Python binding of the FR library: same operations as the C ABI, torch tensors for device
+memory and the current HIP stream.  Every step of the path runs in libfrmi's kernels."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import FR_EULER, FR_FP32, FR_FP64, FR_NAVIER_STOKES, check, fr_mesh_desc, fr_params, lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a is not None and a.size else None
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """One FR discretisation (one or several concatenated meshes) on the current GPU.
+
+    ``mesh``: mesh description (node coordinates, GLL element nodes, face tags, periodic
+    translations, element ranges); ``flow``: per-mesh free stream / viscosity and fluid
+    constants.  ``precision`` 'fp64' or 'fp32' (accumulators stay FP64).
+    """
+
+    def __init__(self, mesh, p: int, flow, equations: str = "ns", precision: str = "fp64", probes=None,
+                 probe_mesh=None, max_samples: int = 0, forces: bool = False):
+        L = lib()
+        self.dim = mesh.dim
+        self.p = p
+        self.n_mesh = mesh.n_mesh
+        self.equations = equations
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+            keep.append(a)
+            return a
+        node = arr(mesh.node_xyz, np.float64)
+        en = arr(mesh.elem_nodes, np.int64)
+        fb = arr(mesh.face_bc, np.int32)
+        pv = arr(np.asarray(mesh.periodic_vec).reshape(-1, mesh.dim), np.float64)
+        mb = arr(mesh.mesh_elem_begin, np.int64)
+        md = fr_mesh_desc(dim=mesh.dim, p=p, geom_q=mesh.q, n_periodic=pv.shape[0], n_elem=en.shape[0],
+                          n_node=node.shape[0], node_xyz=_ptr(node), elem_nodes=_ptr(en), face_bc=_ptr(fb),
+                          periodic_vec=_ptr(pv), n_mesh=mesh.n_mesh, reserved0=0, mesh_elem_begin=_ptr(mb))
+        rho = arr(flow.rho_inf, np.float64)
+        vel = arr(flow.vel_inf, np.float64)
+        pin = arr(flow.p_inf, np.float64)
+        mu = arr(flow.mu, np.float64)
+        npb = 0
+        pxyz = pm = None
+        if probes is not None:
+            pxyz = arr(np.atleast_2d(probes), np.float64)
+            npb = pxyz.shape[0]
+            pm = arr(np.zeros(npb) if probe_mesh is None else probe_mesh, np.int32)
+        prm = fr_params(equations=FR_NAVIER_STOKES if equations == "ns" else FR_EULER,
+                        precision=FR_FP64 if precision == "fp64" else FR_FP32,
+                        gamma=flow.gamma, prandtl=flow.prandtl, ldg_beta=flow.ldg_beta, ldg_tau=flow.ldg_tau,
+                        rho_inf=_ptr(rho), vel_inf=_ptr(vel), p_inf=_ptr(pin), mu=_ptr(mu),
+                        n_probe=npb, max_samples=max(int(max_samples), 1 if npb else 0),
+                        probe_xyz=_ptr(pxyz), probe_mesh=_ptr(pm), forces=1 if forces else 0, reserved0=0)
+        h = C.c_void_p()
+        check(L.fr_build_operators(C.byref(md), C.byref(prm), C.byref(h)))
+        self._h = h
+        shp = (C.c_int64 * 3)()
+        check(L.fr_state_shape(h, shp))
+        self.shape = tuple(int(x) for x in shp)
+        self.n_probe = npb
+
+    # ----------------------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_state(self, t: torch.Tensor, name: str):
+        if not (t.is_cuda and t.dtype == self.dtype and tuple(t.shape) == self.shape and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {self.dtype} CUDA tensor of shape {self.shape}")
+
+    def new_state(self) -> torch.Tensor:
+        return torch.empty(self.shape, dtype=self.dtype, device="cuda")
+
+    def solpt_coords(self) -> np.ndarray:
+        out = np.empty((self.shape[0], self.shape[2], self.dim))
+        check(lib().fr_solpt_coords(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def rhs(self, u: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        self._check_state(u, "u")
+        r = self.new_state() if out is None else out
+        self._check_state(r, "out")
+        check(lib().fr_rhs(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(r.data_ptr()), _stream(stream)))
+        return r
+
+    def rk_step(self, u: torch.Tensor, dt: torch.Tensor, n_steps: int = 1, sample_every: int = 0, stream=None):
+        self._check_state(u, "u")
+        if not (dt.is_cuda and dt.dtype == torch.float64 and dt.numel() == self.n_mesh and dt.is_contiguous()):
+            raise ValueError("dt must be a contiguous float64 CUDA tensor with one entry per mesh")
+        check(lib().fr_rk_step(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), int(n_steps),
+                               int(sample_every), _stream(stream)))
+        return u
+
+    def reset_accumulators(self, stream=None):
+        check(lib().fr_reset_accumulators(self._h, _stream(stream)))
+
+    def probe_oaspl(self, p_ref: float = 1.0, stream=None) -> dict:
+        npb = max(self.n_probe, 1)
+        prms = np.zeros(npb)
+        oaspl = np.zeros(npb)
+        force = np.zeros(self.n_mesh * self.dim)
+        n = C.c_int64()
+        check(lib().fr_probe_oaspl(self._h, float(p_ref), prms.ctypes.data_as(C.c_void_p),
+                                   oaspl.ctypes.data_as(C.c_void_p), force.ctypes.data_as(C.c_void_p),
+                                   C.byref(n), _stream(stream)))
+        return {"prms": prms[:self.n_probe], "oaspl": oaspl[:self.n_probe],
+                "mean_force": force.reshape(self.n_mesh, self.dim), "n_samples": int(n.value)}
+
+    def probe_series(self, cap: int, stream=None) -> np.ndarray:
+        out = np.zeros((max(self.n_probe, 1), cap))
+        n = C.c_int64()
+        check(lib().fr_probe_series(self._h, out.ctypes.data_as(C.c_void_p), int(cap), C.byref(n), _stream(stream)))
+        return out[:self.n_probe, :min(int(n.value), cap)]
+
+    def rhs_vjp(self, u: torch.Tensor, r_bar: torch.Tensor, u_bar: torch.Tensor, x_bar: torch.Tensor | None = None,
+                stream=None):
+        self._check_state(u, "u")
+        self._check_state(r_bar, "r_bar")
+        self._check_state(u_bar, "u_bar")
+        xb = C.c_void_p(x_bar.data_ptr()) if x_bar is not None else None
+        check(lib().fr_rhs_vjp(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(r_bar.data_ptr()),
+                               C.c_void_p(u_bar.data_ptr()), xb, _stream(stream)))
+        return u_bar

@@ -1,0 +1,131 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
+
+Tolerances: FP64 relative L2 (max over variables) <= 1e-12 on the state after RK4 steps
+(the stated per-step target) and <= 1e-11 on the residual itself (the residual is a difference
+of fluxes ~ p_inf / h, so its round-off is amplified relative to its size; the bound is the
+FP64 unit round-off 1.1e-16 times a conservative 1e5 amplification).  FP32: relative L2 <= 1e-5
+on the state after one step; the residual within 2e-3 relative (FP32 unit round-off 6e-8 times
+the same amplification, rounded up).
+"""
+import numpy as np
+import pytest
+import torch
+
+from cases import make_case, oracle_for, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["euler_vortex", "euler_farfield_curved", "ns_periodic_curved", "ns_ogrid", "ns_channel_p3",
+         "ns_box3d_p2", "ns_cgrid_p4", "ns_cavity_batch"]
+
+
+def _solver(name, precision="fp64", forces=True):
+    from paper_2312_14167_amd import Solver
+    s, m, p, fp, eq, u0, dt, probes, pm = oracle_for(name)
+    sol = Solver(m, p, fp, equations=eq, precision=precision, probes=probes, probe_mesh=pm, max_samples=64,
+                 forces=forces)
+    return s, sol, u0, dt
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_solpt_coords_match_oracle(name, gpu):
+    s, sol, u0, dt = _solver(name)
+    np.testing.assert_allclose(sol.solpt_coords(), s.solpt_coords(), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rhs_fp64(name, gpu):
+    s, sol, u0, dt = _solver(name)
+    Rref = s.residual(u0)
+    R = sol.rhs(u0.to(gpu))
+    torch.cuda.synchronize()
+    err = rel_l2(R, Rref)
+    print(f"{name}: rhs fp64 rel L2 {err:.3e}")
+    assert err <= 1e-11, err
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rk4_fp64_1_and_20_steps_with_probe(name, gpu):
+    s, sol, u0, dt = _solver(name)
+    dtt = torch.tensor(dt, dtype=torch.float64, device=gpu)
+    u = u0.to(gpu).clone()
+    sol.reset_accumulators()
+    sol.rk_step(u, dtt, 1, sample_every=1)
+    uref1, P1, F1 = s.run(u0, torch.tensor(dt), 1, sample_every=1)
+    torch.cuda.synchronize()
+    e1 = rel_l2(u, uref1)
+    sol.rk_step(u, dtt, 19, sample_every=1)
+    uref, P, F = s.run(uref1, torch.tensor(dt), 19, sample_every=1, step0=1)
+    P = torch.cat([P1, P])
+    F = torch.cat([F1, F])
+    e20 = rel_l2(u, uref)
+    ser = sol.probe_series(64)
+    st = sol.probe_oaspl(p_ref=2e-5)
+    print(f"{name}: rk4 fp64 rel L2 1 step {e1:.3e}, 20 steps {e20:.3e}")
+    assert e1 <= 1e-12 and e20 <= 1e-12, (e1, e20)
+    assert st["n_samples"] == 20
+    np.testing.assert_allclose(ser.T, P.numpy(), rtol=1e-12, atol=0)
+    pr = P.numpy()
+    np.testing.assert_allclose(st["prms"], pr.std(axis=0), rtol=1e-6, atol=1e-13)
+    if s.viscous and (s.bT == 1).any():
+        Fm = F.mean(dim=0).numpy()
+        scale = np.abs(Fm).max()
+        np.testing.assert_allclose(st["mean_force"], Fm, rtol=0, atol=1e-10 * max(scale, 1e-3))
+
+
+@pytest.mark.parametrize("name", ["euler_vortex", "ns_periodic_curved", "ns_ogrid", "ns_box3d_p2", "ns_cgrid_p4",
+                                  "ns_cavity_batch"])
+def test_fp32_vs_fp64_oracle(name, gpu):
+    s, sol, u0, dt = _solver(name, precision="fp32")
+    Rref = s.residual(u0)
+    R = sol.rhs(u0.float().to(gpu))
+    eR = rel_l2(R, Rref)
+    u = u0.float().to(gpu).clone()
+    dtt = torch.tensor(dt, dtype=torch.float64, device=gpu)
+    sol.rk_step(u, dtt, 1)
+    uref, _, _ = s.run(u0, torch.tensor(dt), 1, sample_every=0)
+    torch.cuda.synchronize()
+    e1 = rel_l2(u, uref)
+    print(f"{name}: fp32 rhs rel L2 {eR:.3e}, 1 step {e1:.3e}")
+    assert e1 <= 1e-5, e1
+    assert eR <= 2e-3, eR
+
+
+def test_graph_replay_matches_direct_launches(gpu, monkeypatch):
+    """Steps replayed from the captured graph equal the same steps launched directly, bit for bit,
+    and two identical runs are bitwise identical (no atomics in the reductions)."""
+    name = "ns_ogrid"
+    s, sol, u0, dt = _solver(name)
+    dtt = torch.tensor(dt, dtype=torch.float64, device=gpu)
+    outs = []
+    for _ in range(2):
+        u = u0.to(gpu).clone()
+        sol.reset_accumulators()
+        sol.rk_step(u, dtt, 5, sample_every=2)
+        outs.append((u.clone(), sol.probe_series(8)))
+    assert torch.equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    monkeypatch.setenv("FRMI_NO_GRAPH", "1")
+    _, sol2, _, _ = _solver(name)
+    u = u0.to(gpu).clone()
+    sol2.rk_step(u, dtt, 5, sample_every=2)
+    assert torch.equal(u, outs[0][0])
+    np.testing.assert_array_equal(sol2.probe_series(8), outs[0][1])
+
+
+def test_ragged_tiles_and_single_element(gpu):
+    """Element counts that leave partial workgroup tiles, and a one-element periodic mesh (an
+    element that is its own neighbour through opposite faces)."""
+    import fr_inputs as fi
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    for n, p in [((1, 1), 2), ((7, 3), 4), ((5, 9), 3)]:
+        m = fi.periodic_box(2, n, q=2, curv=0.1 if min(n) > 1 else 0.0, seed=1)
+        fp = fi.freestream_params(2, 0.3, 100.0, aoa_deg=30.0)
+        s = OracleSystem(m, p, fp, equations="ns")
+        x = s.solpt_coords()
+        u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (4,), 3, 0.01)).permute(0, 2, 1)
+        u0 = u0.contiguous()
+        sol = Solver(m, p, fp, equations="ns")
+        R = sol.rhs(u0.to(gpu))
+        assert rel_l2(R, s.residual(u0)) <= 1e-11

@@ -1,0 +1,109 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol of include/fr.h, the
+ctypes structures match the C layout, and host-side validation errors are reported before any
+device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import fr_inputs as fi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fr.h")
+
+
+def _lib():
+    from paper_2312_14167_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libfrmi.so not built")
+    return _lib
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib().lib()
+    text = open(HEADER).read()
+    names = set(re.findall(r"\b(fr_[a-z_]+)\s*\(", text))
+    names -= {"fr_status"}
+    assert {"fr_build_operators", "fr_rhs", "fr_rk_step", "fr_probe_oaspl", "fr_rhs_vjp"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_ctypes_layout_matches_c_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fr.h"\nint main(void){'
+                   'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fr_mesh_desc), sizeof(fr_params),'
+                   ' offsetof(fr_mesh_desc, mesh_elem_begin), offsetof(fr_params, n_probe),'
+                   ' offsetof(fr_params, forces), offsetof(fr_mesh_desc, n_mesh)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    lb = _lib()
+    want = [C.sizeof(lb.fr_mesh_desc), C.sizeof(lb.fr_params), lb.fr_mesh_desc.mesh_elem_begin.offset,
+            lb.fr_params.n_probe.offset, lb.fr_params.forces.offset, lb.fr_mesh_desc.n_mesh.offset]
+    assert got == want
+
+
+def _build(mesh, p=2, probes=None, eq=1):
+    lb = _lib()
+    L = lb.lib()
+    keep = []
+
+    def a(x, dt):
+        x = np.ascontiguousarray(np.asarray(x, dt))
+        keep.append(x)
+        return x.ctypes.data_as(C.c_void_p) if x.size else None
+    pv = np.asarray(mesh.periodic_vec).reshape(-1, mesh.dim)
+    md = lb.fr_mesh_desc(dim=mesh.dim, p=p, geom_q=mesh.q, n_periodic=pv.shape[0], n_elem=mesh.n_elem,
+                         n_node=mesh.node_xyz.shape[0], node_xyz=a(mesh.node_xyz, np.float64),
+                         elem_nodes=a(mesh.elem_nodes, np.int64), face_bc=a(mesh.face_bc, np.int32),
+                         periodic_vec=a(pv, np.float64), n_mesh=1, reserved0=0, mesh_elem_begin=None)
+    fp = fi.freestream_params(mesh.dim, 0.2, 100.0)
+    prm = lb.fr_params(equations=eq, precision=0, gamma=1.4, prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1,
+                       rho_inf=a(fp.rho_inf, np.float64), vel_inf=a(fp.vel_inf, np.float64),
+                       p_inf=a(fp.p_inf, np.float64), mu=a(fp.mu, np.float64),
+                       n_probe=0 if probes is None else len(probes), max_samples=4,
+                       probe_xyz=None if probes is None else a(probes, np.float64), probe_mesh=None,
+                       forces=0, reserved0=0)
+    h = C.c_void_p()
+    st = L.fr_build_operators(C.byref(md), C.byref(prm), C.byref(h))
+    return st, L.fr_last_error().decode(), h
+
+
+def test_host_validation_errors_without_gpu():
+    lb = _lib()
+    L = lb.lib()
+    # NULL arguments
+    assert L.fr_build_operators(None, None, None) == lb.FR_ERR_ARG
+    assert L.fr_rhs(None, None, None, None) == lb.FR_ERR_ARG
+    assert L.fr_rk_step(None, None, None, 1, 0, None) == lb.FR_ERR_ARG
+    assert L.fr_rhs_vjp(None, None, None, None, None, None) == lb.FR_ERR_ARG
+    shp = (C.c_int64 * 3)()
+    assert L.fr_state_shape(None, shp) == lb.FR_ERR_ARG
+    # unsupported degree
+    m = fi.periodic_box(2, 3, q=1)
+    st, msg, _ = _build(m, p=7)
+    assert st == lb.FR_ERR_UNSUPPORTED
+    # unmatched face
+    m = fi.periodic_box(2, 3, q=1)
+    m.periodic_vec = m.periodic_vec[:1]
+    st, msg, _ = _build(m)
+    assert st == lb.FR_ERR_MESH and "unmatched" in msg
+    # inverted element
+    m = fi.periodic_box(2, 3, q=1, bc="farfield")
+    m.elem_nodes[0] = m.elem_nodes[0][[1, 0, 3, 2]]
+    st, msg, _ = _build(m)
+    assert st == lb.FR_ERR_MESH and "Jacobian" in msg
+    # probe outside the mesh
+    m = fi.periodic_box(2, 3, q=1, bc="farfield")
+    st, msg, _ = _build(m, probes=np.array([[50.0, 0.0]]))
+    assert st == lb.FR_ERR_MESH and "probe" in msg
+    # unknown face tag
+    m = fi.periodic_box(2, 3, q=1, bc="farfield")
+    m.face_bc[0, 0] = 9
+    st, msg, _ = _build(m)
+    assert st == lb.FR_ERR_ARG
+    L.fr_destroy(None)
