@@ -60,7 +60,8 @@ class OracleSystem:
         geo = self.geometry(nodes)
         scale = float(np.ptp(mesh.node_xyz, axis=0).max())
         (eL, fL, eR, fR), (bE, bF, bT) = match_faces(
-            d, geo["x_f"].detach().numpy(), ops.fpt_k, ops.fpt_s, ops.Nfp, mesh.face_bc, mesh.periodic_vec, scale)
+            d, geo["x_f"].detach().numpy(), ops.fpt_k, ops.fpt_s, ops.Nfp, mesh.face_bc, mesh.periodic_vec, scale,
+            elem_mesh)
         self.eL, self.fL, self.eR, self.fR = map(torch.as_tensor, (eL, fL, eR, fR))
         self.bE, self.bF, self.bT = map(torch.as_tensor, (bE, bF, bT))
         self.geo = geo

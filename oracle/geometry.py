@@ -56,8 +56,9 @@ def element_map(node_xyz: torch.Tensor, elem_nodes: np.ndarray, phi: np.ndarray,
 
 
 def match_faces(dim, fpt_x: np.ndarray, fpt_k, fpt_s, Nfp: int, face_bc: np.ndarray, periodic_vec: np.ndarray,
-                scale: float):
-    """Pair FACE_AUTO faces geometrically (directly or under +-periodic translations).
+                scale: float, elem_mesh: np.ndarray | None = None):
+    """Pair FACE_AUTO faces geometrically (directly or under +-periodic translations); faces of
+    different meshes of a batch (``elem_mesh``) are never paired, even where they coincide.
 
     fpt_x[e, f*Nfp + t, :] are the flux-point coordinates.  Returns per flux-point pair
     (eL, fptL, eR, fptR) with L the lexicographically smaller (element, face), and the
@@ -78,7 +79,7 @@ def match_faces(dim, fpt_x: np.ndarray, fpt_k, fpt_s, Nfp: int, face_bc: np.ndar
         found = None
         for sh in shifts:
             for b in tree.query_ball_point(cent[e, f] + sh, tol):
-                if b != a:
+                if b != a and (elem_mesh is None or elem_mesh[auto[b][0]] == elem_mesh[e]):
                     found = (auto[b], sh)
                     break
             if found:

@@ -377,7 +377,8 @@ Connectivity build_connectivity(const MeshIn &m, const Ops1D &o, const Geometry 
         auto it = grid.find(k);
         if (it == grid.end()) continue;
         for (int64_t b : it->second) {
-          if (b == a || partner[b] >= 0) continue;
+          // faces of different meshes of a batch are never paired, even where they coincide
+          if (b == a || partner[b] >= 0 || c.elem_mesh[b / nface] != c.elem_mesh[e]) continue;
           const double *cb = &cent[(size_t)b * 3];
           double dist = 0.0;
           for (int j = 0; j < d; ++j) dist = std::max(dist, std::fabs(cb[j] - tgt[j]));
