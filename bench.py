@@ -1,0 +1,299 @@
+#!/usr/bin/env python3
+"""FR RK-stage throughput on one MI355X.
+
+One step = one classical RK4 step (four FR residual stages and updates) of the whole mesh,
+with the probe pressure and wall force sampled in FP64 before the step: the full hot path.
+Headline workload: 3-D Navier-Stokes FR at p = 4 on an extruded C-grid around a seeded NACA
+4-digit section, 200 x 80 x 12 = 192,000 hexes (24.0M solution points x 5 variables), Re 23000,
+M 0.2, in FP64.  Reported beside it: the same in FP32 (FP64 accumulators), a batched poll of 16
+open-cavity meshes advanced together, per-kernel roofline fractions, and the FP64 CPU oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FR RK-stage GDoF/s (p=4 hex, FP64 vs FP32 vs batched); adjoint/fwd time"
+HBM_PEAK_GBS = 8000.0
+KNAMES = ["interp", "common_sol", "ns_grad", "face_flux", "div_rk", "euler_vol_rk", "probe", "wall_force"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------------------------ workloads
+def naca_workload(scale: float = 1.0, seed: int = 2):
+    import fr_inputs as fi
+    rng = np.random.default_rng(seed)
+    aoa = float(rng.uniform(0.0, 6.0))
+    nw, nf, nn, ns = (max(2, int(round(40 * scale))), max(4, int(round(120 * scale))),
+                      max(2, int(round(80 * scale))), max(2, int(round(12 * scale))))
+    m = fi.c_grid_naca(n_wake=nw, n_foil=nf, n_normal=nn, n_span=ns, q=2, seed=seed)
+    fp = fi.freestream_params(3, 0.2, 23000.0, aoa_deg=aoa)
+    return m, fp, aoa
+
+
+def cavity_batch(n: int = 16, seed: int = 3):
+    """16 open cavities, depth/width ratio seeded in [1.5, 3.5], quad counts seeded in 6k-40k."""
+    import fr_inputs as fi
+    rng = np.random.default_rng(seed)
+    ms = []
+    for _ in range(n):
+        a = float(rng.uniform(1.5, 3.5))
+        target = int(rng.uniform(6000, 40000))
+        lo, hi = 0.005, 0.2
+        for _ in range(30):
+            h = np.sqrt(lo * hi)
+            ne = fi.cavity(a, h=h, q=1).n_elem
+            if ne > target:
+                lo = h
+            else:
+                hi = h
+        ms.append(fi.cavity(a, h=np.sqrt(lo * hi), q=2))
+    m = fi.concat_meshes(ms)
+    fp = fi.freestream_params(2, 0.15, 1500.0, n_mesh=n)
+    probes = np.array([[0.5, 1.79]] * n)
+    return m, fp, probes, [x.n_elem for x in ms]
+
+
+def initial_state(sol, fp, mesh, seed: int):
+    import torch
+    import fr_inputs as fi
+    x = sol.solpt_coords()
+    u = np.empty(x.shape[:-1] + (fp.dim + 2,))
+    for k in range(mesh.n_mesh):
+        lo, hi = mesh.mesh_elem_begin[k], mesh.mesh_elem_begin[k + 1]
+        u[lo:hi] = fi.freestream_state(x[lo:hi], fp, k)
+    noise = fi.noise_like(u.shape, seed, 1e-3)
+    u[..., 1:-1] += noise[..., 1:-1]
+    return torch.tensor(u).permute(0, 2, 1).contiguous()
+
+
+# ------------------------------------------------------------------------------------ accounting
+def algorithmic_bytes(info, dim, T, eq):
+    """Minimum HBM bytes per launch of each kernel (every input read once, every output written
+    once; RK kernels averaged over the four stages of a step)."""
+    Ne, NV, Ns, Nf, npair, nbnd, nwall, nmesh = info
+    NM = dim * dim + 1
+    I = 4
+    b = {}
+    b["interp"] = Ne * (NV * Ns + NV * Nf) * T
+    b["common_sol"] = (npair * (2 * NV * T + 2 * I) + nbnd * (NV * T + I) + (nbnd - nwall) * ((dim + 1) * T + I)
+                       + (2 * npair + nbnd) * NV * T)
+    grad = dim * NV if eq == "ns" else 0
+    b["face_flux"] = (npair * ((2 * NV + 2 * grad + dim + 1) * T + 3 * I) + nbnd * ((NV + grad + dim + 1) * T + 2 * I)
+                      + (2 * npair + nbnd) * NV * T)
+    b["ns_grad"] = Ne * ((NV * Ns + NV * Nf + NM * Ns + dim * NV * Nf + NV * Ns) * T + I)
+    rk_rw = (4 * (NV * Ns + NV * Nf + Ns + NV * Ns) + 3 * NV * Ns       # reads: vol/u, fhat, invJ, u0; acc
+             + 3 * (2 * NV * Ns + NV * Nf) + NV * Ns) / 4.0              # writes: acc, ustage, uf / u0
+    b["div_rk"] = Ne * (rk_rw * T + I)
+    b["euler_vol_rk"] = Ne * ((rk_rw + (NM - 1) * Ns) * T + I)
+    b["probe"] = 0.0
+    b["wall_force"] = nwall * ((NV + dim * NV + dim + 1) * T + 8 + 2 * I)
+    return b
+
+
+def time_steps(sol, u, dt, steps, warmup, sample_every=1):
+    import torch
+    sol.reset_accumulators()
+    for _ in range(warmup):
+        sol.rk_step(u, dt, 1, sample_every=sample_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol.rk_step(u, dt, steps, sample_every=sample_every)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_profile(sol, u, dt, steps):
+    """Per-kernel average durations over `steps` RK4 steps, from HIP events recorded on the launch
+    stream around every kernel."""
+    import ctypes as C
+
+    import torch
+    from paper_2312_14167_amd._lib import check, lib
+    L = lib()
+    L.fr_profile_enable.argtypes = [C.c_void_p, C.c_int32]
+    L.fr_profile_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    ms = np.zeros(8)
+    n = np.zeros(8, dtype=np.int64)
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    check(L.fr_profile_enable(sol._h, 1))
+    check(L.fr_profile_read(sol._h, ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p), st))
+    sol.rk_step(u, dt, steps, sample_every=1)
+    check(L.fr_profile_read(sol._h, ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p), st))
+    check(L.fr_profile_enable(sol._h, 0))
+    return {KNAMES[k]: (ms[k], int(n[k])) for k in range(8) if n[k] > 0}
+
+
+def solver_info(sol):
+    import ctypes as C
+    from paper_2312_14167_amd._lib import check, lib
+    L = lib()
+    L.fr_solver_info.argtypes = [C.c_void_p, C.c_void_p]
+    info = np.zeros(8, dtype=np.int64)
+    check(L.fr_solver_info(sol._h, info.ctypes.data_as(C.c_void_p)))
+    return [int(x) for x in info]
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """The FP64 oracle, as it is, on a bounded sample of the headline workload: a reduced C-grid of
+    the same kind (p = 4 hexes, NS), one RK4 step."""
+    import torch
+    from oracle import OracleSystem
+    m, fp, _ = naca_workload(scale=0.25)
+    s = OracleSystem(m, 4, fp, equations="ns")
+    x = s.solpt_coords()
+    import fr_inputs as fi
+    u = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (5,), 1, 1e-3)).permute(0, 2, 1)
+    u = u.contiguous()
+    s.residual(u)  # warm-up
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        s.rk4_step(u, torch.tensor([1e-6]))
+        n += 1
+        if time.perf_counter() - t0 > budget_s / 2 or n >= 4:
+            break
+    t = (time.perf_counter() - t0) / n
+    dof = m.n_elem * 125 * 5
+    return {"value": dof * 4 / t / 1e9, "unit": "GDoF-stage/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"one RK4 step (4 FR residuals, FP64, dense per-element operators) of a reduced C-grid "
+                      f"around the same section: {m.n_elem} p=4 hexes, NS, {n} repetition(s) averaged"}
+
+
+# ------------------------------------------------------------------------------------ main
+def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None, seed=5, profile=False):
+    import torch
+    from paper_2312_14167_amd import Solver
+    t0 = time.perf_counter()
+    sol = Solver(mesh, 4, fp, equations="ns", precision=precision, probes=probes, probe_mesh=probe_mesh,
+                 max_samples=max(steps + warmup, 1), forces=True)
+    log(f"  built {precision} solver in {time.perf_counter() - t0:.1f}s")
+    u = initial_state(sol, fp, mesh, seed).to(device="cuda", dtype=sol.dtype)
+    # stable explicit dt: the trailing-edge cells of the C-grid are ~7e-4 chords long
+    dt = torch.full((mesh.n_mesh,), 5e-7 if mesh.dim == 3 else 1e-5, dtype=torch.float64, device="cuda")
+    t = time_steps(sol, u, dt, steps, warmup)
+    info = solver_info(sol)
+    dof = info[0] * info[1] * info[2]
+    out = {"sec": t, "gdofs": dof * 4 * steps / t / 1e9, "ms_per_step": 1e3 * t / steps, "info": info,
+           "finite": bool(torch.isfinite(u).all())}
+    if profile:
+        out["kernels"] = kernel_profile(sol, u, dt, max(2, min(steps, 10)))
+    st = sol.probe_oaspl(p_ref=2e-5 * fp.p_inf[0] / 101325.0)
+    out["n_samples"] = st["n_samples"]
+    sol.close()
+    del u
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 192,000 hexes)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "reps": 3}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs one process on one MI355X "
+              f"(got --gpus {args.gpus}); multi-GPU sharding is described, not run.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_2312_14167_amd import Solver  # noqa: F401  (fails loudly without libfrmi.so)
+    K, W = args.steps, args.warmup
+    log("building the 3-D C-grid workload")
+    t0 = time.perf_counter()
+    mesh, fp, aoa = naca_workload(scale=args.scale)
+    probe = mesh.info["probe"][None, :]
+    log(f"  mesh: {mesh.n_elem} hexes ({time.perf_counter() - t0:.1f}s)")
+    log("FP64 headline")
+    r64 = run_variant(mesh, fp, "fp64", K, W, probes=probe, profile=True)
+    log(f"  {r64['gdofs']:.2f} GDoF-stage/s, {r64['ms_per_step']:.2f} ms/step")
+    info = r64["info"]
+    ab = algorithmic_bytes(info, 3, 8, "ns")
+    kern = r64["kernels"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    avg_ms = kern[dom][0] / kern[dom][1]
+    per_kernel = {}
+    for k, (ms, n) in kern.items():
+        if ab.get(k, 0) > 0:
+            gbs = ab[k] / (ms / n * 1e-3) / 1e9
+            per_kernel[k] = {"avg_ms": ms / n, "launches": n, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS,
+                             "share": ms / sum(v[0] for v in kern.values())}
+        else:
+            per_kernel[k] = {"avg_ms": ms / n, "launches": n}
+    achieved = ab[dom] / (avg_ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": r64["gdofs"],
+        "unit": "GDoF-stage/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"3-D Navier-Stokes FR, p=4 hexes, extruded C-grid around a seeded NACA 4-digit "
+                                f"section ({mesh.info['camber']*100:.2f}% camber, 12% thick, AoA {aoa:.2f} deg), "
+                                f"{mesh.n_elem} hexes = {info[0]*info[2]/1e6:.2f}M solution points x 5 variables, "
+                                f"Re 23000, M 0.2; one step = RK4 (4 residual stages) with FP64 probe + "
+                                f"wall-force sampling"),
+                   "dof": info[0] * info[1] * info[2], "stages_per_step": 4},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": avg_ms},
+        "kernels": per_kernel,
+    }
+    if not args.no_variants:
+        log("FP32 (FP64 accumulators)")
+        r32 = run_variant(mesh, fp, "fp32", K, W, probes=probe)
+        log(f"  {r32['gdofs']:.2f} GDoF-stage/s")
+        result["variants"] = {"fp32": {"value": r32["gdofs"], "ms_per_step": r32["ms_per_step"],
+                                       "speedup_vs_fp64": r32["gdofs"] / r64["gdofs"]}}
+        del mesh
+        log("batched poll: 16 cavities, FP32, one launch per kernel over all meshes")
+        bm, bfp, bprobes, counts = cavity_batch()
+        rb = run_variant(bm, bfp, "fp32", K, W, probes=bprobes, probe_mesh=np.arange(16))
+        log(f"  {rb['gdofs']:.2f} GDoF-stage/s over {bm.n_elem} quads")
+        result["variants"]["batched_16_cavities_fp32"] = {
+            "value": rb["gdofs"], "ms_per_step": rb["ms_per_step"], "quads": counts, "total_quads": bm.n_elem}
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline()
+        log(f"  {result['cpu_baseline']['value']:.5f} GDoF-stage/s on {result['cpu_baseline']['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,28 @@ fr_status fr_reset_accumulators(fr_solver *s, void *stream);
  * the mesh node coordinates, or NULL.  Returns FR_ERR_UNSUPPORTED for forms not built. */
 fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream);
 
+/* Counts of the discretisation: info[0..7] = {n_elem, nv, Ns, Nf, n_face_pairs (interior and
+ * periodic flux-point pairs), n_boundary_points, n_wall_points, n_mesh}. */
+fr_status fr_solver_info(const fr_solver *s, int64_t info[8]);
+
+/* Kernel identifiers used by the timing interface. */
+#define FR_K_INTERP      0   /* solution -> flux points                         */
+#define FR_K_COMMON_SOL  1   /* LDG common solution (NS)                        */
+#define FR_K_NS_GRAD     2   /* corrected gradient + fluxes + volume divergence */
+#define FR_K_FACE_FLUX   3   /* common normal flux at every flux point          */
+#define FR_K_DIV_RK      4   /* lifting + RK4 stage update + next u_f (NS)      */
+#define FR_K_EULER_VOL   5   /* fluxes + divergence + RK4 update + next u_f     */
+#define FR_K_PROBE       6   /* FP64 probe accumulator                          */
+#define FR_K_FORCE       7   /* FP64 wall-force accumulator                     */
+#define FR_K_COUNT       8
+
+/* Per-kernel timing with HIP events recorded on the launch stream around every kernel.  While
+ * enabled, fr_rhs / fr_rk_step launch kernels directly (no graph replay).  fr_profile_read
+ * synchronises `stream` and returns, per kernel id, the summed duration in ms and the number of
+ * launches since the last read (then resets them).  Arrays have FR_K_COUNT entries. */
+fr_status fr_profile_enable(fr_solver *s, int32_t enable);
+fr_status fr_profile_read(fr_solver *s, double *total_ms, int64_t *launches, void *stream);
+
 /* Release everything the handle owns (NULL is a no-op). */
 void fr_destroy(fr_solver *s);
 

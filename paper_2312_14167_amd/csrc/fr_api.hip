@@ -89,6 +89,11 @@ void free_graphs(fr_solver *s) {
 void destroy(fr_solver *s) {
   if (!s) return;
   free_graphs(s);
+  for (auto &r : s->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : s->prof_pool) (void)hipEventDestroy(e);
   for (void *p : s->owned) (void)hipFree(p);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
@@ -282,7 +287,7 @@ fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, i
     for (int32_t n = 0; n < n_steps; ++n) {
       const bool sample = sample_every > 0 && (s->steps_since_reset % sample_every) == 0;
       const int gi = sample ? 1 : 0;
-      if (s->use_graphs) {
+      if (s->use_graphs && !s->profiling) {
         if (!s->graph[gi] || s->graph_u[gi] != u || s->graph_dt[gi] != dt) {
           if (s->graph[gi]) (void)hipGraphExecDestroy(s->graph[gi]);
           s->graph[gi] = nullptr;
@@ -404,6 +409,52 @@ fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar
   (void)x_bar;
   if (!s || !u || !r_bar || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
   return fail(FR_ERR_UNSUPPORTED, "the vector-Jacobian product is not built for this form");
+}
+
+fr_status fr_solver_info(const fr_solver *s, int64_t info[8]) {
+  if (!s || !info) return fail(FR_ERR_ARG, "NULL argument");
+  info[0] = s->Ne;
+  info[1] = s->NV;
+  info[2] = s->Ns;
+  info[3] = s->Nf;
+  info[4] = s->npair;
+  info[5] = s->nbnd;
+  info[6] = s->n_wall;
+  info[7] = s->n_mesh;
+  return FR_OK;
+}
+
+fr_status fr_profile_enable(fr_solver *s, int32_t enable) {
+  if (!s) return fail(FR_ERR_ARG, "NULL solver");
+  s->profiling = enable ? 1 : 0;
+  return FR_OK;
+}
+
+fr_status fr_profile_read(fr_solver *s, double *total_ms, int64_t *launches, void *stream) {
+  if (!s || !total_ms || !launches) return fail(FR_ERR_ARG, "NULL argument");
+  try {
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    for (auto &r : s->prof_pending) {
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+      if (r.id >= 0 && r.id < FR_K_COUNT) {
+        s->prof_ms[r.id] += ms;
+        s->prof_n[r.id] += 1;
+      }
+      s->prof_pool.push_back(r.a);
+      s->prof_pool.push_back(r.b);
+    }
+    s->prof_pending.clear();
+    for (int k = 0; k < FR_K_COUNT; ++k) {
+      total_ms[k] = s->prof_ms[k];
+      launches[k] = s->prof_n[k];
+      s->prof_ms[k] = 0.0;
+      s->prof_n[k] = 0;
+    }
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
 }
 
 void fr_destroy(fr_solver *s) { destroy(s); }

@@ -750,6 +750,37 @@ __global__ void k_reset_counters(unsigned long long *count, int *nonfinite) {
 // ------------------------------------------------------------------------------------ engine
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// HIP events around one launch when per-kernel timing is enabled (ids FR_K_*)
+struct ProfScope {
+  const fr_solver *s;
+  int id;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  static hipEvent_t get(const fr_solver *s) {
+    if (!s->prof_pool.empty()) {
+      hipEvent_t e = s->prof_pool.back();
+      s->prof_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  ProfScope(const fr_solver *s_, int id_, hipStream_t st_) : s(s_), id(id_), st(st_) {
+    if (s->profiling) {
+      a = get(s);
+      (void)hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (s->profiling) {
+      hipEvent_t b = get(s);
+      (void)hipEventRecord(b, st);
+      s->prof_pending.push_back({id, a, b});
+    }
+  }
+};
+
 template <int D, int P, typename T>
 struct Engine {
   using S = Shape<D, P>;
@@ -776,6 +807,7 @@ struct Engine {
   }
 
   static void interp(const fr_solver *s, const T *u, T *uf, hipStream_t st) {
+    ProfScope ps(s, 0, st);
     k_interp<D, P, T><<<nblk(s->Ne * S::Nf, 256), 256, 0, st>>>(u, uf, ops(s), s->Ne);
   }
 
@@ -790,25 +822,32 @@ struct Engine {
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
     if (s->equations == 1) {
       T *du = (T *)s->du, *gradf = (T *)s->gradf, *vol = (T *)s->vol;
+      { ProfScope ps(s, 1, st);
       k_common_sol<D, P, T><<<nblk(nface, 256), 256, 0, st>>>(uf, s->pairL, s->pairR, s->npair, s->bnd,
                                                                (const T *)s->bnd_nrm, s->n_wall, s->nbnd,
-                                                               s->elem_mesh, fl, ph, du);
+                                                               s->elem_mesh, fl, ph, du); }
       using TL = GradTile<D, P, T>;
+      { ProfScope ps(s, 2, st);
       k_ns_grad<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, du, metric, s->elem_mesh, fl, o, ph, gradf, vol,
-                                                                 s->Ne);
+                                                                 s->Ne); }
       if (force_sample && s->forces && s->n_wall > 0)
+      { ProfScope ps(s, 7, st);
         k_wall_force<D, P, T><<<s->n_mesh, 256, 0, st>>>(uf, gradf, s->bnd, (const T *)s->bnd_nrm, s->bnd_w,
-                                                          s->wall_mesh_begin, s->elem_mesh, fl, ph, s->force_acc);
+                                                          s->wall_mesh_begin, s->elem_mesh, fl, ph, s->force_acc); }
+      { ProfScope ps(s, 3, st);
       k_face_flux<D, P, T, true><<<nblk(nface, 256), 256, 0, st>>>(
           uf, gradf, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm, s->n_wall,
-          s->nbnd, s->elem_mesh, fl, ph, fhat);
+          s->nbnd, s->elem_mesh, fl, ph, fhat); }
       using TD = DivTile<D, P, T>;
+      ProfScope ps(s, 4, st);
       k_div_rk<D, P, T><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk, s->Ne);
     } else {
+      { ProfScope ps(s, 3, st);
       k_face_flux<D, P, T, false><<<nblk(nface, 256), 256, 0, st>>>(
           uf, nullptr, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat); }
       using TE = EulerTile<D, P, T>;
+      ProfScope ps(s, 5, st);
       k_euler_vol_rk<D, P, T><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh, o, ph, rk,
                                                                       s->Ne);
     }
@@ -822,6 +861,7 @@ struct Engine {
   }
 
   static void probe(const fr_solver *s, const T *u, hipStream_t st) {
+    ProfScope ps(s, 6, st);
     k_probe<D, P, T><<<1, 256, 0, st>>>(u, s->probe_elem, s->probe_w, s->probe_pinf, s->n_probe, s->gamma - 1.0,
                                         s->series, s->cap, s->sums, s->count, s->nonfinite);
   }

@@ -82,6 +82,14 @@ struct fr_solver {
   const double *graph_dt[2] = {nullptr, nullptr};
   int use_graphs = 1;
 
+  // per-kernel event timing (FR_K_* ids)
+  int profiling = 0;
+  struct ProfRec { int id; hipEvent_t a, b; };
+  mutable std::vector<ProfRec> prof_pending;
+  mutable std::vector<hipEvent_t> prof_pool;
+  double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t prof_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
   // VJP work arrays (allocated on first use)
   void *vjp_work = nullptr;
   size_t vjp_bytes = 0;
