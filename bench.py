@@ -89,18 +89,17 @@ def algorithmic_bytes(info, dim, T, eq):
     I = 4
     b = {}
     b["interp"] = Ne * (NV * Ns + NV * Nf) * T
-    b["common_sol"] = (npair * (2 * NV * T + 2 * I) + nbnd * (NV * T + I) + (nbnd - nwall) * ((dim + 1) * T + I)
-                       + (2 * npair + nbnd) * NV * T)
-    grad = dim * NV if eq == "ns" else 0
-    b["face_flux"] = (npair * ((2 * NV + 2 * grad + dim + 1) * T + 3 * I) + nbnd * ((NV + grad + dim + 1) * T + 2 * I)
+    vis = NV if eq == "ns" else 0
+    b["face_flux"] = (npair * ((2 * NV + 2 * vis + dim + 1) * T + 2 * I) + nbnd * ((NV + vis + dim + 1) * T + 2 * I)
                       + (2 * npair + nbnd) * NV * T)
-    b["ns_grad"] = Ne * ((NV * Ns + NV * Nf + NM * Ns + dim * NV * Nf + NV * Ns) * T + I)
+    # u, neighbour u_f, metrics, own normals, neighbour codes -> viscous normal flux, volume divergence
+    b["ns_grad"] = Ne * ((NV * Ns + NV * Nf + NM * Ns + dim * Nf + NV * Nf + NV * Ns) * T + Nf * I + I)
     rk_rw = (4 * (NV * Ns + NV * Nf + Ns + NV * Ns) + 3 * NV * Ns       # reads: vol/u, fhat, invJ, u0; acc
-             + 3 * (2 * NV * Ns + NV * Nf) + NV * Ns) / 4.0              # writes: acc, ustage, uf / u0
+             + 4 * NV * Nf + 3 * 2 * NV * Ns + NV * Ns) / 4.0            # writes: u_f, acc + stage state / u0
     b["div_rk"] = Ne * (rk_rw * T + I)
     b["euler_vol_rk"] = Ne * ((rk_rw + (NM - 1) * Ns) * T + I)
     b["probe"] = 0.0
-    b["wall_force"] = nwall * ((NV + dim * NV + dim + 1) * T + 8 + 2 * I)
+    b["wall_force"] = nwall * ((NV + dim + dim + 1) * T + 8 + I)
     return b
 
 

@@ -14,7 +14,7 @@
 namespace frmi {
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
-  void (*step)(const fr_solver *, void *, const double *, bool, hipStream_t);
+  void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
 };
 bool get_dispatch(int dim, int p, int precision, Dispatch &out);
 void launch_fill(double *p, int64_t n, double v, hipStream_t st);
@@ -78,7 +78,7 @@ void *upload_flow(fr_solver *s) {
 }
 
 void free_graphs(fr_solver *s) {
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
     s->graph[k] = nullptr;
     s->graph_u[k] = nullptr;
@@ -210,6 +210,8 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->bnd_nrm = upload_real(s, c.bnd_nrm);
     s->bnd_w = (double *)upload(s, c.bnd_w);
     s->elem_mesh = (int32_t *)upload(s, c.elem_mesh);
+    s->nbr = (int32_t *)upload(s, c.nbr);
+    s->fnrm = upload_real(s, c.fnrm);
     s->h_wall_mesh_begin = c.wall_mesh_begin;
     s->wall_mesh_begin = (int64_t *)upload(s, c.wall_mesh_begin);
     s->flow = s->precision == FR_FP64 ? upload_flow<double>(s) : upload_flow<float>(s);
@@ -220,8 +222,7 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->acc = dalloc(s, nsol * T);
     s->ustage = dalloc(s, nsol * T);
     if (s->equations == FR_NAVIER_STOKES) {
-      s->du = dalloc(s, nf * T);
-      s->gradf = dalloc(s, nf * s->dim * T);
+      s->fvn = dalloc(s, nf * T);
       s->vol = dalloc(s, nsol * T);
     }
     s->h_probe_pinf = pinf;
@@ -286,14 +287,15 @@ fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, i
     Dispatch d = dispatch_of(s);
     for (int32_t n = 0; n < n_steps; ++n) {
       const bool sample = sample_every > 0 && (s->steps_since_reset % sample_every) == 0;
-      const int gi = sample ? 1 : 0;
+      const bool fresh = n == 0;  // later steps of this call reuse the u_f written by the last stage
+      const int gi = (sample ? 1 : 0) + (fresh ? 2 : 0);
       if (s->use_graphs && !s->profiling) {
         if (!s->graph[gi] || s->graph_u[gi] != u || s->graph_dt[gi] != dt) {
           if (s->graph[gi]) (void)hipGraphExecDestroy(s->graph[gi]);
           s->graph[gi] = nullptr;
           hipGraph_t g = nullptr;
           HIP_OK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-          d.step(s, u, dt, sample, s->cap_stream);
+          d.step(s, u, dt, sample, fresh, s->cap_stream);
           hipError_t le = hipGetLastError();
           hipError_t ce = hipStreamEndCapture(s->cap_stream, &g);
           if (le != hipSuccess) throw FrError(FR_ERR_HIP, std::string("launch during capture: ") + hipGetErrorString(le));
@@ -308,7 +310,7 @@ fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, i
         }
         HIP_OK(hipGraphLaunch(s->graph[gi], st));
       } else {
-        d.step(s, u, dt, sample, st);
+        d.step(s, u, dt, sample, fresh, st);
         HIP_OK(hipGetLastError());
       }
       s->steps_since_reset++;

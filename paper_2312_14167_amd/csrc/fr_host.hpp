@@ -63,6 +63,9 @@ struct Connectivity {
   int64_t n_wall = 0;
   std::vector<int64_t> wall_mesh_begin;  // [n_mesh + 1] ranges into the wall list
   std::vector<int32_t> elem_mesh;        // [Ne]
+  // per element flux point: partner code (bit 30 set on the R side) or -(boundary index + 1)
+  std::vector<int32_t> nbr;              // [Ne][Nf]
+  std::vector<double> fnrm;              // [Ne][dim][Nf] outward unit normal (R side: -n_L exactly)
 };
 
 Connectivity build_connectivity(const MeshIn &m, const Ops1D &ops, const Geometry &g);

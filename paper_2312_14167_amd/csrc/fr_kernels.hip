@@ -216,54 +216,36 @@ __global__ __launch_bounds__(256) void k_interp(const T *__restrict__ u, T *__re
   }
 }
 
-// LDG common solution: writes u^ - u_f on both sides (interior) or for the boundary point
-template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void k_common_sol(const T *__restrict__ uf, const int32_t *__restrict__ pairL,
-                                                    const int32_t *__restrict__ pairR, int64_t npair,
-                                                    const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
-                                                    int64_t n_wall, int64_t nbnd, const int32_t *__restrict__ elem_mesh,
-                                                    const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
-                                                    T *__restrict__ du) {
-  using S = Shape<D, P>;
-  constexpr int NV = S::NV, Nf = S::Nf;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid < npair) {
-    const int32_t cL = pairL[gid], cR = pairR[gid];
-    const int64_t eL = cL / Nf, eR = cR / Nf;
-    const int fL = cL % Nf, fR = cR % Nf;
-    const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
-    for (int v = 0; v < NV; ++v) {
-      const T a = uf[(eL * NV + v) * Nf + fL];
-      const T b = uf[(eR * NV + v) * Nf + fR];
-      const T h = wl * a + wr * b;
-      du[(eL * NV + v) * Nf + fL] = h - a;
-      du[(eR * NV + v) * Nf + fR] = h - b;
-    }
-  } else if (gid < npair + nbnd) {
-    const int64_t b = gid - npair;
-    const int32_t c = bnd[b];
-    const int64_t e = c / Nf;
-    const int fp = c % Nf;
-    T uB[NV], ug[NV];
-    for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
-    if (b < n_wall) {
-      T ke = T(0);
-      for (int j = 0; j < D; ++j) ke += uB[1 + j] * uB[1 + j];
-      ug[0] = uB[0];
-      for (int j = 0; j < D; ++j) ug[1 + j] = T(0);
-      ug[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
-    } else {
-      T n[D];
-      for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
-      farfield<D>(uB, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, ug);
-    }
-    for (int v = 0; v < NV; ++v) du[(e * NV + v) * Nf + fp] = ug[v] - uB[v];
+// contiguous tile copy global -> LDS, 16-byte vector accesses when both sides allow it
+template <typename T>
+__device__ __forceinline__ void tile_load(T *__restrict__ dst, const T *__restrict__ src, int n) {
+  constexpr int W = 16 / sizeof(T);
+  if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+    const int nv = n / W;
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    for (int idx = threadIdx.x; idx < nv; idx += blockDim.x) d4[idx] = s4[idx];
+    for (int idx = nv * W + threadIdx.x; idx < n; idx += blockDim.x) dst[idx] = src[idx];
+  } else {
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) dst[idx] = src[idx];
   }
 }
 
-// common normal flux x |N| at every flux point (Rusanov; NS: minus LDG viscous flux + penalty)
+// no-slip wall state: zero velocity, same density and internal energy
+template <int D, typename T>
+__device__ __forceinline__ void wall_state(const T *uB, T *uw) {
+  T ke = T(0);
+  for (int j = 0; j < D; ++j) ke += uB[1 + j] * uB[1 + j];
+  uw[0] = uB[0];
+  for (int j = 0; j < D; ++j) uw[1 + j] = T(0);
+  uw[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
+}
+
+// common normal flux x |N| at every flux point.  Inviscid: Rusanov with the neighbour state or
+// the boundary ghost.  NS: minus the LDG viscous flux assembled from the per-side viscous normal
+// fluxes fvn (each side's F_vis(u, grad u) . n_out, boundary points already in boundary form).
 template <int D, int P, typename T, bool NS>
-__global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, const T *__restrict__ gradf,
+__global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, const T *__restrict__ fvn,
                                                    const int32_t *__restrict__ pairL, const int32_t *__restrict__ pairR,
                                                    const T *__restrict__ pnrm, int64_t npair,
                                                    const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
@@ -286,22 +268,13 @@ __global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, con
     const T mag = pnrm[gid * (D + 1) + D];
     rusanov<D>(uL, uR, n, ph.gamma, ph.gm1, F);
     if (NS) {
-      T gL[D * NV], gR[D * NV];
-      for (int j = 0; j < D; ++j)
-        for (int v = 0; v < NV; ++v) {
-          gL[j * NV + v] = gradf[((eL * D + j) * NV + v) * Nf + fL];
-          gR[j * NV + v] = gradf[((eR * D + j) * NV + v) * Nf + fR];
-        }
-      const T mu = flow[elem_mesh[eL]].mu;
-      Visc<D, T> vs;
-      T fv[NV];
+      // F^_vis . n_L = (1/2 - b) fvn_L + (1/2 + b) (-fvn_R) - tau (u_L - u_R)
       const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
-      visc_state<D>(uL, gL, mu, ph, true, vs);
-      fvis_dot<D>(vs, n, fv);
-      for (int v = 0; v < NV; ++v) F[v] -= wl * fv[v];
-      visc_state<D>(uR, gR, mu, ph, true, vs);
-      fvis_dot<D>(vs, n, fv);
-      for (int v = 0; v < NV; ++v) F[v] -= wr * fv[v] - ph.tau * (uL[v] - uR[v]);
+      for (int v = 0; v < NV; ++v) {
+        const T fl = fvn[(eL * NV + v) * Nf + fL];
+        const T fr = fvn[(eR * NV + v) * Nf + fR];
+        F[v] -= wl * fl - wr * fr - ph.tau * (uL[v] - uR[v]);
+      }
     }
     for (int v = 0; v < NV; ++v) {
       fhat[(eL * NV + v) * Nf + fL] = F[v] * mag;
@@ -316,32 +289,16 @@ __global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, con
     for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
     for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
     const T mag = bnrm[b * (D + 1) + D];
-    const bool wall = b < n_wall;
-    const FlowDev<T> fl = flow[elem_mesh[e]];
-    if (wall) {
+    if (b < n_wall) {
       ug[0] = uB[0];
       for (int j = 0; j < D; ++j) ug[1 + j] = -uB[1 + j];
       ug[D + 1] = uB[D + 1];
     } else {
-      farfield<D>(uB, n, fl, ph.gamma, ph.gm1, ug);
+      farfield<D>(uB, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, ug);
     }
     rusanov<D>(uB, ug, n, ph.gamma, ph.gm1, F);
-    if (NS) {
-      T g[D * NV];
-      for (int j = 0; j < D; ++j)
-        for (int v = 0; v < NV; ++v) g[j * NV + v] = gradf[((e * D + j) * NV + v) * Nf + fp];
-      if (wall) {  // no-slip state: zero velocity, same density and internal energy
-        T ke = T(0);
-        for (int j = 0; j < D; ++j) ke += uB[1 + j] * uB[1 + j];
-        ug[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
-        for (int j = 0; j < D; ++j) ug[1 + j] = T(0);
-      }
-      Visc<D, T> vs;
-      T fv[NV];
-      visc_state<D>(ug, g, fl.mu, ph, !wall, vs);
-      fvis_dot<D>(vs, n, fv);
-      for (int v = 0; v < NV; ++v) F[v] -= fv[v];
-    }
+    if (NS)
+      for (int v = 0; v < NV; ++v) F[v] -= fvn[(e * NV + v) * Nf + fp];
     for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = F[v] * mag;
   }
 }
@@ -350,7 +307,9 @@ __global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, con
 template <int D, int P, typename T>
 struct GradTile {
   using S = Shape<D, P>;
-  static constexpr int LE = cmax(S::NV * S::Ns + S::NV * S::Nf, D * S::NV * S::Ns);
+  // region A: u + (u^ - u_f), later the gradient / transformed flux; region B: own u_f
+  static constexpr int LA = cmax(S::NV * S::Ns + S::NV * S::Nf, D * S::NV * S::Ns);
+  static constexpr int LE = LA + S::NV * S::Nf;
   static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
   static constexpr int BS = round64(E * S::Ns);
 };
@@ -371,22 +330,71 @@ struct EulerTile {
   static constexpr int BS = round64(E * S::Ns);
 };
 
-// NS volume kernel: corrected gradient, gradient at flux points, fluxes and volume divergence
+// element flux-point neighbour code: >= 0 -> partner (element * Nf + flux point), bit 30 set when
+// this element is the R side of the pair; < 0 -> boundary point -(code + 1)
+constexpr int32_t NBR_R_BIT = 1 << 30;
+
+// NS volume kernel.  Per element tile:
+//   own u_f = M0 u; LDG common solution from the neighbour's u_f (or the boundary state);
+//   corrected gradient grad_xi u = D_k u + s_f g_R'(s_f xi)(u^ - u_f); grad_x u = J^-1 S^T grad_xi u;
+//   viscous normal flux at every own flux point fvn = F_vis(u_f, M0 grad_x u) . n_out (walls:
+//   zero-velocity state, no heat flux; far field: Riemann state);
+//   F~_k = S_k . (F_inv - F_vis) at solution points; vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}).
 template <int D, int P, typename T>
 __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
-    const T *__restrict__ u, const T *__restrict__ du, const T *__restrict__ metric,
-    const int32_t *__restrict__ elem_mesh, const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops, PhysDev<T> ph,
-    T *__restrict__ gradf, T *__restrict__ vol, int64_t Ne) {
+    const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
+    const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
+    const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops, PhysDev<T> ph, T *__restrict__ fvn,
+    T *__restrict__ vol, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = GradTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
-  __shared__ T lds[E * TL::LE];
+  __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  T *lu = lds;
-  T *ldu = lds + E * NV * Ns;
-  for (int idx = threadIdx.x; idx < ne * NV * Ns; idx += blockDim.x) lu[idx] = u[e0 * NV * Ns + idx];
-  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) ldu[idx] = du[e0 * NV * Nf + idx];
+  T *lu = lds;                   // [E][NV][Ns]
+  T *ldu = lds + E * NV * Ns;    // [E][NV][Nf]  u^ - u_f
+  T *luf = lds + E * TL::LA;     // [E][NV][Nf]  own u_f
+  tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
+  __syncthreads();
+  const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
+  for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
+    const int el = idx / Nf, fp = idx % Nf;
+    const int64_t e = e0 + el;
+    int base, stride, side;
+    line_of_fpt<D, P>(fp, base, stride, side);
+    const T *lv = side ? ops.lp : ops.lm;
+    T uo[NV], uh[NV];
+    for (int v = 0; v < NV; ++v) {
+      const T *lin = lu + (el * NV + v) * Ns + base;
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+      uo[v] = s;
+      luf[(el * NV + v) * Nf + fp] = s;
+    }
+    const int32_t code = nbr[e * Nf + fp];
+    if (code >= 0) {
+      const int32_t c = code & (NBR_R_BIT - 1);
+      const int64_t e2 = c / Nf;
+      const int f2 = c % Nf;
+      const bool isR = (code & NBR_R_BIT) != 0;
+      for (int v = 0; v < NV; ++v) {
+        const T un = uf[(e2 * NV + v) * Nf + f2];
+        uh[v] = isR ? wl * un + wr * uo[v] : wl * uo[v] + wr * un;
+      }
+    } else {
+      const int64_t b = -(int64_t)code - 1;
+      if (b < n_wall) {
+        wall_state<D>(uo, uh);
+      } else {
+        T n[D];
+        for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+        farfield<D>(uo, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, uh);
+      }
+    }
+    for (int v = 0; v < NV; ++v) ldu[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
+  }
   __syncthreads();
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
@@ -425,17 +433,42 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) lg[((el * D + j) * NV + v) * Ns + i] = gx[j][v];
   __syncthreads();
-  // gradient at flux points for the whole tile (contiguous output range)
-  for (int idx = threadIdx.x; idx < ne * D * NV * Nf; idx += blockDim.x) {
-    const int fp = idx % Nf, rest = idx / Nf;
+  // viscous normal flux at every own flux point
+  for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
+    const int elf = idx / Nf, fp = idx % Nf;
+    const int64_t ef = e0 + elf;
     int base, stride, side;
     line_of_fpt<D, P>(fp, base, stride, side);
     const T *lv = side ? ops.lp : ops.lm;
-    const T *lin = lg + rest * Ns + base;
-    T s = T(0);
+    T g[D * NV], st[NV], n[D];
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) {
+        const T *lin = lg + ((elf * D + j) * NV + v) * Ns + base;
+        T s = T(0);
 #pragma unroll
-    for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-    gradf[e0 * D * NV * Nf + idx] = s;
+        for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+        g[j * NV + v] = s;
+      }
+    for (int v = 0; v < NV; ++v) st[v] = luf[(elf * NV + v) * Nf + fp];
+    for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * D + j) * Nf + fp];
+    const int32_t code = nbr[ef * Nf + fp];
+    bool heat = true;
+    if (code < 0) {
+      const int64_t b = -(int64_t)code - 1;
+      T ub[NV];
+      if (b < n_wall) {
+        wall_state<D>(st, ub);
+        heat = false;
+      } else {
+        farfield<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ub);
+      }
+      for (int v = 0; v < NV; ++v) st[v] = ub[v];
+    }
+    Visc<D, T> vs;
+    T fv[NV];
+    visc_state<D>(st, g, flow[elem_mesh[ef]].mu, ph, heat, vs);
+    fvis_dot<D>(vs, n, fv);
+    for (int v = 0; v < NV; ++v) fvn[(ef * NV + v) * Nf + fp] = fv[v];
   }
   // transformed flux F~_k = S_k . (F_inv - F_vis) at this solution point
   T ft[D][NV];
@@ -545,10 +578,10 @@ __global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_div_rk(const T *__re
   using S = Shape<D, P>;
   using TL = DivTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
-  __shared__ T lds[E * TL::LE];
+  __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) lds[idx] = fhat[e0 * NV * Nf + idx];
+  tile_load(lds, fhat + e0 * NV * Nf, ne * NV * Nf);
   __syncthreads();
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
@@ -589,12 +622,12 @@ __global__ __launch_bounds__((EulerTile<D, P, T>::BS)) void k_euler_vol_rk(
   using S = Shape<D, P>;
   using TL = EulerTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
-  __shared__ T lds[E * TL::LE];
+  __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   T *lF = lds;                  // [E][D][NV][Ns]
   T *lf = lds + E * D * NV * Ns;  // [E][NV][Nf]
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) lf[idx] = fhat[e0 * NV * Nf + idx];
+  tile_load(lf, fhat + e0 * NV * Nf, ne * NV * Nf);
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
   const int64_t e = e0 + el;
@@ -685,15 +718,13 @@ __global__ __launch_bounds__(256) void k_probe(const T *__restrict__ u, const in
   if (threadIdx.x == 0) *count = n + 1;
 }
 
-// wall force per mesh (FP64): sum over wall flux points of w |N| (p n - tau n); one workgroup
-// per mesh, fixed reduction order
+// wall force per mesh (FP64): sum over wall flux points of w |N| (p n - tau n), tau n being the
+// momentum part of the wall viscous normal flux; one workgroup per mesh, fixed reduction order
 template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void k_wall_force(const T *__restrict__ uf, const T *__restrict__ gradf,
+__global__ __launch_bounds__(256) void k_wall_force(const T *__restrict__ uf, const T *__restrict__ fvn,
                                                     const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
                                                     const double *__restrict__ bw,
-                                                    const int64_t *__restrict__ wall_begin,
-                                                    const int32_t *__restrict__ elem_mesh,
-                                                    const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
+                                                    const int64_t *__restrict__ wall_begin, PhysDev<T> ph,
                                                     double *force_acc) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Nf = S::Nf;
@@ -705,26 +736,13 @@ __global__ __launch_bounds__(256) void k_wall_force(const T *__restrict__ uf, co
     const int32_t c = bnd[b];
     const int64_t e = c / Nf;
     const int fp = c % Nf;
-    T uB[NV], g[D * NV], n[D];
+    T uB[NV];
     for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
-    for (int j = 0; j < D; ++j)
-      for (int v = 0; v < NV; ++v) g[j * NV + v] = gradf[((e * D + j) * NV + v) * Nf + fp];
-    for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
-    const double mag = (double)bnrm[b * (D + 1) + D];
     T rho, vel[D], p;
     primitives<D>(uB, ph.gm1, rho, vel, p);
-    T ke = T(0);
-    for (int j = 0; j < D; ++j) ke += uB[1 + j] * uB[1 + j];
-    T uw[NV];
-    uw[0] = uB[0];
-    for (int j = 0; j < D; ++j) uw[1 + j] = T(0);
-    uw[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
-    Visc<D, T> vs;
-    T fv[NV];
-    visc_state<D>(uw, g, flow[elem_mesh[e]].mu, ph, false, vs);
-    fvis_dot<D>(vs, n, fv);
-    const double wm = bw[b] * mag;
-    for (int j = 0; j < D; ++j) f[j] += wm * ((double)p * (double)n[j] - (double)fv[1 + j]);
+    const double wm = bw[b] * (double)bnrm[b * (D + 1) + D];
+    for (int j = 0; j < D; ++j)
+      f[j] += wm * ((double)p * (double)bnrm[b * (D + 1) + j] - (double)fvn[(e * NV + 1 + j) * Nf + fp]);
   }
   for (int j = 0; j < D; ++j) red[threadIdx.x][j] = f[j];
   __syncthreads();
@@ -821,31 +839,35 @@ struct Engine {
     const T *metric = (const T *)s->metric;
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
     if (s->equations == 1) {
-      T *du = (T *)s->du, *gradf = (T *)s->gradf, *vol = (T *)s->vol;
-      { ProfScope ps(s, 1, st);
-      k_common_sol<D, P, T><<<nblk(nface, 256), 256, 0, st>>>(uf, s->pairL, s->pairR, s->npair, s->bnd,
-                                                               (const T *)s->bnd_nrm, s->n_wall, s->nbnd,
-                                                               s->elem_mesh, fl, ph, du); }
+      T *fvn = (T *)s->fvn, *vol = (T *)s->vol;
       using TL = GradTile<D, P, T>;
-      { ProfScope ps(s, 2, st);
-      k_ns_grad<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, du, metric, s->elem_mesh, fl, o, ph, gradf, vol,
-                                                                 s->Ne); }
-      if (force_sample && s->forces && s->n_wall > 0)
-      { ProfScope ps(s, 7, st);
-        k_wall_force<D, P, T><<<s->n_mesh, 256, 0, st>>>(uf, gradf, s->bnd, (const T *)s->bnd_nrm, s->bnd_w,
-                                                          s->wall_mesh_begin, s->elem_mesh, fl, ph, s->force_acc); }
-      { ProfScope ps(s, 3, st);
-      k_face_flux<D, P, T, true><<<nblk(nface, 256), 256, 0, st>>>(
-          uf, gradf, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm, s->n_wall,
-          s->nbnd, s->elem_mesh, fl, ph, fhat); }
+      {
+        ProfScope ps(s, 2, st);
+        k_ns_grad<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, uf, s->nbr, (const T *)s->fnrm,
+                                                                   (const T *)s->bnd_nrm, s->n_wall, metric,
+                                                                   s->elem_mesh, fl, o, ph, fvn, vol, s->Ne);
+      }
+      if (force_sample && s->forces && s->n_wall > 0) {
+        ProfScope ps(s, 7, st);
+        k_wall_force<D, P, T><<<s->n_mesh, 256, 0, st>>>(uf, fvn, s->bnd, (const T *)s->bnd_nrm, s->bnd_w,
+                                                          s->wall_mesh_begin, ph, s->force_acc);
+      }
+      {
+        ProfScope ps(s, 3, st);
+        k_face_flux<D, P, T, true><<<nblk(nface, 256), 256, 0, st>>>(
+            uf, fvn, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
+            s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
+      }
       using TD = DivTile<D, P, T>;
       ProfScope ps(s, 4, st);
       k_div_rk<D, P, T><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk, s->Ne);
     } else {
-      { ProfScope ps(s, 3, st);
-      k_face_flux<D, P, T, false><<<nblk(nface, 256), 256, 0, st>>>(
-          uf, nullptr, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat); }
+      {
+        ProfScope ps(s, 3, st);
+        k_face_flux<D, P, T, false><<<nblk(nface, 256), 256, 0, st>>>(
+            uf, nullptr, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
+            s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
+      }
       using TE = EulerTile<D, P, T>;
       ProfScope ps(s, 5, st);
       k_euler_vol_rk<D, P, T><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh, o, ph, rk,
@@ -866,12 +888,13 @@ struct Engine {
                                         s->series, s->cap, s->sums, s->count, s->nonfinite);
   }
 
-  // one classical RK4 step of u in place
-  static void step(const fr_solver *s, T *u, const double *dt, bool sample, hipStream_t st) {
+  // one classical RK4 step of u in place; `fresh`: s->uf does not hold u_f of u yet (first step
+  // of a call); later steps reuse the flux-point values written by the previous last stage
+  static void step(const fr_solver *s, T *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
     static const double cA[4] = {0.5, 0.5, 1.0, 0.0};
     static const double cB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     if (sample) probe(s, u, st);
-    interp(s, u, (T *)s->uf, st);
+    if (fresh) interp(s, u, (T *)s->uf, st);
     for (int k = 0; k < 4; ++k) {
       RKArgs<T> rk{};
       rk.u0 = u;
@@ -882,7 +905,7 @@ struct Engine {
       rk.cB = (T)cB[k];
       rk.first = k == 0;
       rk.last = k == 3;
-      rk.uf_next = k < 3 ? (T *)s->uf : nullptr;
+      rk.uf_next = (T *)s->uf;
       const T *ust = k == 0 ? u : (const T *)s->ustage;
       stage(s, ust, rk, st, sample && k == 0);
     }
@@ -892,7 +915,7 @@ struct Engine {
 // ------------------------------------------------------------------------------------ dispatch
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
-  void (*step)(const fr_solver *, void *, const double *, bool, hipStream_t);
+  void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
 };
 
 template <int D, int P, typename T>
@@ -901,8 +924,8 @@ Dispatch make_dispatch() {
   d.rhs = [](const fr_solver *s, const void *u, void *r, hipStream_t st) {
     Engine<D, P, T>::rhs(s, (const T *)u, (T *)r, st);
   };
-  d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, hipStream_t st) {
-    Engine<D, P, T>::step(s, (T *)u, dt, sample, st);
+  d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
+    Engine<D, P, T>::step(s, (T *)u, dt, sample, fresh, st);
   };
   return d;
 }

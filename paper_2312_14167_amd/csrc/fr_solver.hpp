@@ -49,9 +49,9 @@ struct fr_solver {
   // device arrays (precision T unless noted)
   void *metric = nullptr;   // [Ne][dim*dim+1][Ns]
   void *uf = nullptr;       // [Ne][NV][Nf]
-  void *du = nullptr;       // [Ne][NV][Nf]   (NS)
-  void *gradf = nullptr;    // [Ne][dim][NV][Nf] (NS)
-  void *vol = nullptr;      // [Ne][NV][Ns]   (NS)
+  void *fvn = nullptr;      // [Ne][NV][Nf]   viscous normal flux at own flux points (NS)
+  void *vol = nullptr;      // [Ne][NV][Ns]   volume divergence (NS)
+  void *fnrm = nullptr;     // [Ne][dim][Nf]  outward unit normal at own flux points
   void *fhat = nullptr;     // [Ne][NV][Nf]
   void *acc = nullptr;      // [Ne][NV][Ns]
   void *ustage = nullptr;   // [Ne][NV][Ns]
@@ -59,6 +59,7 @@ struct fr_solver {
   void *bnd_nrm = nullptr;  // [nbnd][dim+1]
   void *flow = nullptr;     // FlowDev<T>[n_mesh]
   int32_t *pairL = nullptr, *pairR = nullptr, *bnd = nullptr, *elem_mesh = nullptr;
+  int32_t *nbr = nullptr;   // [Ne][Nf] neighbour code of every own flux point
   int64_t npair = 0, nbnd = 0, n_wall = 0;
   double *bnd_w = nullptr;          // FP64 [nbnd]
   int64_t *wall_mesh_begin = nullptr;  // device [n_mesh+1]
@@ -77,9 +78,9 @@ struct fr_solver {
   // time stepping / graphs
   int64_t steps_since_reset = 0;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  void *graph_u[2] = {nullptr, nullptr};
-  const double *graph_dt[2] = {nullptr, nullptr};
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // (sample, fresh u_f) variants
+  void *graph_u[4] = {nullptr, nullptr, nullptr, nullptr};
+  const double *graph_dt[4] = {nullptr, nullptr, nullptr, nullptr};
   int use_graphs = 1;
 
   // per-kernel event timing (FR_K_* ids)
