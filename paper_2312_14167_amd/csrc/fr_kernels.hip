@@ -149,6 +149,48 @@ __device__ __forceinline__ void fvis_dot(const Visc<D, T> &o, const T *m, T *out
   out[D + 1] = en;
 }
 
+// viscous normal flux F_vis(st, grad) . n with the flux-point gradient produced one derivative
+// direction at a time (grad_d(v) = gdir(d, v)); keeps 8 accumulators instead of the full
+// gradient and stress tensor:
+//   (tau n)_i = mu (sum_j d_j v_i n_j + sum_j d_i v_j n_j - 2/3 div n_i),
+//   energy    = v . (tau n) + kappa d_n(p/rho)   (zero heat flux when !heat)
+template <int D, typename T, class G>
+__device__ __forceinline__ void fvis_normal_stream(const T *st, const G &gdir, const T *n, T mu,
+                                                   const PhysDev<T> &ph, bool heat, T *fv) {
+  constexpr int NV = D + 2;
+  const T ir = T(1) / st[0];
+  const T Es = st[D + 1] * ir;
+  T vel[D], dvn[D], dvT[D];
+  for (int m = 0; m < D; ++m) { vel[m] = st[1 + m] * ir; dvn[m] = T(0); }
+  T div = T(0), dthn = T(0);
+#pragma unroll 1
+  for (int d = 0; d < D; ++d) {
+    T gd[NV];
+    for (int v = 0; v < NV; ++v) gd[v] = gdir(d, v);
+    T sv = T(0), tn = T(0);
+    for (int m = 0; m < D; ++m) {
+      const T dvdm = (gd[1 + m] - vel[m] * gd[0]) * ir;  // d_d v_m
+      sv += vel[m] * dvdm;
+      dvn[m] += dvdm * n[d];
+      tn += dvdm * n[m];
+      if (m == d) div += dvdm;
+    }
+    dvT[d] = tn;
+    const T dth = ph.gm1 * ((gd[D + 1] - Es * gd[0]) * ir - sv);
+    dthn += dth * n[d];
+  }
+  const T c23 = T(2) / T(3);
+  T en = T(0);
+  fv[0] = T(0);
+  for (int i = 0; i < D; ++i) {
+    const T t = mu * (dvn[i] + dvT[i] - c23 * div * n[i]);
+    fv[1 + i] = t;
+    en += vel[i] * t;
+  }
+  const T kappa = heat ? mu * ph.gamma / (ph.prandtl * ph.gm1) : T(0);
+  fv[D + 1] = en + kappa * dthn;
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void rusanov(const T *uL, const T *uR, const T *n, T gamma, T gm1, T *F) {
   constexpr int NV = D + 2;
@@ -214,6 +256,16 @@ __global__ __launch_bounds__(256) void k_interp(const T *__restrict__ u, T *__re
     for (int a = 0; a < P; ++a) s += lv[a] * ue[a * stride];
     uf[(e * S::NV + v) * S::Nf + fp] = s;
   }
+}
+
+// operator tables staged in LDS: per-lane dynamic indexing into them is an LDS read instead of
+// a register-resident copy of every coefficient
+template <typename T, int P>
+__device__ __forceinline__ void stage_ops(OpsDev<T, P> &dst, const OpsDev<T, P> &src) {
+  constexpr int n = (int)(sizeof(OpsDev<T, P>) / sizeof(T));
+  const T *s = reinterpret_cast<const T *>(&src);
+  T *d = reinterpret_cast<T *>(&dst);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) d[k] = s[k];
 }
 
 // contiguous tile copy global -> LDS, 16-byte vector accesses when both sides allow it
@@ -344,12 +396,14 @@ template <int D, int P, typename T>
 __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
-    const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops, PhysDev<T> ph, T *__restrict__ fvn,
+    const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, T *__restrict__ fvn,
     T *__restrict__ vol, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = GradTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
+  __shared__ OpsDev<T, P> ops;
+  stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
   T *lu = lds;                   // [E][NV][Ns]
@@ -399,13 +453,18 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
   const int64_t e = e0 + el;
-  T uv[NV], Sm[D][D], gx[D][NV];
+  // per solution point: corrected gradient, then the transformed flux right away, so that only
+  // F~ (dim x nv values) stays live through the flux-point phase below
+  T ft[D][NV];
+  T gx[D][NV];
   if (act) {
+    T Sm[D][D];
     for (int k = 0; k < D; ++k)
       for (int j = 0; j < D; ++j) Sm[k][j] = metric[(e * NM + k * D + j) * Ns + i];
     const T invJ = metric[(e * NM + D * D) * Ns + i];
-    for (int v = 0; v < NV; ++v) uv[v] = lu[(el * NV + v) * Ns + i];
-    T gr[D][NV];
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) gx[j][v] = T(0);
+#pragma unroll 1
     for (int k = 0; k < D; ++k) {
       int base, stride, ik, t;
       line_of_sol<D, P>(i, k, base, stride, ik, t);
@@ -417,15 +476,21 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
         for (int a = 0; a < P; ++a) s += ops.D[ik * P + a] * lin[a * stride];
         const T *ld = ldu + (el * NV + v) * Nf;
         s += cm * ld[(2 * k) * Nfp + t] + cp * ld[(2 * k + 1) * Nfp + t];
-        gr[k][v] = s;
+        for (int j = 0; j < D; ++j) gx[j][v] += Sm[k][j] * s;
       }
     }
     for (int j = 0; j < D; ++j)
-      for (int v = 0; v < NV; ++v) {
-        T s = T(0);
-        for (int k = 0; k < D; ++k) s += Sm[k][j] * gr[k][v];
-        gx[j][v] = invJ * s;
-      }
+      for (int v = 0; v < NV; ++v) gx[j][v] *= invJ;
+    T uv[NV];
+    for (int v = 0; v < NV; ++v) uv[v] = lu[(el * NV + v) * Ns + i];
+    Visc<D, T> vs;
+    visc_state<D>(uv, &gx[0][0], flow[elem_mesh[e]].mu, ph, true, vs);
+    for (int k = 0; k < D; ++k) {
+      T fi[NV], fv[NV];
+      finv_dot<D>(uv, Sm[k], ph.gm1, fi);
+      fvis_dot<D>(vs, Sm[k], fv);
+      for (int v = 0; v < NV; ++v) ft[k][v] = fi[v] - fv[v];
+    }
   }
   __syncthreads();
   T *lg = lds;  // [E][D][NV][Ns]
@@ -440,15 +505,7 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     int base, stride, side;
     line_of_fpt<D, P>(fp, base, stride, side);
     const T *lv = side ? ops.lp : ops.lm;
-    T g[D * NV], st[NV], n[D];
-    for (int j = 0; j < D; ++j)
-      for (int v = 0; v < NV; ++v) {
-        const T *lin = lg + ((elf * D + j) * NV + v) * Ns + base;
-        T s = T(0);
-#pragma unroll
-        for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-        g[j * NV + v] = s;
-      }
+    T st[NV], n[D];
     for (int v = 0; v < NV; ++v) st[v] = luf[(elf * NV + v) * Nf + fp];
     for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * D + j) * Nf + fp];
     const int32_t code = nbr[ef * Nf + fp];
@@ -464,26 +521,17 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
       }
       for (int v = 0; v < NV; ++v) st[v] = ub[v];
     }
-    Visc<D, T> vs;
+    const T *lge = lg + elf * D * NV * Ns + base;
+    auto gdir = [&](int d, int v) {
+      const T *lin = lge + (d * NV + v) * Ns;
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+      return s;
+    };
     T fv[NV];
-    visc_state<D>(st, g, flow[elem_mesh[ef]].mu, ph, heat, vs);
-    fvis_dot<D>(vs, n, fv);
+    fvis_normal_stream<D>(st, gdir, n, flow[elem_mesh[ef]].mu, ph, heat, fv);
     for (int v = 0; v < NV; ++v) fvn[(ef * NV + v) * Nf + fp] = fv[v];
-  }
-  // transformed flux F~_k = S_k . (F_inv - F_vis) at this solution point
-  T ft[D][NV];
-  if (act) {
-    Visc<D, T> vs;
-    T gflat[D * NV];
-    for (int j = 0; j < D; ++j)
-      for (int v = 0; v < NV; ++v) gflat[j * NV + v] = gx[j][v];
-    visc_state<D>(uv, gflat, flow[elem_mesh[e]].mu, ph, true, vs);
-    for (int k = 0; k < D; ++k) {
-      T fi[NV], fv[NV];
-      finv_dot<D>(uv, Sm[k], ph.gm1, fi);
-      fvis_dot<D>(vs, Sm[k], fv);
-      for (int v = 0; v < NV; ++v) ft[k][v] = fi[v] - fv[v];
-    }
   }
   __syncthreads();
   if (act)
@@ -493,6 +541,7 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
   if (act) {
     for (int v = 0; v < NV; ++v) {
       T accv = T(0);
+#pragma unroll 1
       for (int k = 0; k < D; ++k) {
         int base, stride, ik, t;
         line_of_sol<D, P>(i, k, base, stride, ik, t);
@@ -574,11 +623,13 @@ template <int D, int P, typename T>
 __global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_div_rk(const T *__restrict__ vol, const T *__restrict__ fhat,
                                                                 const T *__restrict__ metric,
                                                                 const int32_t *__restrict__ elem_mesh,
-                                                                OpsDev<T, P> ops, RKArgs<T> rk, int64_t Ne) {
+                                                                OpsDev<T, P> ops_arg, RKArgs<T> rk, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = DivTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
+  __shared__ OpsDev<T, P> ops;
+  stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
   tile_load(lds, fhat + e0 * NV * Nf, ne * NV * Nf);
@@ -618,11 +669,13 @@ template <int D, int P, typename T>
 __global__ __launch_bounds__((EulerTile<D, P, T>::BS)) void k_euler_vol_rk(
     const T *u,  // may alias rk.ustage: every thread reads its own point before writing it
     const T *__restrict__ fhat, const T *__restrict__ metric,
-    const int32_t *__restrict__ elem_mesh, OpsDev<T, P> ops, PhysDev<T> ph, RKArgs<T> rk, int64_t Ne) {
+    const int32_t *__restrict__ elem_mesh, OpsDev<T, P> ops_arg, PhysDev<T> ph, RKArgs<T> rk, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = EulerTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
+  __shared__ OpsDev<T, P> ops;
+  stage_ops(ops, ops_arg);
   T *lF = lds;                  // [E][D][NV][Ns]
   T *lf = lds + E * D * NV * Ns;  // [E][NV][Nf]
   const int64_t e0 = (int64_t)blockIdx.x * E;
@@ -649,6 +702,7 @@ __global__ __launch_bounds__((EulerTile<D, P, T>::BS)) void k_euler_vol_rk(
     T R[NV];
     for (int v = 0; v < NV; ++v) {
       T accv = T(0);
+#pragma unroll 1
       for (int k = 0; k < D; ++k) {
         int base, stride, ik, t;
         line_of_sol<D, P>(i, k, base, stride, ik, t);
