@@ -143,9 +143,12 @@ fr_status fr_probe_series(fr_solver *s, double *series, int64_t cap, int64_t *n,
 /* Zero the sample counter, probe sums / series and force sums (kernel fill, graph safe). */
 fr_status fr_reset_accumulators(fr_solver *s, void *stream);
 
-/* Vector-Jacobian product of fr_rhs: u_bar += (dR/du)^T r_bar (device state arrays, same
- * dtype as the state).  x_bar: device FP64 [n_node][dim] accumulating the sensitivity to
- * the mesh node coordinates, or NULL.  Returns FR_ERR_UNSUPPORTED for forms not built. */
+/* Vector-Jacobian product of fr_rhs (the adjoint of the residual at state u):
+ * u_bar += (dR/du)^T r_bar.  u, r_bar, u_bar: device state arrays of the solver's dtype;
+ * u_bar may not alias u or r_bar.  Overwrites the solver's flux-point work arrays (later
+ * fr_rhs / fr_rk_step calls recompute them); allocates an adjoint work area on first use.
+ * x_bar (sensitivity to the mesh node coordinates) must be NULL: FR_ERR_UNSUPPORTED
+ * otherwise. */
 fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream);
 
 /* Counts of the discretisation: info[0..7] = {n_elem, nv, Ns, Nf, n_face_pairs (interior and

@@ -67,6 +67,27 @@ def viscous_flux(u, gu, mu, gamma, prandtl, heat: bool = True):
     return torch.cat([zero[..., None, :], tau, energy[..., None, :]], dim=-2)
 
 
+TIE_RTOL = 1e-12
+
+
+class _TieAveragedMax(torch.autograd.Function):
+    """max(a, b) whose derivative is the average of both one-sided derivatives when a and b agree
+    to a relative 1e-12 (a kink: any convex combination is a valid derivative; averaging makes
+    the choice insensitive to round-off), and that of the larger argument otherwise."""
+
+    @staticmethod
+    def forward(ctx, a, b):
+        ctx.save_for_backward(a, b)
+        return torch.maximum(a, b)
+
+    @staticmethod
+    def backward(ctx, g):
+        a, b = ctx.saved_tensors
+        tie = (a - b).abs() <= TIE_RTOL * torch.maximum(a.abs(), b.abs())
+        wa = torch.where(tie, torch.full_like(a, 0.5), (a > b).to(a.dtype))
+        return g * wa, g * (1.0 - wa)
+
+
 def rusanov(uL, uR, n, gamma):
     """Rusanov common normal flux 1/2 (F(uL) + F(uR)).n - 1/2 lambda (uR - uL),
     lambda = max(|v_L.n| + c_L, |v_R.n| + c_R)."""
@@ -76,7 +97,7 @@ def rusanov(uL, uR, n, gamma):
     rR, vR, pR = primitives(uR, gamma)
     aL = (vL * n).sum(-1).abs() + torch.sqrt(gamma * pL / rL)
     aR = (vR * n).sum(-1).abs() + torch.sqrt(gamma * pR / rR)
-    lam = torch.maximum(aL, aR)
+    lam = _TieAveragedMax.apply(aL, aR)
     return 0.5 * (fL + fR) - 0.5 * lam[..., None] * (uR - uL)
 
 

@@ -19,6 +19,8 @@ struct Dispatch {
 bool get_dispatch(int dim, int p, int precision, Dispatch &out);
 void launch_fill(double *p, int64_t n, double v, hipStream_t st);
 void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st);
+size_t vjp_work_elems(const fr_solver *s);
+bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, hipStream_t st);
 }  // namespace frmi
 
 using namespace frmi;
@@ -407,10 +409,22 @@ fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl
 }
 
 fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream) {
-  (void)stream;
-  (void)x_bar;
   if (!s || !u || !r_bar || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
-  return fail(FR_ERR_UNSUPPORTED, "the vector-Jacobian product is not built for this form");
+  if (u_bar == u || u_bar == r_bar) return fail(FR_ERR_ARG, "u_bar must not alias u or r_bar");
+  if (x_bar) return fail(FR_ERR_UNSUPPORTED, "mesh-node sensitivities (x_bar) are not built; pass NULL");
+  try {
+    const size_t need = vjp_work_elems(s) * s->tsize;
+    if (!s->vjp_work || s->vjp_bytes < need) {
+      s->vjp_work = dalloc(s, need);  // kept until fr_destroy
+      s->vjp_bytes = need;
+    }
+    if (!launch_vjp(s, u, r_bar, u_bar, s->vjp_work, (hipStream_t)stream))
+      throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+    HIP_OK(hipGetLastError());
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
 }
 
 fr_status fr_solver_info(const fr_solver *s, int64_t info[8]) {

@@ -1,0 +1,844 @@
+// Vector-Jacobian product of the FR residual: u_bar += (dR/du)^T r_bar, hand-derived, for the
+// Euler and Navier-Stokes forms in 2-D and 3-D.  The residual (Eqs. (1)-(7) discretised by FR) is
+//   R = -(1/J) [ vol + Lift F^ ],  vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}),
+// with F~_k = S_k . (F_inv(u) - F_vis(u, grad u)) and F^ the common normal flux.  Its adjoint runs
+// the pipeline backwards:
+//   vjp_div    w = -(1/J) r_bar;  vol_bar = w;  F^_bar = Lift^T w                  (element local)
+//   vjp_face   Rusanov / LDG / boundary adjoints -> u_f_bar (both sides), fvn_bar   (per flux point)
+//   vjp_vol    recompute u_f, u^, grad u, F~ in LDS; F~_bar = (D_k - Lift s M0)^T vol_bar;
+//              pointwise flux adjoints -> u_bar, grad_bar; fvn adjoint at flux points; transposed
+//              corrected gradient -> u_bar, (u^ - u_f)_bar -> own / neighbour u_f_bar
+//   vjp_final  u_bar += u_vol_bar + M0^T (u_f_bar own + neighbour)
+// Kink conventions: |x| has derivative 0 at 0; max(a_L, a_R) of the Rusanov speed sends its
+// adjoint to the larger side, and half to each side when the two agree to a relative 1e-12.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fr_device.hpp"
+
+namespace frmi {
+
+// ------------------------------------------------------------------------------------ pointwise adjoints
+template <int D, typename T>
+__device__ __forceinline__ void pressure_grad(const T *u, T gm1, T &p, T *dp) {
+  const T r = T(1) / u[0];
+  T m2 = T(0);
+  for (int j = 0; j < D; ++j) m2 += u[1 + j] * u[1 + j];
+  p = gm1 * (u[D + 1] - T(0.5) * m2 * r);
+  dp[0] = gm1 * T(0.5) * m2 * r * r;
+  for (int j = 0; j < D; ++j) dp[1 + j] = -gm1 * u[1 + j] * r;
+  dp[D + 1] = gm1;
+}
+
+// ub += (d (F_inv(u) . m) / du)^T fb
+template <int D, typename T>
+__device__ __forceinline__ void finv_dot_vjp(const T *u, const T *m, T gm1, const T *fb, T *ub) {
+  constexpr int NV = D + 2;
+  T p, dp[NV];
+  pressure_grad<D>(u, gm1, p, dp);
+  const T r = T(1) / u[0];
+  T a = T(0);
+  for (int j = 0; j < D; ++j) a += u[1 + j] * m[j];
+  const T ar = a * r, H = u[D + 1] + p;
+  T Pb = fb[D + 1] * ar, q = T(0);
+  for (int i = 0; i < D; ++i) {
+    Pb += fb[1 + i] * m[i];
+    q += fb[1 + i] * u[1 + i];
+  }
+  const T arb = q + fb[D + 1] * H;
+  ub[0] += arb * (-a * r * r) + Pb * dp[0];
+  for (int j = 0; j < D; ++j) ub[1 + j] += fb[0] * m[j] + fb[1 + j] * ar + arb * m[j] * r + Pb * dp[1 + j];
+  ub[D + 1] += fb[D + 1] * ar + Pb * dp[D + 1];
+}
+
+// ub += ab * d(|v.n| + c)/du
+template <int D, typename T>
+__device__ __forceinline__ void wavespeed_vjp(const T *u, const T *n, T gamma, T gm1, T ab, T *ub) {
+  constexpr int NV = D + 2;
+  T p, dp[NV];
+  pressure_grad<D>(u, gm1, p, dp);
+  const T r = T(1) / u[0];
+  T vn = T(0);
+  for (int j = 0; j < D; ++j) vn += u[1 + j] * n[j];
+  vn *= r;
+  const T sg = vn > T(0) ? T(1) : (vn < T(0) ? T(-1) : T(0));
+  const T c = sqrt(gamma * p * r);
+  const T cf = ab * gamma / (T(2) * c);
+  ub[0] += ab * sg * (-vn * r) + cf * (dp[0] * r - p * r * r);
+  for (int j = 0; j < D; ++j) ub[1 + j] += ab * sg * n[j] * r + cf * dp[1 + j] * r;
+  ub[D + 1] += cf * dp[D + 1] * r;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ T wavespeed(const T *u, const T *n, T gamma, T gm1) {
+  T rho, v[D], p;
+  primitives<D>(u, gm1, rho, v, p);
+  T vn = T(0);
+  for (int j = 0; j < D; ++j) vn += v[j] * n[j];
+  return fabs(vn) + sqrt(gamma * p / rho);
+}
+
+// adjoint of rusanov(): uLb += (dF/duL)^T Fb, uRb += (dF/duR)^T Fb
+template <int D, typename T>
+__device__ __forceinline__ void rusanov_vjp(const T *uL, const T *uR, const T *n, T gamma, T gm1, const T *Fb,
+                                            T *uLb, T *uRb) {
+  constexpr int NV = D + 2;
+  T hb[NV];
+  for (int v = 0; v < NV; ++v) hb[v] = T(0.5) * Fb[v];
+  finv_dot_vjp<D>(uL, n, gm1, hb, uLb);
+  finv_dot_vjp<D>(uR, n, gm1, hb, uRb);
+  const T aL = wavespeed<D>(uL, n, gamma, gm1), aR = wavespeed<D>(uR, n, gamma, gm1);
+  const T lam = aL >= aR ? aL : aR;
+  T lamb = T(0);
+  for (int v = 0; v < NV; ++v) {
+    uLb[v] += T(0.5) * lam * Fb[v];
+    uRb[v] -= T(0.5) * lam * Fb[v];
+    lamb -= T(0.5) * Fb[v] * (uR[v] - uL[v]);
+  }
+  // max(aL, aR): the larger side, or half to each when they agree to a relative 1e-12 (FP64) /
+  // 1e-5 (FP32), so that round-off cannot flip the side of the kink
+  const T tol = (sizeof(T) == 8 ? T(1e-12) : T(1e-5)) * (aL >= aR ? aL : aR);
+  if (aL - aR > tol)
+    wavespeed_vjp<D>(uL, n, gamma, gm1, lamb, uLb);
+  else if (aR - aL > tol)
+    wavespeed_vjp<D>(uR, n, gamma, gm1, lamb, uRb);
+  else {
+    wavespeed_vjp<D>(uL, n, gamma, gm1, T(0.5) * lamb, uLb);
+    wavespeed_vjp<D>(uR, n, gamma, gm1, T(0.5) * lamb, uRb);
+  }
+}
+
+// adjoint of the viscous flux F_vis(st, g) . m with the conserved gradient g[d * NV + v]
+template <int D, typename T>
+__device__ __forceinline__ void fvis_vjp(const T *st, const T *g, const T *m, T mu, const PhysDev<T> &ph, bool heat,
+                                         const T *fb, T *stb, T *gb) {
+  constexpr int NV = D + 2;
+  const T r = T(1) / st[0];
+  const T Es = st[D + 1] * r;
+  T vel[D], dv[D][D];
+  for (int i = 0; i < D; ++i) vel[i] = st[1 + i] * r;
+  for (int d = 0; d < D; ++d)
+    for (int i = 0; i < D; ++i) dv[i][d] = (g[d * NV + 1 + i] - vel[i] * g[d * NV]) * r;
+  T div = T(0);
+  for (int i = 0; i < D; ++i) div += dv[i][i];
+  const T c23 = T(2) / T(3);
+  T tn[D];
+  for (int i = 0; i < D; ++i) {
+    T s = T(0);
+    for (int d = 0; d < D; ++d) s += (dv[i][d] + dv[d][i]) * m[d];
+    tn[i] = mu * (s - c23 * div * m[i]);
+  }
+  const T kappa = heat ? mu * ph.gamma / (ph.prandtl * ph.gm1) : T(0);
+  T tb[D], vb[D];
+  T tm = T(0);
+  for (int i = 0; i < D; ++i) {
+    tb[i] = fb[1 + i] + fb[D + 1] * vel[i];
+    vb[i] = fb[D + 1] * tn[i];
+    tm += tb[i] * m[i];
+  }
+  T rb = T(0), Esb = T(0);
+  for (int d = 0; d < D; ++d) {
+    // d_theta_d = gm1 ((g_dE - Es g_d0) r - sum_i v_i dv_id)
+    const T x = fb[D + 1] * kappa * m[d] * ph.gm1;
+    gb[d * NV + D + 1] += x * r;
+    gb[d * NV] -= x * Es * r;
+    Esb -= x * g[d * NV] * r;
+    rb += x * (g[d * NV + D + 1] - Es * g[d * NV]);
+    for (int i = 0; i < D; ++i) {
+      // dv_id adjoint: stress part minus the heat-flux part
+      const T y = mu * (tb[i] * m[d] + tb[d] * m[i] - (i == d ? c23 * tm : T(0))) - x * vel[i];
+      vb[i] -= x * dv[i][d];
+      gb[d * NV + 1 + i] += y * r;
+      gb[d * NV] -= y * vel[i] * r;
+      vb[i] -= y * g[d * NV] * r;
+      rb += y * (g[d * NV + 1 + i] - vel[i] * g[d * NV]);
+    }
+  }
+  for (int i = 0; i < D; ++i) {
+    stb[1 + i] += vb[i] * r;
+    rb += vb[i] * st[1 + i];
+  }
+  stb[D + 1] += Esb * r;
+  rb += Esb * st[D + 1];
+  stb[0] -= rb * r * r;
+}
+
+// adjoint of farfield(): uLb += (d ub / d uL)^T ubb
+template <int D, typename T>
+__device__ __forceinline__ void farfield_vjp(const T *uL, const T *n, const FlowDev<T> &fl, T gamma, T gm1,
+                                             const T *ubb, T *uLb) {
+  // forward recompute
+  const T rL = uL[0];
+  T vL[D], m2 = T(0);
+  for (int j = 0; j < D; ++j) {
+    vL[j] = uL[1 + j] / rL;
+    m2 += uL[1 + j] * uL[1 + j];
+  }
+  const T pL = gm1 * (uL[D + 1] - T(0.5) * m2 / rL);
+  const T cL = sqrt(gamma * pL / rL);
+  const T ci = sqrt(gamma * fl.p / fl.rho);
+  T vnL = T(0), vni = T(0);
+  for (int j = 0; j < D; ++j) { vnL += vL[j] * n[j]; vni += fl.v[j] * n[j]; }
+  const T Rp = vnL + T(2) * cL / gm1;
+  const T Rm = vni - T(2) * ci / gm1;
+  const T vn = T(0.5) * (Rp + Rm);
+  const T c = T(0.25) * gm1 * (Rp - Rm);
+  const bool out = vn > T(0);
+  const T s = out ? pL / pow(rL, gamma) : fl.p / pow(fl.rho, gamma);
+  const T X = c * c / (gamma * s);
+  const T rho = pow(X, T(1) / gm1);
+  T v[D], v2 = T(0);
+  for (int j = 0; j < D; ++j) {
+    const T vt = out ? vL[j] - vnL * n[j] : fl.v[j] - vni * n[j];
+    v[j] = vt + vn * n[j];
+    v2 += v[j] * v[j];
+  }
+  // reverse
+  T rhob = ubb[0] + T(0.5) * v2 * ubb[D + 1];
+  T vb[D];
+  for (int j = 0; j < D; ++j) {
+    rhob += ubb[1 + j] * v[j];
+    vb[j] = ubb[1 + j] * rho + ubb[D + 1] * rho * v[j];
+  }
+  const T pb = ubb[D + 1] / gm1;
+  rhob += pb * c * c / gamma;
+  T cb = pb * T(2) * rho * c / gamma;
+  const T Xb = rhob * rho / (gm1 * X);
+  cb += Xb * T(2) * c / (gamma * s);
+  const T sb = -Xb * X / s;
+  T vnb = T(0);
+  for (int j = 0; j < D; ++j) vnb += vb[j] * n[j];
+  const T Rpb = T(0.5) * vnb + T(0.25) * gm1 * cb;
+  T vnLb = Rpb;
+  T cLb = T(2) * Rpb / gm1;
+  T vLb[D];
+  T pLb = T(0), rLb = T(0);
+  for (int j = 0; j < D; ++j) vLb[j] = T(0);
+  if (out) {
+    T tdot = T(0);
+    for (int j = 0; j < D; ++j) {
+      vLb[j] += vb[j];
+      tdot += vb[j] * n[j];
+    }
+    vnLb -= tdot;
+    const T rg = pow(rL, gamma);
+    pLb += sb / rg;
+    rLb -= gamma * sb * pL / (rg * rL);
+  }
+  for (int j = 0; j < D; ++j) vLb[j] += vnLb * n[j];
+  pLb += cLb * gamma / (T(2) * cL * rL);
+  rLb -= cLb * gamma * pL / (T(2) * cL * rL * rL);
+  for (int j = 0; j < D; ++j) {
+    uLb[1 + j] += vLb[j] / rL - gm1 * pLb * uL[1 + j] / rL;
+    rLb -= vLb[j] * uL[1 + j] / (rL * rL);
+  }
+  uLb[D + 1] += gm1 * pLb;
+  rLb += gm1 * pLb * T(0.5) * m2 / (rL * rL);
+  uLb[0] += rLb;
+}
+
+// adjoint of wall_state() (zero velocity, same density and internal energy)
+template <int D, typename T>
+__device__ __forceinline__ void wall_state_vjp(const T *uB, const T *wb, T *uBb) {
+  const T r = T(1) / uB[0];
+  T m2 = T(0);
+  for (int j = 0; j < D; ++j) m2 += uB[1 + j] * uB[1 + j];
+  uBb[0] += wb[0] + wb[D + 1] * T(0.5) * m2 * r * r;
+  for (int j = 0; j < D; ++j) uBb[1 + j] -= wb[D + 1] * uB[1 + j] * r;
+  uBb[D + 1] += wb[D + 1];
+}
+
+// ------------------------------------------------------------------------------------ kernels
+// u_f = M0 u (forward values at the linearisation point)
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_vjp_interp(const T *__restrict__ u, T *__restrict__ uf, OpsDev<T, P> ops,
+                                                    int64_t Ne) {
+  using S = Shape<D, P>;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Ne * S::Nf) return;
+  const int64_t e = gid / S::Nf;
+  const int fp = (int)(gid % S::Nf);
+  int base, stride, side;
+  line_of_fpt<D, P>(fp, base, stride, side);
+  const T *lv = side ? ops.lp : ops.lm;
+  for (int v = 0; v < S::NV; ++v) {
+    const T *ue = u + (e * S::NV + v) * S::Ns + base;
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) s += lv[a] * ue[a * stride];
+    uf[(e * S::NV + v) * S::Nf + fp] = s;
+  }
+}
+
+template <int D, int P, typename T>
+struct VjpDivTile {
+  using S = Shape<D, P>;
+  static constexpr int LE = S::NV * S::Ns;
+  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int BS = round64(E * S::Ns);
+};
+
+// w = -(1/J) r_bar -> vol_bar (solution points) and F^_bar = Lift^T w (flux points)
+template <int D, int P, typename T>
+__global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *__restrict__ rbar,
+                                                                       const T *__restrict__ metric,
+                                                                       OpsDev<T, P> ops_arg, T *__restrict__ volbar,
+                                                                       T *__restrict__ fhatbar, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = VjpDivTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, NV = S::NV, NM = S::NM;
+  __shared__ __attribute__((aligned(16))) T lw[E * TL::LE];
+  __shared__ OpsDev<T, P> ops;
+  stage_ops(ops, ops_arg);
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  if (el < ne) {
+    const int64_t e = e0 + el;
+    const T invJ = metric[(e * NM + D * D) * Ns + i];
+    for (int v = 0; v < NV; ++v) {
+      const T w = -invJ * rbar[(e * NV + v) * Ns + i];
+      lw[(el * NV + v) * Ns + i] = w;
+      volbar[(e * NV + v) * Ns + i] = w;
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) {
+    const int fp = idx % Nf, rest = idx / Nf;
+    int base, stride, side;
+    line_of_fpt<D, P>(fp, base, stride, side);
+    const T *g = side ? ops.gp : ops.gm;
+    const T *lin = lw + rest * Ns + base;
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) s += g[a] * lin[a * stride];
+    fhatbar[e0 * NV * Nf + idx] = s;
+  }
+}
+
+// adjoint of the common-flux kernel: u_f_bar of both sides and (NS) the viscous-normal-flux adjoints
+template <int D, int P, typename T, bool NS>
+__global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, const T *__restrict__ fhatbar,
+                                                  const int32_t *__restrict__ pairL, const int32_t *__restrict__ pairR,
+                                                  const T *__restrict__ pnrm, int64_t npair,
+                                                  const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
+                                                  int64_t n_wall, int64_t nbnd, const int32_t *__restrict__ elem_mesh,
+                                                  const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
+                                                  T *__restrict__ ufbar, T *__restrict__ fvnbar) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Nf = S::Nf;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < npair) {
+    const int32_t cL = pairL[gid], cR = pairR[gid];
+    const int64_t eL = cL / Nf, eR = cR / Nf;
+    const int fL = cL % Nf, fR = cR % Nf;
+    T uL[NV], uR[NV], n[D], Fb[NV], uLb[NV], uRb[NV];
+    for (int j = 0; j < D; ++j) n[j] = pnrm[gid * (D + 1) + j];
+    const T mag = pnrm[gid * (D + 1) + D];
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = uf[(eL * NV + v) * Nf + fL];
+      uR[v] = uf[(eR * NV + v) * Nf + fR];
+      Fb[v] = mag * (fhatbar[(eL * NV + v) * Nf + fL] - fhatbar[(eR * NV + v) * Nf + fR]);
+      uLb[v] = T(0);
+      uRb[v] = T(0);
+    }
+    rusanov_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, uLb, uRb);
+    if (NS) {
+      const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
+      for (int v = 0; v < NV; ++v) {
+        uLb[v] += ph.tau * Fb[v];
+        uRb[v] -= ph.tau * Fb[v];
+        fvnbar[(eL * NV + v) * Nf + fL] = -wl * Fb[v];
+        fvnbar[(eR * NV + v) * Nf + fR] = wr * Fb[v];
+      }
+    }
+    for (int v = 0; v < NV; ++v) {
+      ufbar[(eL * NV + v) * Nf + fL] = uLb[v];
+      ufbar[(eR * NV + v) * Nf + fR] = uRb[v];
+    }
+  } else if (gid < npair + nbnd) {
+    const int64_t b = gid - npair;
+    const int32_t c = bnd[b];
+    const int64_t e = c / Nf;
+    const int fp = c % Nf;
+    T uB[NV], ug[NV], n[D], Fb[NV], uBb[NV], ugb[NV];
+    for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+    const T mag = bnrm[b * (D + 1) + D];
+    for (int v = 0; v < NV; ++v) {
+      uB[v] = uf[(e * NV + v) * Nf + fp];
+      Fb[v] = mag * fhatbar[(e * NV + v) * Nf + fp];
+      uBb[v] = T(0);
+      ugb[v] = T(0);
+    }
+    const bool wall = b < n_wall;
+    const FlowDev<T> fl = flow[elem_mesh[e]];
+    if (wall) {
+      ug[0] = uB[0];
+      for (int j = 0; j < D; ++j) ug[1 + j] = -uB[1 + j];
+      ug[D + 1] = uB[D + 1];
+    } else {
+      farfield<D>(uB, n, fl, ph.gamma, ph.gm1, ug);
+    }
+    rusanov_vjp<D>(uB, ug, n, ph.gamma, ph.gm1, Fb, uBb, ugb);
+    if (wall) {
+      uBb[0] += ugb[0];
+      for (int j = 0; j < D; ++j) uBb[1 + j] -= ugb[1 + j];
+      uBb[D + 1] += ugb[D + 1];
+    } else {
+      farfield_vjp<D>(uB, n, fl, ph.gamma, ph.gm1, ugb, uBb);
+    }
+    for (int v = 0; v < NV; ++v) {
+      ufbar[(e * NV + v) * Nf + fp] = uBb[v];
+      if (NS) fvnbar[(e * NV + v) * Nf + fp] = -Fb[v];
+    }
+  }
+}
+
+template <int D, int P, typename T>
+struct VjpVolTile {
+  using S = Shape<D, P>;
+  // A: u + (u^ - u_f) | gradient | flux-point gradient adjoint | reference-gradient adjoint
+  static constexpr int LA = cmax(cmax(S::NV * S::Ns + S::NV * S::Nf, D * S::NV * S::Ns), D * S::NV * S::Nf);
+  // + own u_f + vol_bar + own u_f adjoint
+  static constexpr int LE = LA + S::NV * S::Nf + S::NV * S::Ns + S::NV * S::Nf;
+  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int BS = round64(cmax(E * S::Ns, E * S::Nf));
+};
+
+// NS volume adjoint (see the file header); writes the solution-point adjoint ubvol (may alias
+// volbar: each tile reads its vol_bar before writing), the own-flux-point adjoint ufb_own and the
+// neighbour-slot adjoint ufb_nbr
+template <int D, int P, typename T>
+__global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
+    const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
+    const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
+    const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, const T *volbar,
+    const T *__restrict__ fvnbar, const T *ufb_face, T *ubvol, T *ufb_own, T *__restrict__ ufb_nbr, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = VjpVolTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
+  __shared__ OpsDev<T, P> ops;
+  stage_ops(ops, ops_arg);
+  T *lA = lds;
+  T *luf = lds + E * TL::LA;             // [E][NV][Nf]
+  T *lvb = luf + E * NV * Nf;            // [E][NV][Ns]
+  T *lub = lvb + E * NV * Ns;            // [E][NV][Nf] own u_f adjoint
+  T *lu = lA;                            // [E][NV][Ns]
+  T *ldu = lA + E * NV * Ns;             // [E][NV][Nf]
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
+  tile_load(lvb, volbar + e0 * NV * Ns, ne * NV * Ns);
+  __syncthreads();
+  const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
+  // own u_f, LDG common solution, u^ - u_f (forward recompute)
+  for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
+    const int el = idx / Nf, fp = idx % Nf;
+    const int64_t e = e0 + el;
+    int base, stride, side;
+    line_of_fpt<D, P>(fp, base, stride, side);
+    const T *lv = side ? ops.lp : ops.lm;
+    T uo[NV], uh[NV];
+    for (int v = 0; v < NV; ++v) {
+      const T *lin = lu + (el * NV + v) * Ns + base;
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+      uo[v] = s;
+      luf[(el * NV + v) * Nf + fp] = s;
+    }
+    const int32_t code = nbr[e * Nf + fp];
+    if (code >= 0) {
+      const int32_t c = code & (NBR_R_BIT - 1);
+      const int64_t e2 = c / Nf;
+      const int f2 = c % Nf;
+      const bool isR = (code & NBR_R_BIT) != 0;
+      for (int v = 0; v < NV; ++v) {
+        const T un = uf[(e2 * NV + v) * Nf + f2];
+        uh[v] = isR ? wl * un + wr * uo[v] : wl * uo[v] + wr * un;
+      }
+    } else {
+      const int64_t b = -(int64_t)code - 1;
+      if (b < n_wall) {
+        wall_state<D>(uo, uh);
+      } else {
+        T n[D];
+        for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+        farfield<D>(uo, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, uh);
+      }
+      for (int v = 0; v < NV; ++v) ufb_nbr[(e * NV + v) * Nf + fp] = T(0);  // no neighbour here
+    }
+    for (int v = 0; v < NV; ++v) ldu[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
+  }
+  __syncthreads();
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  const bool act = threadIdx.x < E * Ns && el < ne;
+  const int64_t e = e0 + el;
+  T uv[NV], gx[D][NV];
+  if (act) {
+    T Sm[D][D];
+    for (int k = 0; k < D; ++k)
+      for (int j = 0; j < D; ++j) Sm[k][j] = metric[(e * NM + k * D + j) * Ns + i];
+    const T invJ = metric[(e * NM + D * D) * Ns + i];
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) gx[j][v] = T(0);
+#pragma unroll 1
+    for (int k = 0; k < D; ++k) {
+      int base, stride, ik, t;
+      line_of_sol<D, P>(i, k, base, stride, ik, t);
+      const T cm = -ops.gm[ik], cp = ops.gp[ik];
+      for (int v = 0; v < NV; ++v) {
+        const T *lin = lu + (el * NV + v) * Ns + base;
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) s += ops.D[ik * P + a] * lin[a * stride];
+        const T *ld = ldu + (el * NV + v) * Nf;
+        s += cm * ld[(2 * k) * Nfp + t] + cp * ld[(2 * k + 1) * Nfp + t];
+        for (int j = 0; j < D; ++j) gx[j][v] += Sm[k][j] * s;
+      }
+    }
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) gx[j][v] *= invJ;
+    for (int v = 0; v < NV; ++v) uv[v] = lu[(el * NV + v) * Ns + i];
+  }
+  __syncthreads();
+  T *lg = lA;  // [E][D][NV][Ns] physical gradient
+  if (act)
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) lg[((el * D + j) * NV + v) * Ns + i] = gx[j][v];
+  __syncthreads();
+  // adjoint of the viscous normal flux at own flux points (one flux point per thread)
+  const int ef_idx = threadIdx.x;
+  const bool actf = ef_idx < ne * Nf;
+  T gbf[D * NV], stb[NV];
+  int fpl = 0, elf = 0;
+  if (actf) {
+    elf = ef_idx / Nf;
+    fpl = ef_idx % Nf;
+    const int64_t ef = e0 + elf;
+    int base, stride, side;
+    line_of_fpt<D, P>(fpl, base, stride, side);
+    const T *lv = side ? ops.lp : ops.lm;
+    T g[D * NV], st[NV], n[D], fb[NV];
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) {
+        const T *lin = lg + ((elf * D + j) * NV + v) * Ns + base;
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+        g[j * NV + v] = s;
+        gbf[j * NV + v] = T(0);
+      }
+    for (int v = 0; v < NV; ++v) {
+      st[v] = luf[(elf * NV + v) * Nf + fpl];
+      fb[v] = fvnbar[(ef * NV + v) * Nf + fpl];
+      stb[v] = T(0);
+    }
+    for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * D + j) * Nf + fpl];
+    const int32_t code = nbr[ef * Nf + fpl];
+    T ub[NV];
+    bool heat = true, wall = false;
+    int64_t b = -1;
+    for (int v = 0; v < NV; ++v) ub[v] = st[v];
+    if (code < 0) {
+      b = -(int64_t)code - 1;
+      if (b < n_wall) {
+        wall_state<D>(st, ub);
+        heat = false;
+        wall = true;
+      } else {
+        farfield<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ub);
+      }
+    }
+    T ubb[NV];
+    for (int v = 0; v < NV; ++v) ubb[v] = T(0);
+    fvis_vjp<D>(ub, g, n, flow[elem_mesh[ef]].mu, ph, heat, fb, ubb, gbf);
+    if (code < 0) {
+      if (wall)
+        wall_state_vjp<D>(st, ubb, stb);
+      else
+        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ubb, stb);
+    } else {
+      for (int v = 0; v < NV; ++v) stb[v] = ubb[v];
+    }
+  }
+  __syncthreads();
+  T *lgb = lA;  // [E][D][NV][Nf] adjoint of the flux-point gradient
+  if (actf) {
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) lgb[((elf * D + j) * NV + v) * Nf + fpl] = gbf[j * NV + v];
+    const int64_t ef = e0 + elf;
+    for (int v = 0; v < NV; ++v) lub[(elf * NV + v) * Nf + fpl] = stb[v] + ufb_face[(ef * NV + v) * Nf + fpl];
+  }
+  __syncthreads();
+  // solution points: F~_bar from vol_bar, pointwise flux adjoints, gradient adjoint
+  T ubs[NV], grb[D][NV];
+  if (act) {
+    T Sm[D][D];
+    for (int k = 0; k < D; ++k)
+      for (int j = 0; j < D; ++j) Sm[k][j] = metric[(e * NM + k * D + j) * Ns + i];
+    const T invJ = metric[(e * NM + D * D) * Ns + i];
+    T gxb[D * NV];
+    for (int q = 0; q < D * NV; ++q) gxb[q] = T(0);
+    for (int v = 0; v < NV; ++v) ubs[v] = T(0);
+#pragma unroll 1
+    for (int k = 0; k < D; ++k) {
+      int base, stride, ik, t;
+      line_of_sol<D, P>(i, k, base, stride, ik, t);
+      T ftb[NV];
+      for (int v = 0; v < NV; ++v) {
+        const T *lin = lvb + (el * NV + v) * Ns + base;
+        T sd = T(0), sm = T(0), sp = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          const T w = lin[a * stride];
+          sd += ops.D[a * P + ik] * w;
+          sm += ops.gm[a] * w;
+          sp += ops.gp[a] * w;
+        }
+        ftb[v] = sd + ops.lm[ik] * sm - ops.lp[ik] * sp;
+      }
+      finv_dot_vjp<D>(uv, Sm[k], ph.gm1, ftb, ubs);
+      for (int v = 0; v < NV; ++v) ftb[v] = -ftb[v];
+      fvis_vjp<D>(uv, &gx[0][0], Sm[k], flow[elem_mesh[e]].mu, ph, true, ftb, ubs, gxb);
+      // flux-point gradient adjoint back to this solution point (M0^T along the k-line)
+      for (int j = 0; j < D; ++j)
+        for (int v = 0; v < NV; ++v) {
+          const T *lgf = lgb + ((el * D + j) * NV + v) * Nf;
+          gxb[j * NV + v] += ops.lm[ik] * lgf[(2 * k) * Nfp + t] + ops.lp[ik] * lgf[(2 * k + 1) * Nfp + t];
+        }
+    }
+    // grad_x u = J^-1 S^T grad_xi u  ->  reference-gradient adjoint
+    for (int k = 0; k < D; ++k)
+      for (int v = 0; v < NV; ++v) {
+        T s = T(0);
+        for (int j = 0; j < D; ++j) s += Sm[k][j] * gxb[j * NV + v];
+        grb[k][v] = invJ * s;
+      }
+  }
+  __syncthreads();
+  T *lrb = lA;  // [E][D][NV][Ns] reference-gradient adjoint
+  if (act)
+    for (int k = 0; k < D; ++k)
+      for (int v = 0; v < NV; ++v) lrb[((el * D + k) * NV + v) * Ns + i] = grb[k][v];
+  __syncthreads();
+  if (act) {
+    // D_k^T of the reference gradient
+#pragma unroll 1
+    for (int k = 0; k < D; ++k) {
+      int base, stride, ik, t;
+      line_of_sol<D, P>(i, k, base, stride, ik, t);
+      for (int v = 0; v < NV; ++v) {
+        const T *lin = lrb + ((el * D + k) * NV + v) * Ns + base;
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) s += ops.D[a * P + ik] * lin[a * stride];
+        ubs[v] += s;
+      }
+    }
+    for (int v = 0; v < NV; ++v) ubvol[(e * NV + v) * Ns + i] = ubs[v];
+  }
+  // lifting of (u^ - u_f): adjoint at flux points -> own and neighbour u_f adjoints
+  if (actf) {
+    const int64_t ef = e0 + elf;
+    int base, stride, side;
+    line_of_fpt<D, P>(fpl, base, stride, side);
+    const int k = (fpl / Nfp) >> 1;
+    T dub[NV];
+    for (int v = 0; v < NV; ++v) {
+      const T *lin = lrb + ((elf * D + k) * NV + v) * Ns + base;
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += (side ? ops.gp[a] : -ops.gm[a]) * lin[a * stride];
+      dub[v] = s;
+    }
+    T own[NV];
+    for (int v = 0; v < NV; ++v) own[v] = lub[(elf * NV + v) * Nf + fpl] - dub[v];
+    const int32_t code = nbr[ef * Nf + fpl];
+    if (code >= 0) {
+      const int32_t c = code & (NBR_R_BIT - 1);
+      const int64_t e2 = c / Nf;
+      const int f2 = c % Nf;
+      const bool isR = (code & NBR_R_BIT) != 0;
+      const T wo = isR ? wr : wl, wn = isR ? wl : wr;
+      for (int v = 0; v < NV; ++v) {
+        own[v] += wo * dub[v];
+        ufb_nbr[(e2 * NV + v) * Nf + f2] = wn * dub[v];
+      }
+    } else {
+      const int64_t b = -(int64_t)code - 1;
+      T st[NV];
+      for (int v = 0; v < NV; ++v) st[v] = luf[(elf * NV + v) * Nf + fpl];
+      if (b < n_wall) {
+        wall_state_vjp<D>(st, dub, own);
+      } else {
+        T n[D];
+        for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, dub, own);
+      }
+    }
+    for (int v = 0; v < NV; ++v) ufb_own[(ef * NV + v) * Nf + fpl] = own[v];
+  }
+}
+
+// Euler volume adjoint: F~_bar from vol_bar, pointwise inviscid-flux adjoint
+template <int D, int P, typename T>
+__global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_euler_vol(const T *__restrict__ u,
+                                                                             const T *__restrict__ metric,
+                                                                             OpsDev<T, P> ops_arg, PhysDev<T> ph,
+                                                                             const T *volbar, T *ubvol, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = VjpDivTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, NV = S::NV, NM = S::NM;
+  __shared__ __attribute__((aligned(16))) T lvb[E * TL::LE];
+  __shared__ OpsDev<T, P> ops;
+  stage_ops(ops, ops_arg);
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  tile_load(lvb, volbar + e0 * NV * Ns, ne * NV * Ns);
+  __syncthreads();
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  if (el >= ne) return;
+  const int64_t e = e0 + el;
+  T uv[NV], ubs[NV];
+  for (int v = 0; v < NV; ++v) {
+    uv[v] = u[(e * NV + v) * Ns + i];
+    ubs[v] = T(0);
+  }
+  for (int k = 0; k < D; ++k) {
+    T Sk[D];
+    for (int j = 0; j < D; ++j) Sk[j] = metric[(e * NM + k * D + j) * Ns + i];
+    int base, stride, ik, t;
+    line_of_sol<D, P>(i, k, base, stride, ik, t);
+    T ftb[NV];
+    for (int v = 0; v < NV; ++v) {
+      const T *lin = lvb + (el * NV + v) * Ns + base;
+      T sd = T(0), sm = T(0), sp = T(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        const T w = lin[a * stride];
+        sd += ops.D[a * P + ik] * w;
+        sm += ops.gm[a] * w;
+        sp += ops.gp[a] * w;
+      }
+      ftb[v] = sd + ops.lm[ik] * sm - ops.lp[ik] * sp;
+    }
+    finv_dot_vjp<D>(uv, Sk, ph.gm1, ftb, ubs);
+  }
+  for (int v = 0; v < NV; ++v) ubvol[(e * NV + v) * Ns + i] = ubs[v];
+}
+
+// u_bar += ubvol + M0^T (ufb_own + ufb_nbr)
+template <int D, int P, typename T>
+__global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_final(const T *ubvol, const T *__restrict__ ufb_own,
+                                                                         const T *__restrict__ ufb_nbr,
+                                                                         OpsDev<T, P> ops_arg, T *__restrict__ ubar,
+                                                                         int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = VjpDivTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV;
+  __shared__ OpsDev<T, P> ops;
+  stage_ops(ops, ops_arg);
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  if (el >= ne) return;
+  const int64_t e = e0 + el;
+  for (int v = 0; v < NV; ++v) {
+    T s = ubvol[(e * NV + v) * Ns + i];
+    const T *fo = ufb_own + (e * NV + v) * Nf;
+    const T *fn = ufb_nbr ? ufb_nbr + (e * NV + v) * Nf : nullptr;
+    for (int k = 0; k < D; ++k) {
+      int base, stride, ik, t;
+      line_of_sol<D, P>(i, k, base, stride, ik, t);
+      const int fm = (2 * k) * Nfp + t, fpp = (2 * k + 1) * Nfp + t;
+      T am = fo[fm], ap = fo[fpp];
+      if (fn) {
+        am += fn[fm];
+        ap += fn[fpp];
+      }
+      s += ops.lm[ik] * am + ops.lp[ik] * ap;
+    }
+    ubar[(e * NV + v) * Ns + i] += s;
+  }
+}
+
+// ------------------------------------------------------------------------------------ launcher
+static inline unsigned vblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int D, int P, typename T>
+struct VjpEngine {
+  using S = Shape<D, P>;
+  static void run(const fr_solver *s, const T *u, const T *rbar, T *ubar, T *work, hipStream_t st) {
+    OpsDev<T, P> o;
+    for (int i = 0; i < P * P; ++i) o.D[i] = (T)s->ops.D[i];
+    for (int i = 0; i < P; ++i) {
+      o.lm[i] = (T)s->ops.lm[i];
+      o.lp[i] = (T)s->ops.lp[i];
+      o.gp[i] = (T)s->ops.gp[i];
+      o.gm[i] = (T)s->ops.gm[i];
+    }
+    PhysDev<T> ph;
+    ph.gamma = (T)s->gamma;
+    ph.gm1 = (T)(s->gamma - 1.0);
+    ph.prandtl = (T)s->prandtl;
+    ph.beta = (T)s->beta;
+    ph.tau = (T)s->tau;
+    const int64_t Ne = s->Ne, nsol = Ne * S::NV * S::Ns, nf = Ne * S::NV * S::Nf;
+    T *volbar = work;            // also the solution-point adjoint (read before write per tile)
+    T *fhatbar = volbar + nsol;  // also the own flux-point adjoint
+    T *ufbface = fhatbar + nf;
+    T *fvnbar = ufbface + nf;
+    T *ufbnbr = fvnbar + nf;
+    T *uf = (T *)s->uf;
+    const T *metric = (const T *)s->metric;
+    const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
+    k_vjp_interp<D, P, T><<<vblk(Ne * S::Nf, 256), 256, 0, st>>>(u, uf, o, Ne);
+    using TD = VjpDivTile<D, P, T>;
+    k_vjp_div<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, metric, o, volbar, fhatbar, Ne);
+    const int64_t nface = s->npair + s->nbnd;
+    if (s->equations == 1) {
+      k_vjp_face<D, P, T, true><<<vblk(nface, 256), 256, 0, st>>>(
+          uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, fvnbar);
+      using TV = VjpVolTile<D, P, T>;
+      k_vjp_ns_vol<D, P, T><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
+          u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
+          volbar, fvnbar, ufbface, volbar, fhatbar, ufbnbr, Ne);
+      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, fhatbar, ufbnbr, o, ubar, Ne);
+    } else {
+      k_vjp_face<D, P, T, false><<<vblk(nface, 256), 256, 0, st>>>(
+          uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr);
+      k_vjp_euler_vol<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(u, metric, o, ph, volbar, volbar, Ne);
+      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, nullptr, o, ubar, Ne);
+    }
+  }
+};
+
+// work-array size in elements of the state type
+size_t vjp_work_elems(const fr_solver *s) {
+  return (size_t)s->Ne * s->NV * (s->Ns + 4 * s->Nf);
+}
+
+bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, hipStream_t st) {
+#define FR_VCASE(DD, PP)                                                                              \
+  if (s->dim == DD && s->p + 1 == PP) {                                                               \
+    if (s->precision == 0)                                                                            \
+      VjpEngine<DD, PP, double>::run(s, (const double *)u, (const double *)rbar, (double *)ubar,      \
+                                     (double *)work, st);                                             \
+    else                                                                                              \
+      VjpEngine<DD, PP, float>::run(s, (const float *)u, (const float *)rbar, (float *)ubar,          \
+                                    (float *)work, st);                                               \
+    return true;                                                                                      \
+  }
+  FR_VCASE(2, 2) FR_VCASE(2, 3) FR_VCASE(2, 4) FR_VCASE(2, 5)
+  FR_VCASE(3, 2) FR_VCASE(3, 3) FR_VCASE(3, 4) FR_VCASE(3, 5)
+#undef FR_VCASE
+  return false;
+}
+
+}  // namespace frmi

@@ -341,3 +341,24 @@ def test_batched_meshes_equal_separate_solves():
     Rb = sb.residual(ub)
     Rs = torch.cat([s.residual(u) for s, u in parts])
     assert torch.allclose(Rb, Rs, rtol=1e-13, atol=1e-12 * Rs.abs().max().item())
+
+
+@pytest.mark.parametrize("eq", ["euler", "ns"])
+def test_oracle_gradient_matches_central_differences(eq):
+    """The oracle gradient (reverse-mode autograd through the FP64 residual) agrees with central
+    finite differences along seeded directions: <J^T r, v> = <r, (R(u + e v) - R(u - e v)) / 2e>."""
+    m = fi.o_grid(8, 3, q=2, r1=4.0, stretch=1.3, seed=4, wall="wall" if eq == "ns" else "farfield")
+    fp = fi.freestream_params(2, 0.3, 100.0 if eq == "ns" else None, aoa_deg=10.0)
+    s = OracleSystem(m, 2, fp, equations=eq)
+    u0 = state_at(s, fi.freestream_state, fp=fp)
+    rng = np.random.default_rng(8)
+    u0 = u0 * (1.0 + torch.tensor(rng.uniform(-0.02, 0.02, u0.shape)))
+    r = torch.tensor(rng.normal(size=u0.shape))
+    u = u0.clone().requires_grad_(True)
+    (s.residual(u) * r).sum().backward()
+    for _ in range(3):
+        v = torch.tensor(rng.normal(size=u0.shape)) * u0.abs().mean()
+        eps = 1e-6
+        fd = ((s.residual(u0 + eps * v) - s.residual(u0 - eps * v)) * r).sum() / (2 * eps)
+        ad = (u.grad * v).sum()
+        assert abs(float(fd - ad)) <= 1e-6 * abs(float(ad)), (float(fd), float(ad))
