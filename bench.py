@@ -161,7 +161,7 @@ def cpu_baseline(budget_s: float = 20.0):
     t0 = time.perf_counter()
     n = 0
     while True:
-        s.rk4_step(u, torch.tensor([1e-6]))
+        s.rk4_step(u, torch.tensor([1e-6], dtype=torch.float64))
         n += 1
         if time.perf_counter() - t0 > budget_s / 2 or n >= 4:
             break

@@ -173,6 +173,21 @@ fr_status fr_solver_info(const fr_solver *s, int64_t info[8]);
 fr_status fr_profile_enable(fr_solver *s, int32_t enable);
 fr_status fr_profile_read(fr_solver *s, double *total_ms, int64_t *launches, void *stream);
 
+/* Adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du with p_a the probe pressure
+ * (interpolated conserved state, then Eq. (5)).  p_bar: device FP64 [n_probe]. */
+fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, void *stream);
+
+/* One classical RK4 step of u (device state, in place, no sampling) that also stores the three
+ * intermediate stage states y2 = u + dt/2 k1, y3 = u + dt/2 k2, y4 = u + dt k3 of the step in
+ * stages[3][n_elem][nv][Ns] (device, state dtype), for use by fr_rk_step_vjp. */
+fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, void *stages, void *stream);
+
+/* Adjoint of one RK4 step u_n -> u_{n+1}: on entry u_bar holds dJ/du_{n+1}, on return dJ/du_n
+ * (= (du_{n+1}/du_n)^T u_bar).  stages: the step's stage states from fr_rk_step_stages, or NULL
+ * to recompute them from u_n.  dt: device FP64 [n_mesh].  Allocates its work area on first use. */
+fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, void *u_bar,
+                         void *stream);
+
 /* Release everything the handle owns (NULL is a no-op). */
 void fr_destroy(fr_solver *s);
 

@@ -175,7 +175,9 @@ class OracleSystem:
 
     # ------------------------------------------------------------------ time stepping
     def rk4_step(self, u, dt, geo=None):
-        """Classical RK4 with dt[mesh]."""
+        """Classical RK4 with dt[mesh] (a float, a float64 array or a float64 tensor)."""
+        if isinstance(dt, torch.Tensor) and dt.dtype != DT:
+            raise TypeError("dt must be float64 (a float32 dt silently perturbs the step size)")
         dte = torch.as_tensor(dt, dtype=DT).reshape(-1)[self.elem_mesh][:, None, None]
         k1 = self.residual(u, geo)
         k2 = self.residual(u + 0.5 * dte * k1, geo)

@@ -60,12 +60,19 @@ def lib() -> C.CDLL:
     L.fr_probe_series.argtypes = [vp, vp, i64, C.POINTER(i64), vp]
     L.fr_reset_accumulators.argtypes = [vp, vp]
     L.fr_rhs_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fr_solver_info.argtypes = [vp, vp]
+    L.fr_profile_enable.argtypes = [vp, i32]
+    L.fr_profile_read.argtypes = [vp, vp, vp, vp]
+    L.fr_probe_vjp.argtypes = [vp, vp, vp, vp, vp]
+    L.fr_rk_step_stages.argtypes = [vp, vp, vp, vp, vp]
+    L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fr_destroy.argtypes = [vp]
     L.fr_destroy.restype = None
     L.fr_last_error.argtypes = []
     L.fr_last_error.restype = C.c_char_p
     for name in ("fr_build_operators", "fr_state_shape", "fr_solpt_coords", "fr_rhs", "fr_rk_step",
-                 "fr_probe_oaspl", "fr_probe_series", "fr_reset_accumulators", "fr_rhs_vjp"):
+                 "fr_probe_oaspl", "fr_probe_series", "fr_reset_accumulators", "fr_rhs_vjp", "fr_solver_info",
+                 "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp"):
         getattr(L, name).restype = i32
     _lib = L
     return L

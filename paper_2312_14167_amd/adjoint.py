@@ -1,0 +1,60 @@
+"""Checkpointed adjoint of an RK4 trajectory with probe sampling, as a torch.autograd.Function.
+
+Forward: K RK4 steps of the FR residual from u_0 with the probe pressure sampled before every
+step (p_n = p(u_n), n = 0..K-1), keeping the state every `checkpoint_every` steps.  Backward:
+segment by segment in reverse, the segment's states and RK stage states are recomputed from its
+checkpoint (fr_rk_step_stages), then each step is reversed with fr_rk_step_vjp and the probe
+adjoint fr_probe_vjp:  u_bar_n = (du_{n+1}/du_n)^T u_bar_{n+1} + (dp_n/du_n)^T p_bar_n.
+All arithmetic runs in the library's kernels; torch provides the tensors and the tape.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class FRTrajectory(torch.autograd.Function):
+    """p = FRTrajectory.apply(u0, solver, dt, n_steps, checkpoint_every) -> [n_steps, n_probe] FP64."""
+
+    @staticmethod
+    def forward(ctx, u0, solver, dt, n_steps: int, checkpoint_every: int = 20):
+        C = max(1, int(checkpoint_every))
+        u = u0.detach().clone()
+        ckpts = {0: u.clone()}
+        solver.reset_accumulators()
+        for n in range(n_steps):
+            solver.rk_step(u, dt, 1, sample_every=1)
+            if (n + 1) % C == 0 and n + 1 < n_steps:
+                ckpts[n + 1] = u.clone()
+        series = solver.probe_series(n_steps)                    # [n_probe, K]
+        ctx.solver, ctx.dt, ctx.K, ctx.C, ctx.ckpts = solver, dt, n_steps, C, ckpts
+        return torch.tensor(series.T.copy(), dtype=torch.float64, device=u0.device)
+
+    @staticmethod
+    def backward(ctx, p_bar):
+        sol, dt, K, C = ctx.solver, ctx.dt, ctx.K, ctx.C
+        p_bar = p_bar.detach().to(torch.float64).contiguous()
+        ub = torch.zeros(sol.shape, dtype=sol.dtype, device=p_bar.device)   # dJ/du_K = 0
+        for s0 in reversed(range(0, K, C)):
+            s1 = min(s0 + C, K)
+            u = ctx.ckpts[s0].clone()
+            states, stages = [], []
+            for n in range(s0, s1):
+                states.append(u.clone())
+                st = torch.empty((3,) + sol.shape, dtype=sol.dtype, device=u.device)
+                sol.rk_step_stages(u, dt, st)
+                stages.append(st)
+            for n in reversed(range(s0, s1)):
+                un, st = states[n - s0], stages[n - s0]
+                sol.rk_step_vjp(un, dt, ub, st)
+                sol.probe_vjp(un, p_bar[n], ub)
+        return ub, None, None, None, None
+
+
+def probe_variance_gradient(solver, u0, dt, n_steps: int, checkpoint_every: int = 20):
+    """J = sum over probes of (1/K) sum_n (p_n - mean p)^2 (the time-mean square of the probe
+    pressure fluctuation) and dJ/du0."""
+    u = u0.detach().clone().requires_grad_(True)
+    p = FRTrajectory.apply(u, solver, dt, n_steps, checkpoint_every)
+    J = ((p - p.mean(dim=0, keepdim=True)) ** 2).mean(dim=0).sum()
+    J.backward()
+    return float(J), u.grad

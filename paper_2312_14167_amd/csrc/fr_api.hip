@@ -15,6 +15,11 @@ namespace frmi {
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
+  void (*step_record)(const fr_solver *, void *, const double *, void *, hipStream_t);
+  void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
+  void (*rk_adj_combine)(const fr_solver *, const void *, const void *, void *, void *, double, double,
+                         const double *, hipStream_t);
+  void (*zero)(const fr_solver *, void *, hipStream_t);
 };
 bool get_dispatch(int dim, int p, int precision, Dispatch &out);
 void launch_fill(double *p, int64_t n, double v, hipStream_t st);
@@ -420,6 +425,70 @@ fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar
     }
     if (!launch_vjp(s, u, r_bar, u_bar, s->vjp_work, (hipStream_t)stream))
       throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+    HIP_OK(hipGetLastError());
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, void *stream) {
+  if (!s || !u || !u_bar || (s->n_probe > 0 && !p_bar)) return fail(FR_ERR_ARG, "NULL argument");
+  try {
+    Dispatch d = dispatch_of(s);
+    d.probe_vjp(s, u, p_bar, u_bar, (hipStream_t)stream);
+    HIP_OK(hipGetLastError());
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, void *stages, void *stream) {
+  if (!s || !u || !dt || !stages) return fail(FR_ERR_ARG, "NULL argument");
+  try {
+    Dispatch d = dispatch_of(s);
+    d.step_record(s, u, dt, stages, (hipStream_t)stream);
+    HIP_OK(hipGetLastError());
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, void *u_bar,
+                         void *stream) {
+  if (!s || !u_n || !dt || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
+  if (u_bar == u_n) return fail(FR_ERR_ARG, "u_bar must not alias u_n");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Dispatch d = dispatch_of(s);
+    const size_t nb = (size_t)s->Ne * s->NV * s->Ns * s->tsize;
+    if (!s->adj_work) s->adj_work = (char *)dalloc(s, nb * 7);  // A, KB, Z, temp state, 3 stages
+    if (!s->vjp_work) {
+      s->vjp_bytes = vjp_work_elems(s) * s->tsize;
+      s->vjp_work = dalloc(s, s->vjp_bytes);
+    }
+    char *A = s->adj_work, *KB = A + nb, *Z = KB + nb, *TMP = Z + nb, *STG = TMP + nb;
+    const char *Y = (const char *)stages;
+    if (!Y) {  // recompute the stage states from u_n on a copy
+      HIP_OK(hipMemcpyAsync(TMP, u_n, nb, hipMemcpyDeviceToDevice, st));
+      d.step_record(s, TMP, dt, STG, st);
+      Y = STG;
+    }
+    HIP_OK(hipMemcpyAsync(A, u_bar, nb, hipMemcpyDeviceToDevice, st));
+    // u_{n+1} = u_n + dt/6 (k1 + 2 k2 + 2 k3 + k4); k_{s} = R(y_s), y1 = u_n, y2 = u_n + dt/2 k1,
+    // y3 = u_n + dt/2 k2, y4 = u_n + dt k3.  Reverse:
+    const void *ys[4] = {u_n, Y, Y + nb, Y + 2 * nb};
+    const double cA[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};  // weight of A in k_bar_s
+    const double cZ[4] = {0.5, 0.5, 1.0, 0.0};                          // y_{s+1} = u + cZ[s] dt k_s
+    d.rk_adj_combine(s, A, nullptr, KB, u_bar, cA[3], 0.0, dt, st);    // k4_bar = dt/6 a
+    for (int k = 3; k >= 0; --k) {
+      d.zero(s, Z, st);
+      if (!launch_vjp(s, ys[k], KB, Z, s->vjp_work, st)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+      // u_bar += z_k; k_{k-1}_bar = dt (cA a + cZ[k-1] z_k)
+      d.rk_adj_combine(s, A, Z, KB, u_bar, k > 0 ? cA[k - 1] : 0.0, k > 0 ? cZ[k - 1] : 0.0, dt, st);
+    }
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());

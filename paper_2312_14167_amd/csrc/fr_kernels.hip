@@ -328,6 +328,7 @@ struct RKArgs {
   T cA, cB;          // u_next = u0 + cA dt R ; acc += cB dt R
   int first, last;
   T *uf_next;        // flux-point values of the new stage state, or nullptr
+  T *ustage_copy;    // optional second copy of the new stage state (adjoint recording)
 };
 
 // shared epilogue: R at (el, i) for all variables -> rhs output or RK update; the new stage
@@ -350,6 +351,7 @@ __device__ __forceinline__ void rk_epilogue(const T *R, int64_t e, int i, const 
       rk.acc[o] = a + rk.cB * dt * R[v];
       w[v] = u0 + rk.cA * dt * R[v];
       rk.ustage[o] = w[v];
+      if (rk.ustage_copy) rk.ustage_copy[o] = w[v];
     } else {
       w[v] = u0 + (a + rk.cB * dt * R[v]);
       rk.u0[o] = w[v];
@@ -565,6 +567,67 @@ __global__ __launch_bounds__(256) void k_wall_force(const T *__restrict__ uf, co
     for (int j = 0; j < D; ++j) force_acc[m * D + j] += red[0][j];
 }
 
+// adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du (one workgroup, probes in order)
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_probe_vjp(const T *__restrict__ u, const int64_t *__restrict__ pelem,
+                                                   const double *__restrict__ pw, int n_probe, double gm1,
+                                                   const double *__restrict__ pbar, T *ubar) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns;
+  __shared__ double red[256];
+  __shared__ double dpdu[NV];
+  for (int a = 0; a < n_probe; ++a) {
+    const int64_t e = pelem[a];
+    double up[NV];
+    for (int v = 0; v < NV; ++v) {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < Ns; i += blockDim.x) s += pw[(int64_t)a * Ns + i] * (double)u[(e * NV + v) * Ns + i];
+      red[threadIdx.x] = s;
+      __syncthreads();
+      for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+      }
+      up[v] = red[0];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      // p = (gamma-1)(E - |m|^2 / (2 rho)) at the interpolated state
+      double m2 = 0.0;
+      for (int j = 0; j < D; ++j) m2 += up[1 + j] * up[1 + j];
+      dpdu[0] = gm1 * 0.5 * m2 / (up[0] * up[0]);
+      for (int j = 0; j < D; ++j) dpdu[1 + j] = -gm1 * up[1 + j] / up[0];
+      dpdu[D + 1] = gm1;
+    }
+    __syncthreads();
+    const double pb = pbar[a];
+    for (int idx = threadIdx.x; idx < NV * Ns; idx += blockDim.x) {
+      const int v = idx / Ns, i = idx % Ns;
+      ubar[(e * NV + v) * Ns + i] += (T)(pb * dpdu[v] * pw[(int64_t)a * Ns + i]);
+    }
+    __syncthreads();
+  }
+}
+
+// RK4 adjoint combination: kb = dt (ca a + cz z); ub += z
+template <typename T>
+__global__ void k_rk_adj_combine(const T *__restrict__ a, const T *__restrict__ z, T *__restrict__ kb,
+                                 T *__restrict__ ub, double ca, double cz, const double *__restrict__ dt,
+                                 const int32_t *__restrict__ elem_mesh, int64_t per_elem, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T d = (T)dt[elem_mesh[i / per_elem]];
+  const T zi = z ? z[i] : T(0);
+  kb[i] = d * ((T)ca * a[i] + (T)cz * zi);
+  if (z) ub[i] += zi;
+}
+
+template <typename T>
+__global__ void k_fill_t(T *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
+}
+
 // fill kernel (graph-safe replacement for memset)
 __global__ void k_fill_f64(double *p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -700,7 +763,8 @@ struct Engine {
 
   // one classical RK4 step of u in place; `fresh`: s->uf does not hold u_f of u yet (first step
   // of a call); later steps reuse the flux-point values written by the previous last stage
-  static void step(const fr_solver *s, T *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
+  static void step(const fr_solver *s, T *u, const double *dt, bool sample, bool fresh, hipStream_t st,
+                   T *record = nullptr) {
     static const double cA[4] = {0.5, 0.5, 1.0, 0.0};
     static const double cB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     if (sample) probe(s, u, st);
@@ -716,6 +780,7 @@ struct Engine {
       rk.first = k == 0;
       rk.last = k == 3;
       rk.uf_next = (T *)s->uf;
+      rk.ustage_copy = (record && k < 3) ? record + (int64_t)k * s->Ne * S::NV * S::Ns : nullptr;
       const T *ust = k == 0 ? u : (const T *)s->ustage;
       stage(s, ust, rk, st, sample && k == 0);
     }
@@ -726,6 +791,11 @@ struct Engine {
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
+  void (*step_record)(const fr_solver *, void *, const double *, void *, hipStream_t);
+  void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
+  void (*rk_adj_combine)(const fr_solver *, const void *, const void *, void *, void *, double, double,
+                         const double *, hipStream_t);
+  void (*zero)(const fr_solver *, void *, hipStream_t);
 };
 
 template <int D, int P, typename T>
@@ -736,6 +806,26 @@ Dispatch make_dispatch() {
   };
   d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
     Engine<D, P, T>::step(s, (T *)u, dt, sample, fresh, st);
+  };
+  d.step_record = [](const fr_solver *s, void *u, const double *dt, void *rec, hipStream_t st) {
+    Engine<D, P, T>::step(s, (T *)u, dt, false, true, st, (T *)rec);
+  };
+  d.probe_vjp = [](const fr_solver *s, const void *u, const double *pbar, void *ub, hipStream_t st) {
+    if (s->n_probe > 0)
+      k_probe_vjp<D, P, T><<<1, 256, 0, st>>>((const T *)u, s->probe_elem, s->probe_w, s->n_probe,
+                                              s->gamma - 1.0, pbar, (T *)ub);
+  };
+  d.rk_adj_combine = [](const fr_solver *s, const void *a, const void *z, void *kb, void *ub, double ca, double cz,
+                        const double *dt, hipStream_t st) {
+    using S = Shape<D, P>;
+    const int64_t per = (int64_t)S::NV * S::Ns, n = s->Ne * per;
+    k_rk_adj_combine<T><<<nblk(n, 256), 256, 0, st>>>((const T *)a, (const T *)z, (T *)kb, (T *)ub, ca, cz, dt,
+                                                       s->elem_mesh, per, n);
+  };
+  d.zero = [](const fr_solver *s, void *p, hipStream_t st) {
+    using S = Shape<D, P>;
+    const int64_t n = s->Ne * S::NV * S::Ns;
+    k_fill_t<T><<<nblk(n, 256), 256, 0, st>>>((T *)p, n);
   };
   return d;
 }

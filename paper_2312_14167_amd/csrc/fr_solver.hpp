@@ -94,6 +94,7 @@ struct fr_solver {
   // VJP work arrays (allocated on first use)
   void *vjp_work = nullptr;
   size_t vjp_bytes = 0;
+  char *adj_work = nullptr;  // RK-step adjoint: 7 state-sized arrays
 
   std::vector<void *> owned;  // everything hipMalloc'ed
 };

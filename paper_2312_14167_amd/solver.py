@@ -135,6 +135,46 @@ class Solver:
         check(lib().fr_probe_series(self._h, out.ctypes.data_as(C.c_void_p), int(cap), C.byref(n), _stream(stream)))
         return out[:self.n_probe, :min(int(n.value), cap)]
 
+    def info(self) -> dict:
+        a = np.zeros(8, dtype=np.int64)
+        check(lib().fr_solver_info(self._h, a.ctypes.data_as(C.c_void_p)))
+        keys = ["n_elem", "nv", "ns", "nf", "n_pairs", "n_boundary", "n_wall", "n_mesh"]
+        return dict(zip(keys, (int(x) for x in a)))
+
+    def _check_dt(self, dt):
+        if not (dt.is_cuda and dt.dtype == torch.float64 and dt.numel() == self.n_mesh and dt.is_contiguous()):
+            raise ValueError("dt must be a contiguous float64 CUDA tensor with one entry per mesh")
+
+    def probe_vjp(self, u: torch.Tensor, p_bar: torch.Tensor, u_bar: torch.Tensor, stream=None):
+        """u_bar += sum_a p_bar[a] dp_a/du (p_bar: float64 CUDA tensor [n_probe])."""
+        self._check_state(u, "u")
+        self._check_state(u_bar, "u_bar")
+        p_bar = p_bar.to(device=u.device, dtype=torch.float64).contiguous()
+        check(lib().fr_probe_vjp(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(p_bar.data_ptr()),
+                                 C.c_void_p(u_bar.data_ptr()), _stream(stream)))
+        return u_bar
+
+    def rk_step_stages(self, u: torch.Tensor, dt: torch.Tensor, stages: torch.Tensor, stream=None):
+        """One RK4 step of u in place, recording y2, y3, y4 into stages [3, *shape]."""
+        self._check_state(u, "u")
+        self._check_dt(dt)
+        if not (stages.is_cuda and stages.dtype == self.dtype and tuple(stages.shape) == (3,) + self.shape
+                and stages.is_contiguous()):
+            raise ValueError("stages must be a contiguous CUDA tensor of shape (3,) + state shape")
+        check(lib().fr_rk_step_stages(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()),
+                                      C.c_void_p(stages.data_ptr()), _stream(stream)))
+        return u
+
+    def rk_step_vjp(self, u_n: torch.Tensor, dt: torch.Tensor, u_bar: torch.Tensor, stages=None, stream=None):
+        """u_bar <- (d u_{n+1} / d u_n)^T u_bar for one RK4 step from u_n."""
+        self._check_state(u_n, "u_n")
+        self._check_state(u_bar, "u_bar")
+        self._check_dt(dt)
+        sp = C.c_void_p(stages.data_ptr()) if stages is not None else None
+        check(lib().fr_rk_step_vjp(self._h, C.c_void_p(u_n.data_ptr()), C.c_void_p(dt.data_ptr()), sp,
+                                   C.c_void_p(u_bar.data_ptr()), _stream(stream)))
+        return u_bar
+
     def rhs_vjp(self, u: torch.Tensor, r_bar: torch.Tensor, u_bar: torch.Tensor, x_bar: torch.Tensor | None = None,
                 stream=None):
         self._check_state(u, "u")

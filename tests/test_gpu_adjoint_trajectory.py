@@ -1,0 +1,96 @@
+"""Checkpointed RK4-trajectory adjoint (fr_rk_step_stages / fr_rk_step_vjp / fr_probe_vjp behind a
+torch.autograd.Function) against reverse-mode autograd of the FP64 oracle trajectory and against
+central differences of the GPU objective.  Objective: time-mean square of the probe pressure
+fluctuation, J = (1/K) sum_n (p_n - mean p)^2, gradient with respect to the initial state."""
+import numpy as np
+import pytest
+import torch
+
+import fr_inputs as fi
+
+pytestmark = pytest.mark.gpu
+
+
+def _case():
+    m = fi.o_grid(16, 6, q=3, r1=6.0, stretch=1.2, seed=7)
+    fp = fi.freestream_params(2, 0.2, 1000.0)
+    return m, 3, fp, [[0.0, 3.0]]
+
+
+def _objective(p):
+    return ((p - p.mean(dim=0, keepdim=True)) ** 2).mean(dim=0).sum()
+
+
+def test_trajectory_gradient_matches_oracle_and_fd(gpu):
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+    m, p, fp, probes = _case()
+    s = OracleSystem(m, p, fp, equations="ns", probes=probes)
+    x = s.solpt_coords()
+    u0 = fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (4,), 3, 2e-2)
+    u0 = torch.tensor(u0).permute(0, 2, 1).contiguous()
+    K, C, dt = 12, 5, 2e-4
+    # oracle: autograd through the whole trajectory
+    uo = u0.clone().requires_grad_(True)
+    u, ps = uo, []
+    for n in range(K):
+        ps.append(s.probe_pressure(u))
+        u = s.rk4_step(u, torch.tensor([dt], dtype=torch.float64))
+    Jref = _objective(torch.stack(ps))
+    Jref.backward()
+    gref = uo.grad
+    # GPU adjoint
+    sol = Solver(m, p, fp, equations="ns", probes=probes, max_samples=K)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    ug = u0.to(gpu).clone().requires_grad_(True)
+    P = FRTrajectory.apply(ug, sol, dtt, K, C)
+    J = _objective(P)
+    J.backward()
+    g = ug.grad
+    # J is the variance of a signal p ~ p_inf = 17.9 with fluctuations sigma ~ 5e-3: its relative
+    # round-off is ~ eps (p_inf / sigma)^2 ~ 3e-9 per operation, hence the 1e-6 bound
+    assert abs(float(J) - float(Jref)) <= 1e-6 * abs(float(Jref)), (float(J), float(Jref))
+    pref = torch.stack(ps).detach()
+    dp = float((P.detach().cpu() - pref).abs().max())
+    sig = float(pref.std())
+    err = float((g.cpu() - gref).norm() / gref.norm())
+    print(f"probe series max diff {dp:.3e} (sigma {sig:.3e}); trajectory gradient rel L2 vs oracle {err:.3e}")
+    # the gradient (2/K) sum (p_n - mean p) dp_n/du inherits the relative accuracy of the
+    # fluctuation p - mean p, i.e. ~ dp / sigma
+    assert dp <= 1e-12 * float(pref.abs().max()), dp
+    assert err <= max(1e-9, 20 * dp / sig), err
+    # central differences of the GPU objective along seeded directions
+    rng = np.random.default_rng(11)
+    for _ in range(2):
+        v = torch.tensor(rng.normal(size=u0.shape), device=gpu) * 1e-2
+        eps = 1e-4
+        with torch.no_grad():
+            Jp = _objective(FRTrajectory.apply(u0.to(gpu) + eps * v, sol, dtt, K, C))
+            Jm = _objective(FRTrajectory.apply(u0.to(gpu) - eps * v, sol, dtt, K, C))
+        fd = float((Jp - Jm) / (2 * eps))
+        ad = float((g * v).sum())
+        print(f"directional derivative: central difference {fd:.10e} adjoint {ad:.10e}")
+        assert abs(fd - ad) <= 1e-5 * abs(ad), (fd, ad)
+
+
+def test_rk_step_vjp_recompute_equals_recorded_stages(gpu):
+    from paper_2312_14167_amd import Solver
+    m, p, fp, probes = _case()
+    sol = Solver(m, p, fp, equations="ns", probes=probes, max_samples=4)
+    x = sol.solpt_coords()
+    u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (4,), 4, 1e-2)).permute(0, 2, 1)
+    u0 = u0.contiguous().to(gpu)
+    dtt = torch.tensor([2e-4], dtype=torch.float64, device=gpu)
+    st = torch.empty((3,) + sol.shape, dtype=torch.float64, device=gpu)
+    u = u0.clone()
+    sol.rk_step_stages(u, dtt, st)
+    u2 = u0.clone()
+    sol.rk_step(u2, dtt, 1)
+    assert torch.equal(u, u2)   # the recording step is the same step
+    a = torch.tensor(np.random.default_rng(2).normal(size=u0.shape), device=gpu)
+    b1 = a.clone()
+    sol.rk_step_vjp(u0, dtt, b1, st)
+    b2 = a.clone()
+    sol.rk_step_vjp(u0, dtt, b2, None)
+    assert torch.equal(b1, b2)

@@ -168,7 +168,7 @@ def test_entropy_wave_order():
         s = OracleSystem(m, p, fp, equations="euler")
         u = state_at(s, fi.entropy_wave_state)
         nst = 25
-        u, _, _ = s.run(u, torch.tensor([T / nst]), nst, sample_every=0)
+        u, _, _ = s.run(u, torch.tensor([T / nst], dtype=torch.float64), nst, sample_every=0)
         ue = state_at(s, fi.entropy_wave_state, t=T)
         errs.append(_l2(s, u - ue))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
@@ -184,7 +184,7 @@ def test_isentropic_vortex_closed_form():
     s = OracleSystem(m, 3, fp, equations="euler")
     u = state_at(s, fi.vortex_state)
     dt = 2.120e-3
-    u, _, _ = s.run(u, torch.tensor([dt]), 20, sample_every=0)
+    u, _, _ = s.run(u, torch.tensor([dt], dtype=torch.float64), 20, sample_every=0)
     ue = state_at(s, fi.vortex_state, t=20 * dt)
     err = (u - ue).abs().max().item()
     assert err < 1e-4, err
@@ -238,10 +238,10 @@ def test_rk4_temporal_order():
     s = OracleSystem(m, 2, fp, equations="euler")
     u0 = state_at(s, fi.entropy_wave_state, amp=0.3)
     T, n = 1.0, 16
-    ref, _, _ = s.run(u0, torch.tensor([T / (8 * n)]), 8 * n, sample_every=0)
+    ref, _, _ = s.run(u0, torch.tensor([T / (8 * n)], dtype=torch.float64), 8 * n, sample_every=0)
     e = []
     for mult in (1, 2):
-        u, _, _ = s.run(u0, torch.tensor([T / (mult * n)]), mult * n, sample_every=0)
+        u, _, _ = s.run(u0, torch.tensor([T / (mult * n)], dtype=torch.float64), mult * n, sample_every=0)
         e.append((u - ref).abs().max().item())
     assert 12.0 < e[0] / e[1] < 20.0, e
 
