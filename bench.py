@@ -67,6 +67,15 @@ def cavity_batch(n: int = 16, seed: int = 3):
     return m, fp, probes, [x.n_elem for x in ms]
 
 
+def cylinder_workload(n_theta=160, n_r=128, p=4, q=4, seed=1):
+    """O-grid around a unit-diameter cylinder, radius 0.5 to 30, radial stretching 1.04, interior
+    corners perturbed <= 5 % of the local spacing, Re 1000, M 0.2, probe 3 D above."""
+    import fr_inputs as fi
+    m = fi.o_grid(n_theta, n_r, r0=0.5, r1=30.0, stretch=1.04, q=q, perturb=0.05, seed=seed)
+    fp = fi.freestream_params(2, 0.2, 1000.0)
+    return m, fp
+
+
 def initial_state(sol, fp, mesh, seed: int):
     import torch
     import fr_inputs as fi
@@ -198,6 +207,102 @@ def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None
     return out
 
 
+def adjoint_ratio(K=200, C=20):
+    """Forward RK4 trajectory with probe sampling vs its checkpointed adjoint (gradient of the
+    time-mean square probe-pressure fluctuation w.r.t. the initial state), cylinder O-grid
+    80 x 64, p = 3, FP64."""
+    import torch
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+    m, fp = cylinder_workload(80, 64, p=3, q=3)
+    probe = np.array([[0.0, 3.0]])
+    sol = Solver(m, 3, fp, equations="ns", probes=probe, max_samples=K, forces=False)
+    u0 = initial_state(sol, fp, m, 9).cuda()
+    dt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
+    # warm-up (graph capture, work allocation)
+    ug = u0.clone().requires_grad_(True)
+    P = FRTrajectory.apply(ug, sol, dt, 4, 2)
+    ((P - P.mean(0)) ** 2).mean(0).sum().backward()
+    torch.cuda.synchronize()
+    ug = u0.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    P = FRTrajectory.apply(ug, sol, dt, K, C)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J = ((P - P.mean(0)) ** 2).mean(0).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = ug.grad
+    return {"forward_s": t1 - t0, "backward_s": t2 - t1, "adjoint_over_forward": (t2 - t1) / (t1 - t0),
+            "forward_plus_adjoint_over_forward": (t2 - t0) / (t1 - t0),
+            "steps": K, "checkpoint_every": C, "quads": m.n_elem, "p": 3, "objective": float(J.detach()),
+            "grad_finite": bool(torch.isfinite(g).all()),
+            "workload": "cylinder O-grid 80 x 64, p=3, FP64, 200 RK4 steps, checkpoint every 20"}
+
+
+def cylinder_precision_drift(n_steps=5000):
+    """FP32 vs FP64 state after n_steps RK4 steps on the 160 x 128 p = 4 cylinder O-grid."""
+    import torch
+    from paper_2312_14167_amd import Solver
+    m, fp = cylinder_workload()
+    probe = np.array([[0.0, 3.0]])
+    out = {}
+    res = {}
+    for prec in ("fp64", "fp32"):
+        sol = Solver(m, 4, fp, equations="ns", precision=prec, probes=probe, max_samples=n_steps, forces=True)
+        u = initial_state(sol, fp, m, 7).to(device="cuda", dtype=sol.dtype)
+        dt = torch.tensor([2e-5], dtype=torch.float64, device="cuda")
+        sol.rk_step(u, dt, 2, sample_every=1)
+        sol.reset_accumulators()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol.rk_step(u, dt, n_steps, sample_every=1)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        info = solver_info(sol)
+        st = sol.probe_oaspl(p_ref=2e-5 * fp.p_inf[0] / 101325.0)
+        res[prec] = u.double()
+        out[prec] = {"gdofs": info[0] * info[1] * info[2] * 4 * n_steps / t / 1e9, "ms_per_step": 1e3 * t / n_steps,
+                     "oaspl_db": float(st["oaspl"][0]), "mean_force": st["mean_force"][0].tolist(),
+                     "finite": bool(torch.isfinite(u).all())}
+        sol.close()
+    a, b = res["fp32"], res["fp64"]
+    rel = float((((a - b) ** 2).sum(dim=(0, 2)).sqrt() / (b ** 2).sum(dim=(0, 2)).sqrt()).max())
+    out["fp32_vs_fp64_rel_l2"] = rel
+    out["steps"] = n_steps
+    out["workload"] = "cylinder O-grid 160 x 128 (20,480 quads), p=4, Re 1000, M 0.2, dt 2e-5"
+    return out
+
+
+def sequential_cavities(bm, bfp, counts, steps, precision="fp32"):
+    """The batched poll's 16 meshes advanced one after the other (16 solvers)."""
+    import torch
+    import fr_inputs as fi
+    from paper_2312_14167_amd import Solver
+    total = 0.0
+    dof = 0
+    for k in range(bm.n_mesh):
+        lo, hi = bm.mesh_elem_begin[k], bm.mesh_elem_begin[k + 1]
+        used = np.unique(bm.elem_nodes[lo:hi])
+        remap = -np.ones(bm.node_xyz.shape[0], dtype=np.int64)
+        remap[used] = np.arange(len(used))
+        mk = fi.MeshDesc(dim=2, q=bm.q, node_xyz=bm.node_xyz[used], elem_nodes=remap[bm.elem_nodes[lo:hi]],
+                         face_bc=bm.face_bc[lo:hi], periodic_vec=np.zeros((0, 2)),
+                         mesh_elem_begin=np.array([0, hi - lo]))
+        fpk = fi.FlowParams(dim=2, rho_inf=bfp.rho_inf[k:k + 1], vel_inf=bfp.vel_inf[k:k + 1],
+                            p_inf=bfp.p_inf[k:k + 1], mu=bfp.mu[k:k + 1])
+        sol = Solver(mk, 4, fpk, equations="ns", precision=precision, probes=np.array([[0.5, 1.79]]),
+                     max_samples=steps + 4, forces=True)
+        u = initial_state(sol, fpk, mk, 5).to(device="cuda", dtype=sol.dtype)
+        dt = torch.full((1,), 1e-5, dtype=torch.float64, device="cuda")
+        total += time_steps(sol, u, dt, steps, 2)
+        info = solver_info(sol)
+        dof += info[0] * info[1] * info[2]
+        sol.close()
+    return {"sec": total, "gdofs": dof * 4 * steps / total / 1e9, "ms_per_step": 1e3 * total / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +310,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-drift", action="store_true", help="skip the 5000-step FP32/FP64 cylinder run")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 192,000 hexes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
@@ -285,8 +391,23 @@ def main():
         bm, bfp, bprobes, counts = cavity_batch()
         rb = run_variant(bm, bfp, "fp32", K, W, probes=bprobes, probe_mesh=np.arange(16))
         log(f"  {rb['gdofs']:.2f} GDoF-stage/s over {bm.n_elem} quads")
+        log("16 sequential FP32 solves of the same meshes")
+        rs = sequential_cavities(bm, bfp, counts, K)
+        log(f"  {rs['gdofs']:.2f} GDoF-stage/s")
         result["variants"]["batched_16_cavities_fp32"] = {
-            "value": rb["gdofs"], "ms_per_step": rb["ms_per_step"], "quads": counts, "total_quads": bm.n_elem}
+            "value": rb["gdofs"], "ms_per_step": rb["ms_per_step"], "quads": counts, "total_quads": bm.n_elem,
+            "sequential_fp32_value": rs["gdofs"], "sequential_fp32_ms_per_step": rs["ms_per_step"],
+            "speedup_vs_sequential_fp32": rs["ms_per_step"] / rb["ms_per_step"]}
+        log("adjoint / forward time (cylinder 80 x 64, p=3, 200 steps)")
+        ra = adjoint_ratio()
+        log(f"  forward {ra['forward_s']:.3f}s backward {ra['backward_s']:.3f}s ratio {ra['adjoint_over_forward']:.2f}")
+        result["variants"]["adjoint"] = ra
+        if not args.no_drift:
+            log("FP32 vs FP64 after 5000 steps (cylinder 160 x 128, p=4)")
+            rd = cylinder_precision_drift()
+            log(f"  rel L2 {rd['fp32_vs_fp64_rel_l2']:.3e}; fp64 {rd['fp64']['gdofs']:.2f}, "
+                f"fp32 {rd['fp32']['gdofs']:.2f} GDoF-stage/s")
+            result["variants"]["cylinder_5000_steps"] = rd
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline()

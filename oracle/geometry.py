@@ -128,6 +128,7 @@ def locate_point(xp: np.ndarray, node_xyz: np.ndarray, elem_nodes: np.ndarray, d
         xi = np.zeros(dim)
         Xe = Xe_all[e]
         ok = False
+        polish = 0
         for _ in range(60):
             phi, dphi = geometry_basis(dim, q, xi[None, :])
             x = phi[0] @ Xe
@@ -139,9 +140,14 @@ def locate_point(xp: np.ndarray, node_xyz: np.ndarray, elem_nodes: np.ndarray, d
             xi = xi - dxi
             if np.max(np.abs(xi)) > 3.0:
                 break
-            if np.max(np.abs(dxi)) < 1e-14:
+            # converged to 1e-12 in reference coordinates, then two polishing iterations (round-off
+            # in x limits |dxi| to ~eps |x| / h, above 1e-14 for small elements far from the origin)
+            if ok:
+                polish += 1
+                if polish == 2:
+                    break
+            elif np.max(np.abs(dxi)) < 1e-12:
                 ok = True
-                break
         if ok and np.max(np.abs(xi)) <= 1.0 + tol_in:
             return int(e), xi
     raise ValueError(f"point {xp} is outside every element")

@@ -33,20 +33,19 @@ class FRTrajectory(torch.autograd.Function):
     def backward(ctx, p_bar):
         sol, dt, K, C = ctx.solver, ctx.dt, ctx.K, ctx.C
         p_bar = p_bar.detach().to(torch.float64).contiguous()
-        ub = torch.zeros(sol.shape, dtype=sol.dtype, device=p_bar.device)   # dJ/du_K = 0
+        dev = p_bar.device
+        ub = torch.zeros(sol.shape, dtype=sol.dtype, device=dev)   # dJ/du_K = 0
+        states = torch.empty((C,) + sol.shape, dtype=sol.dtype, device=dev)      # reused by every segment
+        stages = torch.empty((C, 3) + sol.shape, dtype=sol.dtype, device=dev)
         for s0 in reversed(range(0, K, C)):
             s1 = min(s0 + C, K)
             u = ctx.ckpts[s0].clone()
-            states, stages = [], []
             for n in range(s0, s1):
-                states.append(u.clone())
-                st = torch.empty((3,) + sol.shape, dtype=sol.dtype, device=u.device)
-                sol.rk_step_stages(u, dt, st)
-                stages.append(st)
+                states[n - s0].copy_(u)
+                sol.rk_step_stages(u, dt, stages[n - s0])
             for n in reversed(range(s0, s1)):
-                un, st = states[n - s0], stages[n - s0]
-                sol.rk_step_vjp(un, dt, ub, st)
-                sol.probe_vjp(un, p_bar[n], ub)
+                sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0])
+                sol.probe_vjp(states[n - s0], p_bar[n], ub)
         return ub, None, None, None, None
 
 

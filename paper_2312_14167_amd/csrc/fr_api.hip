@@ -17,7 +17,7 @@ struct Dispatch {
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
   void (*step_record)(const fr_solver *, void *, const double *, void *, hipStream_t);
   void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
-  void (*rk_adj_combine)(const fr_solver *, const void *, const void *, void *, void *, double, double,
+  void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
                          const double *, hipStream_t);
   void (*zero)(const fr_solver *, void *, hipStream_t);
 };
@@ -476,18 +476,17 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
       d.step_record(s, TMP, dt, STG, st);
       Y = STG;
     }
-    HIP_OK(hipMemcpyAsync(A, u_bar, nb, hipMemcpyDeviceToDevice, st));
     // u_{n+1} = u_n + dt/6 (k1 + 2 k2 + 2 k3 + k4); k_{s} = R(y_s), y1 = u_n, y2 = u_n + dt/2 k1,
-    // y3 = u_n + dt/2 k2, y4 = u_n + dt k3.  Reverse:
+    // y3 = u_n + dt/2 k2, y4 = u_n + dt k3.  Reverse, with a = u_bar on entry:
+    //   k4_bar = dt/6 a;  z_s = (dR/du (y_s))^T k_s_bar;  u_bar += z_s;
+    //   k_{s-1}_bar = dt (w_{s-1} a + c_{s-1} z_s)  with w = (1/6, 1/3, 1/3), c = (1/2, 1/2, 1)
     const void *ys[4] = {u_n, Y, Y + nb, Y + 2 * nb};
-    const double cA[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};  // weight of A in k_bar_s
-    const double cZ[4] = {0.5, 0.5, 1.0, 0.0};                          // y_{s+1} = u + cZ[s] dt k_s
-    d.rk_adj_combine(s, A, nullptr, KB, u_bar, cA[3], 0.0, dt, st);    // k4_bar = dt/6 a
+    const double cA[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double cZ[4] = {0.5, 0.5, 1.0, 0.0};
+    d.rk_adj_combine(s, A, nullptr, KB, u_bar, Z, cA[3], 0.0, dt, st);  // A = a, KB = dt/6 a, Z = 0
     for (int k = 3; k >= 0; --k) {
-      d.zero(s, Z, st);
       if (!launch_vjp(s, ys[k], KB, Z, s->vjp_work, st)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
-      // u_bar += z_k; k_{k-1}_bar = dt (cA a + cZ[k-1] z_k)
-      d.rk_adj_combine(s, A, Z, KB, u_bar, k > 0 ? cA[k - 1] : 0.0, k > 0 ? cZ[k - 1] : 0.0, dt, st);
+      d.rk_adj_combine(s, A, Z, KB, u_bar, nullptr, k > 0 ? cA[k - 1] : 0.0, k > 0 ? cZ[k - 1] : 0.0, dt, st);
     }
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {

@@ -507,6 +507,7 @@ Probe locate_probe(const MeshIn &m, const Ops1D &o, const double *xp, int mesh) 
     if (!near) continue;
     double xi[3] = {0.0, 0.0, 0.0};
     bool ok = false;
+    int polish = 0;
     for (int it = 0; it < 60; ++it) {
       std::vector<double> ref(xi, xi + d);
       GeoBasis b = geo_basis(d, m.q, ref);
@@ -525,7 +526,13 @@ Probe locate_probe(const MeshIn &m, const Ops1D &o, const double *xp, int mesh) 
         mxi = std::max(mxi, std::fabs(xi[k]));
       }
       if (mxi > 3.0) break;
-      if (mx < 1e-14) { ok = true; break; }
+      // converged to 1e-12 in reference coordinates, then two polishing iterations (round-off in x
+      // limits |dxi| to ~eps |x| / h, above 1e-14 for small elements far from the origin)
+      if (ok) {
+        if (++polish == 2) break;
+      } else if (mx < 1e-12) {
+        ok = true;
+      }
     }
     double mxi = 0.0;
     for (int k = 0; k < d; ++k) mxi = std::max(mxi, std::fabs(xi[k]));

@@ -609,17 +609,26 @@ __global__ __launch_bounds__(256) void k_probe_vjp(const T *__restrict__ u, cons
   }
 }
 
-// RK4 adjoint combination: kb = dt (ca a + cz z); ub += z
+// RK4 adjoint combination.  init (z == nullptr): a = ub; kb = dt ca ub; zz = 0.
+// otherwise: kb = dt (ca a + cz z); ub += z; z = 0 (ready for the next accumulation)
 template <typename T>
-__global__ void k_rk_adj_combine(const T *__restrict__ a, const T *__restrict__ z, T *__restrict__ kb,
-                                 T *__restrict__ ub, double ca, double cz, const double *__restrict__ dt,
+__global__ void k_rk_adj_combine(T *__restrict__ a, T *__restrict__ z, T *__restrict__ kb, T *__restrict__ ub,
+                                 T *__restrict__ zz, double ca, double cz, const double *__restrict__ dt,
                                  const int32_t *__restrict__ elem_mesh, int64_t per_elem, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const T d = (T)dt[elem_mesh[i / per_elem]];
-  const T zi = z ? z[i] : T(0);
-  kb[i] = d * ((T)ca * a[i] + (T)cz * zi);
-  if (z) ub[i] += zi;
+  if (!z) {
+    const T ai = ub[i];
+    a[i] = ai;
+    kb[i] = d * (T)ca * ai;
+    zz[i] = T(0);
+  } else {
+    const T zi = z[i];
+    kb[i] = d * ((T)ca * a[i] + (T)cz * zi);
+    ub[i] += zi;
+    z[i] = T(0);
+  }
 }
 
 template <typename T>
@@ -793,7 +802,7 @@ struct Dispatch {
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
   void (*step_record)(const fr_solver *, void *, const double *, void *, hipStream_t);
   void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
-  void (*rk_adj_combine)(const fr_solver *, const void *, const void *, void *, void *, double, double,
+  void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
                          const double *, hipStream_t);
   void (*zero)(const fr_solver *, void *, hipStream_t);
 };
@@ -815,11 +824,11 @@ Dispatch make_dispatch() {
       k_probe_vjp<D, P, T><<<1, 256, 0, st>>>((const T *)u, s->probe_elem, s->probe_w, s->n_probe,
                                               s->gamma - 1.0, pbar, (T *)ub);
   };
-  d.rk_adj_combine = [](const fr_solver *s, const void *a, const void *z, void *kb, void *ub, double ca, double cz,
+  d.rk_adj_combine = [](const fr_solver *s, void *a, void *z, void *kb, void *ub, void *zz, double ca, double cz,
                         const double *dt, hipStream_t st) {
     using S = Shape<D, P>;
     const int64_t per = (int64_t)S::NV * S::Ns, n = s->Ne * per;
-    k_rk_adj_combine<T><<<nblk(n, 256), 256, 0, st>>>((const T *)a, (const T *)z, (T *)kb, (T *)ub, ca, cz, dt,
+    k_rk_adj_combine<T><<<nblk(n, 256), 256, 0, st>>>((T *)a, (T *)z, (T *)kb, (T *)ub, (T *)zz, ca, cz, dt,
                                                        s->elem_mesh, per, n);
   };
   d.zero = [](const fr_solver *s, void *p, hipStream_t st) {
