@@ -50,7 +50,7 @@ def test_trajectory_gradient_matches_oracle_and_fd(gpu):
     g = ug.grad
     # J is the variance of a signal p ~ p_inf = 17.9 with fluctuations sigma ~ 5e-3: its relative
     # round-off is ~ eps (p_inf / sigma)^2 ~ 3e-9 per operation, hence the 1e-6 bound
-    assert abs(float(J) - float(Jref)) <= 1e-6 * abs(float(Jref)), (float(J), float(Jref))
+    assert abs(float(J.detach()) - float(Jref.detach())) <= 1e-6 * abs(float(Jref)), (float(J.detach()), float(Jref.detach()))
     pref = torch.stack(ps).detach()
     dp = float((P.detach().cpu() - pref).abs().max())
     sig = float(pref.std())
@@ -94,3 +94,52 @@ def test_rk_step_vjp_recompute_equals_recorded_stages(gpu):
     b2 = a.clone()
     sol.rk_step_vjp(u0, dtt, b2, None)
     assert torch.equal(b1, b2)
+
+
+def test_adjoint_full_size_cylinder_80x64(gpu):
+    """The adjoint workload at full size: cylinder O-grid 80 x 64, p = 3, FP64.
+    (a) 200 RK4 steps with checkpoints every 20: the adjoint directional derivative against central
+        differences of the GPU objective along 50 seeded random directions in u0;
+    (b) 20 steps: the gradient against reverse-mode autograd of the oracle trajectory."""
+    import bench
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+    m, fp = bench.cylinder_workload(80, 64, p=3, q=3)
+    probes = [[0.0, 3.0]]
+    sol = Solver(m, 3, fp, equations="ns", probes=probes, max_samples=200)
+    u0 = bench.initial_state(sol, fp, m, 9).to(gpu)
+    dtt = torch.tensor([1e-4], dtype=torch.float64, device=gpu)
+    K, C = 200, 20
+    ug = u0.clone().requires_grad_(True)
+    J = _objective(FRTrajectory.apply(ug, sol, dtt, K, C))
+    J.backward()
+    g = ug.grad
+    rng = np.random.default_rng(50)
+    worst = 0.0
+    for _ in range(50):
+        v = torch.tensor(rng.normal(size=u0.shape), device=gpu)
+        v = v / v.norm() * u0.norm() * 1e-3
+        eps = 1e-3
+        with torch.no_grad():
+            Jp = _objective(FRTrajectory.apply(u0 + eps * v, sol, dtt, K, C))
+            Jm = _objective(FRTrajectory.apply(u0 - eps * v, sol, dtt, K, C))
+        fd = float((Jp - Jm) / (2 * eps))
+        ad = float((g * v).sum())
+        worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-300))
+    print(f"80x64 adjoint: worst relative FD mismatch over 50 directions {worst:.3e}")
+    assert worst <= 1e-4, worst
+    # oracle gradient over 20 steps at the same size
+    s = OracleSystem(m, 3, fp, equations="ns", probes=probes)
+    K2 = 20
+    uo = u0.cpu().clone().requires_grad_(True)
+    u, ps = uo, []
+    for n in range(K2):
+        ps.append(s.probe_pressure(u))
+        u = s.rk4_step(u, torch.tensor([1e-4], dtype=torch.float64))
+    _objective(torch.stack(ps)).backward()
+    ug2 = u0.clone().requires_grad_(True)
+    _objective(FRTrajectory.apply(ug2, sol, dtt, K2, C)).backward()
+    err = float((ug2.grad.cpu() - uo.grad).norm() / uo.grad.norm())
+    print(f"80x64 adjoint, 20 steps: gradient rel L2 vs oracle {err:.3e}")
+    assert err <= 1e-9, err

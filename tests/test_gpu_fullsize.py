@@ -1,0 +1,200 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+The residual of an element depends only on the elements within two faces of it (its own state,
+its neighbours' flux-point states and their viscous normal fluxes, which depend on their
+neighbours' flux-point states).  So the FP64 oracle, run on the index-space box of radius 2
+around a sampled element (faces leaving the box tagged far field), reproduces that element's
+residual exactly, and is compared with the full-size GPU residual element by element.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import fr_inputs as fi
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _patch(mesh, centre, nbr_boxes):
+    """Sub-mesh of the elements whose grid index lies in one of the boxes (lists of per-direction
+    index sets); AUTO faces whose partner is outside become far field."""
+    gi = mesh.info["grid_index"]
+    keep = np.zeros(mesh.n_elem, dtype=bool)
+    for box in nbr_boxes:
+        m = np.ones(mesh.n_elem, dtype=bool)
+        for k, idx in enumerate(box):
+            m &= np.isin(gi[:, k], idx)
+        keep |= m
+    sel = np.nonzero(keep)[0]
+    used = np.unique(mesh.elem_nodes[sel])
+    remap = -np.ones(mesh.node_xyz.shape[0], dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    sub = fi.MeshDesc(dim=mesh.dim, q=mesh.q, node_xyz=mesh.node_xyz[used], elem_nodes=remap[mesh.elem_nodes[sel]],
+                      face_bc=mesh.face_bc[sel].copy(), periodic_vec=mesh.periodic_vec.copy(),
+                      mesh_elem_begin=np.array([0, len(sel)], dtype=np.int64))
+    return sel, sub
+
+
+def _close_patch(sub, oracle_cls, p, fp):
+    """Tag AUTO faces of the patch without a partner inside it (they lie >= 3 faces from the
+    centre) as far field, then build the oracle on the patch."""
+    import itertools
+
+    from scipy.spatial import cKDTree
+    d, q = sub.dim, sub.q
+    nf = 2 * d
+    cents = np.zeros((sub.n_elem, nf, d))
+    for f in range(nf):
+        k, side = f // 2, f % 2
+        corners = []
+        for bits in itertools.product([0, q], repeat=d - 1):
+            idx, b = [0] * d, 0
+            for m in range(d):
+                if m == k:
+                    idx[m] = q * side
+                else:
+                    idx[m] = bits[b]
+                    b += 1
+            corners.append(sum(idx[m] * (q + 1) ** m for m in range(d)))
+        cents[:, f] = sub.node_xyz[sub.elem_nodes[:, corners]].mean(axis=1)
+    auto = np.argwhere(sub.face_bc == fi.FACE_AUTO)
+    pts = cents[auto[:, 0], auto[:, 1]]
+    tree = cKDTree(pts)
+    scale = float(np.ptp(sub.node_xyz, axis=0).max())
+    shifts = [np.zeros(d)] + [sg * v for v in sub.periodic_vec for sg in (1.0, -1.0)]
+    for a, (e, f) in enumerate(auto):
+        found = False
+        for sh in shifts:
+            if any(b != a for b in tree.query_ball_point(pts[a] + sh, 1e-9 * scale)):
+                found = True
+                break
+        if not found:
+            sub.face_bc[e, f] = fi.BC_FARFIELD
+    return oracle_cls(sub, p, fp, equations="ns")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _tol(s, le, Rref_e, p_inf):
+    """Round-off bound for one element's residual.  R is a difference of flux terms of size
+    ~ p_inf |S| / J, so relative to ||R_e|| round-off is amplified by
+    kappa_flux = p_inf max|S/J| / max|R_e|; the metric terms are differences of node coordinates
+    of size |x| over an element of size h ~ 2 J^(1/d), amplifying by kappa_geo = max|x| / h; the
+    Lagrange derivative and lifting operators have norms ~ (p+1)^2.
+    Bound: 1e-14 (p+1)^2 kappa_flux kappa_geo (about 100 unit round-offs), never below 1e-11."""
+    d = s.dim
+    SJ = (s.geo["S"][le].abs().amax(dim=(-1, -2)) / s.geo["J"][le]).max().item()
+    kappa_flux = p_inf * SJ / max(float(np.abs(Rref_e).max()), 1e-300)
+    h = 2.0 * float(s.geo["J"][le].min()) ** (1.0 / d)
+    kappa_geo = float(s.geo["x_s"][le].abs().max()) / h
+    return max(1e-11, 1e-14 * (s.p + 1) ** 2 * kappa_flux * kappa_geo)
+
+
+def test_naca_cgrid_full_size_sampled_residual(gpu):
+    import bench
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    mesh, fp, _ = bench.naca_workload(scale=1.0)
+    sol = Solver(mesh, 4, fp, equations="ns", precision="fp64")
+    u = bench.initial_state(sol, fp, mesh, 5)
+    R = sol.rhs(u.to(gpu)).cpu()
+    gi = mesh.info["grid_index"]
+    na, nn, nz = gi[:, 0].max() + 1, gi[:, 1].max() + 1, gi[:, 2].max() + 1
+    rng = np.random.default_rng(0)
+    # wall next to the trailing edge, wake cut, leading edge, outflow, outer boundary, random interior
+    picks = [(40, 0, 0), (20, 0, 5), (100, 0, 11), (0, 10, 3), (150, 79, 6),
+             tuple(int(x) for x in rng.integers([0, 0, 0], [na, nn, nz]))]
+    xs = sol.solpt_coords()
+    for (i, j, k) in picks:
+        e = int(np.nonzero((gi[:, 0] == i) & (gi[:, 1] == j) & (gi[:, 2] == k))[0][0])
+        ib = [x for x in range(i - 2, i + 3) if 0 <= x < na]
+        jb = [x for x in range(j - 2, j + 3) if 0 <= x < nn]
+        kb = [x % nz for x in range(k - 2, k + 3)]
+        boxes = [[ib, jb, kb]]
+        if j <= 2:  # across the wake cut
+            boxes.append([[na - 1 - x for x in ib if 0 <= na - 1 - x < na], [0, 1, 2], kb])
+        sel, sub = _patch(mesh, e, boxes)
+        s = _close_patch(sub, OracleSystem, 4, fp)
+        le = int(np.nonzero(sel == e)[0][0])
+        up = u[sel]
+        Rp = s.residual(up)
+        np.testing.assert_allclose(s.solpt_coords()[le], xs[e], atol=1e-12)
+        err = _rel(R[e].numpy(), Rp[le].numpy())
+        tol = _tol(s, le, Rp[le].numpy(), fp.p_inf[0])
+        print(f"element {e} grid {(i, j, k)}: patch of {len(sel)}; residual rel L2 {err:.3e} (bound {tol:.1e})")
+        assert err <= tol, err
+
+
+def test_cylinder_ogrid_full_size_sampled_residual_and_fp32(gpu):
+    import bench
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    mesh, fp = bench.cylinder_workload()
+    sol = Solver(mesh, 4, fp, equations="ns", precision="fp64")
+    u = bench.initial_state(sol, fp, mesh, 7)
+    R = sol.rhs(u.to(gpu)).cpu()
+    gi = mesh.info["grid_index"]
+    nr, nt = gi[:, 0].max() + 1, gi[:, 1].max() + 1
+    for (ir, it) in [(0, 0), (0, 77), (64, 40), (127, 120), (3, 159)]:
+        e = int(np.nonzero((gi[:, 0] == ir) & (gi[:, 1] == it))[0][0])
+        rb = [x for x in range(ir - 2, ir + 3) if 0 <= x < nr]
+        tb = [x % nt for x in range(it - 2, it + 3)]
+        sel, sub = _patch(mesh, e, [[rb, tb]])
+        s = _close_patch(sub, OracleSystem, 4, fp)
+        le = int(np.nonzero(sel == e)[0][0])
+        Rp = s.residual(u[sel])[le].numpy()
+        err = _rel(R[e].numpy(), Rp)
+        tol = _tol(s, le, Rp, fp.p_inf[0])
+        print(f"cylinder element {(ir, it)}: residual rel L2 {err:.3e} (bound {tol:.1e})")
+        assert err <= tol, err
+    # FP32 at full size: one RK4 step against the FP64 GPU step (itself pinned above)
+    dt = torch.tensor([2e-5], dtype=torch.float64, device=gpu)
+    u64 = u.to(gpu).clone()
+    sol.rk_step(u64, dt, 1)
+    s32 = Solver(mesh, 4, fp, equations="ns", precision="fp32")
+    u32 = u.float().to(gpu).clone()
+    s32.rk_step(u32, dt, 1)
+    # Relative L2 of density, momentum (as one vector: a per-component measure would depend on the
+    # free stream's orientation, and a cross-stream component is ~1e-3 of the momentum) and energy.
+    e2 = ((u32.double() - u64) ** 2).sum(dim=(0, 2))
+    n2 = (u64 ** 2).sum(dim=(0, 2))
+    d = sol.dim
+    grouped = [(0, 1), (1, 1 + d), (1 + d, 2 + d)]
+    rel = max(float((e2[a:b].sum() / n2[a:b].sum()).sqrt()) for a, b in grouped)
+    per_comp = (e2 / n2).sqrt().cpu().numpy()
+    whole = float((e2.sum() / n2.sum()).sqrt())
+    print(f"cylinder full size: FP32 vs FP64 after one step rel L2 {rel:.3e} (whole state {whole:.3e}, "
+          f"per component {np.array2string(per_comp, precision=2)})")
+    assert rel <= 1e-5
+
+
+def test_vortex_full_size_20_steps(gpu):
+    """The 32 x 32 p = 3 isentropic-vortex case in full: 20 RK4 steps at dt = 2.12e-3 against the
+    oracle (<= 1e-12) and the translated closed form (same error as the oracle's)."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m = fi.periodic_box(2, 32, q=1)
+    fp = fi.vortex_params()
+    s = OracleSystem(m, 3, fp, equations="euler")
+    x = s.solpt_coords()
+    u0 = torch.tensor(fi.vortex_state(x)).permute(0, 2, 1).contiguous()
+    dt = 2.12e-3
+    uref, _, _ = s.run(u0, torch.tensor([dt], dtype=torch.float64), 20, sample_every=0)
+    sol = Solver(m, 3, fp, equations="euler")
+    u = u0.to(gpu).clone()
+    sol.rk_step(u, torch.tensor([dt], dtype=torch.float64, device=gpu), 20)
+    ue = torch.tensor(fi.vortex_state(x, t=20 * dt)).permute(0, 2, 1)
+    num = ((u.cpu() - uref) ** 2).sum(dim=(0, 2)).sqrt()
+    den = (uref ** 2).sum(dim=(0, 2)).sqrt()
+    assert float((num / den).max()) <= 1e-12
+    eg = float((u.cpu() - ue).abs().max())
+    eo = float((uref - ue).abs().max())
+    print(f"vortex: |GPU - exact| {eg:.3e}, |oracle - exact| {eo:.3e}")
+    assert abs(eg - eo) <= 1e-12 and eg < 1e-4
