@@ -90,19 +90,26 @@ def initial_state(sol, fp, mesh, seed: int):
 
 
 # ------------------------------------------------------------------------------------ accounting
-def algorithmic_bytes(info, dim, T, eq):
+def algorithmic_bytes(info, dim, T, eq, ldg_beta=0.5):
     """Minimum HBM bytes per launch of each kernel (every input read once, every output written
-    once; RK kernels averaged over the four stages of a step)."""
+    once; RK kernels averaged over the four stages of a step).  With the one-sided LDG flux
+    (beta = +-1/2) only one side of each interior face pair takes the neighbour's u_f and
+    supplies a viscous normal flux, so only that side's values move."""
     Ne, NV, Ns, Nf, npair, nbnd, nwall, nmesh = info
     NM = dim * dim + 1
     I = 4
+    sides = 1 if abs(ldg_beta) == 0.5 else 2
     b = {}
     b["interp"] = Ne * (NV * Ns + NV * Nf) * T
-    vis = NV if eq == "ns" else 0
-    b["face_flux"] = (npair * ((2 * NV + 2 * vis + dim + 1) * T + 2 * I) + nbnd * ((NV + vis + dim + 1) * T + 2 * I)
+    vis = NV * sides if eq == "ns" else 0
+    b["face_flux"] = (npair * ((2 * NV + vis + dim + 1) * T + 2 * I)
+                      + nbnd * ((NV + (NV if eq == "ns" else 0) + dim + 1) * T + I)
                       + (2 * npair + nbnd) * NV * T)
-    # u, neighbour u_f, metrics, own normals, neighbour codes -> viscous normal flux, volume divergence
-    b["ns_grad"] = Ne * ((NV * Ns + NV * Nf + NM * Ns + dim * Nf + NV * Nf + NV * Ns) * T + Nf * I + I)
+    # u, metrics, neighbour codes -> vol; neighbour u_f where the common solution takes it; own
+    # normals and viscous normal flux where the common viscous flux takes it
+    needed = sides * npair + nbnd
+    b["ns_grad"] = (Ne * ((2 * NV * Ns + NM * Ns) * T + Nf * I)
+                    + sides * npair * NV * T + needed * (dim + NV) * T)
     rk_rw = (4 * (NV * Ns + NV * Nf + Ns + NV * Ns) + 3 * NV * Ns       # reads: vol/u, fhat, invJ, u0; acc
              + 4 * NV * Nf + 3 * 2 * NV * Ns + NV * Ns) / 4.0            # writes: u_f, acc + stage state / u0
     b["div_rk"] = Ne * (rk_rw * T + I)
@@ -343,7 +350,7 @@ def main():
     r64 = run_variant(mesh, fp, "fp64", K, W, probes=probe, profile=True)
     log(f"  {r64['gdofs']:.2f} GDoF-stage/s, {r64['ms_per_step']:.2f} ms/step")
     info = r64["info"]
-    ab = algorithmic_bytes(info, 3, 8, "ns")
+    ab = algorithmic_bytes(info, 3, 8, "ns", fp.ldg_beta)
     kern = r64["kernels"]
     dom = max(kern, key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]

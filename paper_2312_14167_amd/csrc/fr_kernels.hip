@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_interp(const T *__restrict__ u, T *__re
 // the boundary ghost.  NS: minus the LDG viscous flux assembled from the per-side viscous normal
 // fluxes fvn (each side's F_vis(u, grad u) . n_out, boundary points already in boundary form).
 template <int D, int P, typename T, bool NS>
-__global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, const T *__restrict__ fvn,
+__global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, const T *__restrict__ fvn,
                                                    const int32_t *__restrict__ pairL, const int32_t *__restrict__ pairR,
                                                    const T *__restrict__ pnrm, int64_t npair,
                                                    const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
@@ -81,10 +81,17 @@ __global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, con
     if (NS) {
       // F^_vis . n_L = (1/2 - b) fvn_L + (1/2 + b) (-fvn_R) - tau (u_L - u_R)
       const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
-      for (int v = 0; v < NV; ++v) {
-        const T fl = fvn[(eL * NV + v) * Nf + fL];
-        const T fr = fvn[(eR * NV + v) * Nf + fR];
-        F[v] -= wl * fl - wr * fr - ph.tau * (uL[v] - uR[v]);
+      // a side with zero weight (one-sided LDG) never had its fvn computed: not read
+      if (wl == T(0)) {
+        for (int v = 0; v < NV; ++v) F[v] -= -wr * fvn[(eR * NV + v) * Nf + fR] - ph.tau * (uL[v] - uR[v]);
+      } else if (wr == T(0)) {
+        for (int v = 0; v < NV; ++v) F[v] -= wl * fvn[(eL * NV + v) * Nf + fL] - ph.tau * (uL[v] - uR[v]);
+      } else {
+        for (int v = 0; v < NV; ++v) {
+          const T fl = fvn[(eL * NV + v) * Nf + fL];
+          const T fr = fvn[(eR * NV + v) * Nf + fR];
+          F[v] -= wl * fl - wr * fr - ph.tau * (uL[v] - uR[v]);
+        }
       }
     }
     for (int v = 0; v < NV; ++v) {
@@ -118,10 +125,13 @@ __global__ __launch_bounds__(256) void k_face_flux(const T *__restrict__ uf, con
 template <int D, int P, typename T>
 struct GradTile {
   using S = Shape<D, P>;
-  // region A: u + (u^ - u_f), later the gradient / transformed flux; region B: own u_f
-  static constexpr int LA = cmax(S::NV * S::Ns + S::NV * S::Nf, D * S::NV * S::Ns);
-  static constexpr int LE = LA + S::NV * S::Nf;
-  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  // per element: the state [NV][Ns], kept to the flux-point viscous phase, then one region that
+  // holds u^ - u_f [NV][Nf], the physical gradient [D][NV][Ns] and the transformed flux
+  // [D][NV][Ns] in turn.  E is chosen so that four workgroups fit in 160 KB of LDS.
+  static constexpr int LU = S::NV * S::Ns;
+  static constexpr int LG = cmax(S::NV * S::Nf, D * S::NV * S::Ns);
+  static constexpr int LE = LU + LG;
+  static constexpr int E = cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
 };
 
@@ -141,13 +151,22 @@ struct EulerTile {
   static constexpr int BS = round64(E * S::Ns);
 };
 
+// Which side of an interior face pair supplies the viscous normal flux of the LDG common flux
+// F^_vis = (1/2 - b) F_L + (1/2 + b) F_R: +1 (b = 1/2: the R side only), -1 (b = -1/2: the L side
+// only), 0 (both).  The same side is the one whose common solution u^ takes the neighbour's value.
+template <typename T>
+__device__ __forceinline__ int ldg_flux_side(T beta) {
+  return beta == T(0.5) ? 1 : (beta == T(-0.5) ? -1 : 0);
+}
 
 // NS volume kernel.  Per element tile:
 //   own u_f = M0 u; LDG common solution from the neighbour's u_f (or the boundary state);
 //   corrected gradient grad_xi u = D_k u + s_f g_R'(s_f xi)(u^ - u_f); grad_x u = J^-1 S^T grad_xi u;
-//   viscous normal flux at every own flux point fvn = F_vis(u_f, M0 grad_x u) . n_out (walls:
-//   zero-velocity state, no heat flux; far field: Riemann state);
-//   F~_k = S_k . (F_inv - F_vis) at solution points; vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}).
+//   viscous normal flux fvn = F_vis(u_f, M0 grad_x u) . n_out at the own flux points whose value
+//   the common viscous flux uses (walls: zero-velocity state, no heat flux; far field: Riemann
+//   state); F~_k = S_k . (F_inv - F_vis) at solution points;
+//   vol = sum_k D~_k F~_k with D~ = D - (interior part of the correction), i.e.
+//   vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}).
 template <int D, int P, typename T>
 __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
@@ -156,24 +175,44 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     T *__restrict__ vol, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = GradTile<D, P, T>;
-  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM, NFACE = 2 * D;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
+  __shared__ int s_face[E * NFACE];
+  __shared__ int s_nface;
   stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  T *lu = lds;                   // [E][NV][Ns]
-  T *ldu = lds + E * NV * Ns;    // [E][NV][Nf]  u^ - u_f
-  T *luf = lds + E * TL::LA;     // [E][NV][Nf]  own u_f
+  T *lu = lds;                // [E][NV][Ns]
+  T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][D][NV][Ns] gradient / F~
   tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
+  const int side = ldg_flux_side(ph.beta);
+  // list of faces whose viscous normal flux is consumed (boundary faces, and interior faces on
+  // the flux side); every flux point of a face shares its partner face and its side
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int cnt = 0;
+    for (int b = 0; b < ne * NFACE; b += 64) {
+      const int fi = b + lane;
+      bool need = false;
+      if (fi < ne * NFACE) {
+        const int32_t code = nbr[(e0 + fi / NFACE) * Nf + (fi % NFACE) * Nfp];
+        need = code < 0 || side == 0 || (((code & NBR_R_BIT) != 0) == (side > 0));
+      }
+      const unsigned long long m = __ballot(need);
+      if (need) s_face[cnt + __popcll(m & ((1ull << lane) - 1ull))] = fi;
+      cnt += __popcll(m);
+    }
+    if (lane == 0) s_nface = cnt;
+  }
   __syncthreads();
   const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
   for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
     const int el = idx / Nf, fp = idx % Nf;
     const int64_t e = e0 + el;
-    int base, stride, side;
-    line_of_fpt<D, P>(fp, base, stride, side);
-    const T *lv = side ? ops.lp : ops.lm;
+    int base, stride, fs;
+    line_of_fpt<D, P>(fp, base, stride, fs);
+    const T *lv = fs ? ops.lp : ops.lm;
     T uo[NV], uh[NV];
     for (int v = 0; v < NV; ++v) {
       const T *lin = lu + (el * NV + v) * Ns + base;
@@ -181,7 +220,6 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
 #pragma unroll
       for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
       uo[v] = s;
-      luf[(el * NV + v) * Nf + fp] = s;
     }
     const int32_t code = nbr[e * Nf + fp];
     if (code >= 0) {
@@ -189,8 +227,9 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
       const int64_t e2 = c / Nf;
       const int f2 = c % Nf;
       const bool isR = (code & NBR_R_BIT) != 0;
+      const T wn = isR ? wl : wr;  // weight of the neighbour's value; zero on the one-sided LDG's other side
       for (int v = 0; v < NV; ++v) {
-        const T un = uf[(e2 * NV + v) * Nf + f2];
+        const T un = wn != T(0) ? uf[(e2 * NV + v) * Nf + f2] : T(0);
         uh[v] = isR ? wl * un + wr * uo[v] : wl * uo[v] + wr * un;
       }
     } else {
@@ -203,15 +242,13 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
         farfield<D>(uo, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, uh);
       }
     }
-    for (int v = 0; v < NV; ++v) ldu[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
+    for (int v = 0; v < NV; ++v) lw[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
   }
   __syncthreads();
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
   const int64_t e = e0 + el;
-  // per solution point: corrected gradient, then the transformed flux right away, so that only
-  // F~ (dim x nv values) stays live through the flux-point phase below
-  T ft[D][NV];
+  // corrected physical gradient at the own solution point
   T gx[D][NV];
   if (act) {
     T Sm[D][D];
@@ -225,44 +262,47 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
       int base, stride, ik, t;
       line_of_sol<D, P>(i, k, base, stride, ik, t);
       const T cm = -ops.gm[ik], cp = ops.gp[ik];
+      T Sk[D];  // row k selected without dynamic indexing into a private array
+      for (int j = 0; j < D; ++j) {
+        Sk[j] = Sm[0][j];
+        for (int q = 1; q < D; ++q)
+          if (k == q) Sk[j] = Sm[q][j];
+      }
       for (int v = 0; v < NV; ++v) {
         const T *lin = lu + (el * NV + v) * Ns + base;
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < P; ++a) s += ops.D[ik * P + a] * lin[a * stride];
-        const T *ld = ldu + (el * NV + v) * Nf;
+        const T *ld = lw + (el * NV + v) * Nf;
         s += cm * ld[(2 * k) * Nfp + t] + cp * ld[(2 * k + 1) * Nfp + t];
-        for (int j = 0; j < D; ++j) gx[j][v] += Sm[k][j] * s;
+        for (int j = 0; j < D; ++j) gx[j][v] += Sk[j] * s;
       }
     }
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) gx[j][v] *= invJ;
-    T uv[NV];
-    for (int v = 0; v < NV; ++v) uv[v] = lu[(el * NV + v) * Ns + i];
-    Visc<D, T> vs;
-    visc_state<D>(uv, &gx[0][0], flow[elem_mesh[e]].mu, ph, true, vs);
-    for (int k = 0; k < D; ++k) {
-      T fi[NV], fv[NV];
-      finv_dot<D>(uv, Sm[k], ph.gm1, fi);
-      fvis_dot<D>(vs, Sm[k], fv);
-      for (int v = 0; v < NV; ++v) ft[k][v] = fi[v] - fv[v];
-    }
   }
   __syncthreads();
-  T *lg = lds;  // [E][D][NV][Ns]
   if (act)
     for (int j = 0; j < D; ++j)
-      for (int v = 0; v < NV; ++v) lg[((el * D + j) * NV + v) * Ns + i] = gx[j][v];
+      for (int v = 0; v < NV; ++v) lw[((el * D + j) * NV + v) * Ns + i] = gx[j][v];
   __syncthreads();
-  // viscous normal flux at every own flux point
-  for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
-    const int elf = idx / Nf, fp = idx % Nf;
+  // viscous normal flux at the flux points of the listed faces
+  const int nfc = s_nface;
+  for (int idx = threadIdx.x; idx < nfc * Nfp; idx += blockDim.x) {
+    const int fc = s_face[idx / Nfp];
+    const int elf = fc / NFACE, fp = (fc % NFACE) * Nfp + idx % Nfp;
     const int64_t ef = e0 + elf;
-    int base, stride, side;
-    line_of_fpt<D, P>(fp, base, stride, side);
-    const T *lv = side ? ops.lp : ops.lm;
+    int base, stride, fs;
+    line_of_fpt<D, P>(fp, base, stride, fs);
+    const T *lv = fs ? ops.lp : ops.lm;
     T st[NV], n[D];
-    for (int v = 0; v < NV; ++v) st[v] = luf[(elf * NV + v) * Nf + fp];
+    for (int v = 0; v < NV; ++v) {
+      const T *lin = lu + (elf * NV + v) * Ns + base;
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+      st[v] = s;
+    }
     for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * D + j) * Nf + fp];
     const int32_t code = nbr[ef * Nf + fp];
     bool heat = true;
@@ -277,7 +317,7 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
       }
       for (int v = 0; v < NV; ++v) st[v] = ub[v];
     }
-    const T *lge = lg + elf * D * NV * Ns + base;
+    const T *lge = lw + elf * D * NV * Ns + base;
     auto gdir = [&](int d, int v) {
       const T *lin = lge + (d * NV + v) * Ns;
       T s = T(0);
@@ -289,31 +329,46 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     fvis_normal_stream<D>(st, gdir, n, flow[elem_mesh[ef]].mu, ph, heat, fv);
     for (int v = 0; v < NV; ++v) fvn[(ef * NV + v) * Nf + fp] = fv[v];
   }
+  // transformed flux F~_k = S_k . (F_inv - F_vis) at the own solution point, from the gradient
+  // held in LDS (no transformed flux is live in registers through the flux-point phase)
+  T ft[D][NV];
+  if (act) {
+    T uv[NV], g[D * NV];
+    for (int v = 0; v < NV; ++v) uv[v] = lu[(el * NV + v) * Ns + i];
+    for (int j = 0; j < D; ++j)
+      for (int v = 0; v < NV; ++v) g[j * NV + v] = lw[((el * D + j) * NV + v) * Ns + i];
+    Visc<D, T> vs;
+    visc_state<D>(uv, g, flow[elem_mesh[e]].mu, ph, true, vs);
+    for (int k = 0; k < D; ++k) {
+      T Sk[D], fi[NV], fv[NV];
+      for (int j = 0; j < D; ++j) Sk[j] = metric[(e * NM + k * D + j) * Ns + i];  // second read: L2
+      finv_dot<D>(uv, Sk, ph.gm1, fi);
+      fvis_dot<D>(vs, Sk, fv);
+      for (int v = 0; v < NV; ++v) ft[k][v] = fi[v] - fv[v];
+    }
+  }
   __syncthreads();
   if (act)
     for (int k = 0; k < D; ++k)
-      for (int v = 0; v < NV; ++v) lg[((el * D + k) * NV + v) * Ns + i] = ft[k][v];
+      for (int v = 0; v < NV; ++v) lw[((el * D + k) * NV + v) * Ns + i] = ft[k][v];
   __syncthreads();
   if (act) {
-    for (int v = 0; v < NV; ++v) {
-      T accv = T(0);
+    T accv[NV];
+    for (int v = 0; v < NV; ++v) accv[v] = T(0);
 #pragma unroll 1
-      for (int k = 0; k < D; ++k) {
-        int base, stride, ik, t;
-        line_of_sol<D, P>(i, k, base, stride, ik, t);
-        const T *lin = lg + ((el * D + k) * NV + v) * Ns + base;
-        T ds = T(0), fm = T(0), fpv = T(0);
+    for (int k = 0; k < D; ++k) {
+      int base, stride, ik, t;
+      line_of_sol<D, P>(i, k, base, stride, ik, t);
+      const T *dt = ops.Dt + ik * P;
+      for (int v = 0; v < NV; ++v) {
+        const T *lin = lw + ((el * D + k) * NV + v) * Ns + base;
+        T ds = T(0);
 #pragma unroll
-        for (int a = 0; a < P; ++a) {
-          const T val = lin[a * stride];
-          ds += ops.D[ik * P + a] * val;
-          fm += ops.lm[a] * val;
-          fpv += ops.lp[a] * val;
-        }
-        accv += ds + ops.gm[ik] * fm - ops.gp[ik] * fpv;
+        for (int a = 0; a < P; ++a) ds += dt[a] * lin[a * stride];
+        accv[v] += ds;
       }
-      vol[(e * NV + v) * Ns + i] = accv;
     }
+    for (int v = 0; v < NV; ++v) vol[(e * NV + v) * Ns + i] = accv[v];
   }
 }
 
@@ -465,16 +520,11 @@ __global__ __launch_bounds__((EulerTile<D, P, T>::BS)) void k_euler_vol_rk(
         int base, stride, ik, t;
         line_of_sol<D, P>(i, k, base, stride, ik, t);
         const T *lin = lF + ((el * D + k) * NV + v) * Ns + base;
-        T ds = T(0), fm = T(0), fpv = T(0);
+        T ds = T(0);
 #pragma unroll
-        for (int a = 0; a < P; ++a) {
-          const T val = lin[a * stride];
-          ds += ops.D[ik * P + a] * val;
-          fm += ops.lm[a] * val;
-          fpv += ops.lp[a] * val;
-        }
+        for (int a = 0; a < P; ++a) ds += ops.Dt[ik * P + a] * lin[a * stride];
         const T *lfv = lf + (el * NV + v) * Nf;
-        accv += ds + ops.gm[ik] * (fm + lfv[(2 * k) * Nfp + t]) + ops.gp[ik] * (lfv[(2 * k + 1) * Nfp + t] - fpv);
+        accv += ds + ops.gm[ik] * lfv[(2 * k) * Nfp + t] + ops.gp[ik] * lfv[(2 * k + 1) * Nfp + t];
       }
       R[v] = -invJ * accv;
     }
@@ -685,17 +735,7 @@ template <int D, int P, typename T>
 struct Engine {
   using S = Shape<D, P>;
 
-  static OpsDev<T, P> ops(const fr_solver *s) {
-    OpsDev<T, P> o;
-    for (int i = 0; i < P * P; ++i) o.D[i] = (T)s->ops.D[i];
-    for (int i = 0; i < P; ++i) {
-      o.lm[i] = (T)s->ops.lm[i];
-      o.lp[i] = (T)s->ops.lp[i];
-      o.gp[i] = (T)s->ops.gp[i];
-      o.gm[i] = (T)s->ops.gm[i];
-    }
-    return o;
-  }
+  static OpsDev<T, P> ops(const fr_solver *s) { return make_ops<T, P>(s->ops); }
   static PhysDev<T> phys(const fr_solver *s) {
     PhysDev<T> p;
     p.gamma = (T)s->gamma;

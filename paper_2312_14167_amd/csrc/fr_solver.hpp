@@ -21,7 +21,27 @@ struct OpsDev {
   T D[P * P];   // D[a*P + b] = l_b'(xi_a)
   T lm[P], lp[P];
   T gp[P], gm[P];  // g_R'(xi_a), g_R'(-xi_a)
+  // derivative with the interior part of the correction folded in:
+  // Dt[a*P + b] = D[a*P + b] + g_R'(-xi_a) l_b(-1) - g_R'(xi_a) l_b(+1)
+  T Dt[P * P];
 };
+
+// device operator tables in precision T (every entry rounded once from the FP64 host tables)
+template <typename T, int P>
+inline OpsDev<T, P> make_ops(const Ops1D &h) {
+  OpsDev<T, P> o;
+  for (int i = 0; i < P * P; ++i) o.D[i] = (T)h.D[i];
+  for (int i = 0; i < P; ++i) {
+    o.lm[i] = (T)h.lm[i];
+    o.lp[i] = (T)h.lp[i];
+    o.gp[i] = (T)h.gp[i];
+    o.gm[i] = (T)h.gm[i];
+  }
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < P; ++b)
+      o.Dt[a * P + b] = (T)(h.D[a * P + b] + h.gm[a] * h.lm[b] - h.gp[a] * h.lp[b]);
+  return o;
+}
 
 template <typename T>
 struct PhysDev {

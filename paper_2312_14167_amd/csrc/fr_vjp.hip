@@ -590,15 +590,10 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       T ftb[NV];
       for (int v = 0; v < NV; ++v) {
         const T *lin = lvb + (el * NV + v) * Ns + base;
-        T sd = T(0), sm = T(0), sp = T(0);
+        T sd = T(0);  // transpose of the divergence with the folded correction
 #pragma unroll
-        for (int a = 0; a < P; ++a) {
-          const T w = lin[a * stride];
-          sd += ops.D[a * P + ik] * w;
-          sm += ops.gm[a] * w;
-          sp += ops.gp[a] * w;
-        }
-        ftb[v] = sd + ops.lm[ik] * sm - ops.lp[ik] * sp;
+        for (int a = 0; a < P; ++a) sd += ops.Dt[a * P + ik] * lin[a * stride];
+        ftb[v] = sd;
       }
       finv_dot_vjp<D>(uv, Sm[k], ph.gm1, ftb, ubs);
       for (int v = 0; v < NV; ++v) ftb[v] = -ftb[v];
@@ -715,15 +710,10 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_euler_vol(con
     T ftb[NV];
     for (int v = 0; v < NV; ++v) {
       const T *lin = lvb + (el * NV + v) * Ns + base;
-      T sd = T(0), sm = T(0), sp = T(0);
+      T sd = T(0);  // transpose of the divergence with the folded correction
 #pragma unroll
-      for (int a = 0; a < P; ++a) {
-        const T w = lin[a * stride];
-        sd += ops.D[a * P + ik] * w;
-        sm += ops.gm[a] * w;
-        sp += ops.gp[a] * w;
-      }
-      ftb[v] = sd + ops.lm[ik] * sm - ops.lp[ik] * sp;
+      for (int a = 0; a < P; ++a) sd += ops.Dt[a * P + ik] * lin[a * stride];
+      ftb[v] = sd;
     }
     finv_dot_vjp<D>(uv, Sk, ph.gm1, ftb, ubs);
   }
@@ -773,14 +763,7 @@ template <int D, int P, typename T>
 struct VjpEngine {
   using S = Shape<D, P>;
   static void run(const fr_solver *s, const T *u, const T *rbar, T *ubar, T *work, hipStream_t st) {
-    OpsDev<T, P> o;
-    for (int i = 0; i < P * P; ++i) o.D[i] = (T)s->ops.D[i];
-    for (int i = 0; i < P; ++i) {
-      o.lm[i] = (T)s->ops.lm[i];
-      o.lp[i] = (T)s->ops.lp[i];
-      o.gp[i] = (T)s->ops.gp[i];
-      o.gm[i] = (T)s->ops.gm[i];
-    }
+    const OpsDev<T, P> o = make_ops<T, P>(s->ops);
     PhysDev<T> ph;
     ph.gamma = (T)s->gamma;
     ph.gm1 = (T)(s->gamma - 1.0);

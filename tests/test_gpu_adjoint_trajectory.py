@@ -50,7 +50,7 @@ def test_trajectory_gradient_matches_oracle_and_fd(gpu):
     g = ug.grad
     # J is the variance of a signal p ~ p_inf = 17.9 with fluctuations sigma ~ 5e-3: its relative
     # round-off is ~ eps (p_inf / sigma)^2 ~ 3e-9 per operation, hence the 1e-6 bound
-    assert abs(float(J.detach()) - float(Jref.detach())) <= 1e-6 * abs(float(Jref)), (float(J.detach()), float(Jref.detach()))
+    assert abs(float(J.detach()) - float(Jref.detach())) <= 1e-6 * abs(float(Jref.detach())), (float(J.detach()), float(Jref.detach()))
     pref = torch.stack(ps).detach()
     dp = float((P.detach().cpu() - pref).abs().max())
     sig = float(pref.std())

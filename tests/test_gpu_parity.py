@@ -44,6 +44,27 @@ def test_rhs_fp64(name, gpu):
     assert err <= 1e-11, err
 
 
+@pytest.mark.parametrize("beta", [-0.5, 0.0, 0.3])
+@pytest.mark.parametrize("name", ["ns_ogrid", "ns_box3d_p2", "ns_cgrid_p4"])
+def test_rhs_and_step_fp64_other_ldg_beta(name, beta, gpu):
+    """The LDG switch beta: -1/2 (the other one-sided form) and two-sided values, where both sides'
+    viscous normal fluxes enter every interior common flux."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m, p, fp, eq, init, dt, probes = make_case(name)
+    fp.ldg_beta = beta
+    s = OracleSystem(m, p, fp, equations=eq)
+    u0 = torch.tensor(init(s.solpt_coords())).permute(0, 2, 1).contiguous()
+    sol = Solver(m, p, fp, equations=eq)
+    eR = rel_l2(sol.rhs(u0.to(gpu)), s.residual(u0))
+    u = u0.to(gpu).clone()
+    sol.rk_step(u, torch.tensor(dt, dtype=torch.float64, device=gpu), 2)
+    uref, _, _ = s.run(u0, torch.tensor(dt), 2, sample_every=0)
+    e2 = rel_l2(u, uref)
+    print(f"{name} beta {beta}: rhs rel L2 {eR:.3e}, 2 steps {e2:.3e}")
+    assert eR <= 1e-11 and e2 <= 1e-12, (eR, e2)
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_rk4_fp64_1_and_20_steps_with_probe(name, gpu):
     s, sol, u0, dt = _solver(name)

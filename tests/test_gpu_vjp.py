@@ -42,6 +42,25 @@ def test_rhs_vjp_fp64_matches_oracle_autograd(name, gpu):
     assert rel_l2(ub, 2 * ref) <= 1e-10
 
 
+@pytest.mark.parametrize("beta", [-0.5, 0.3])
+@pytest.mark.parametrize("name", ["ns_ogrid", "ns_box3d_p2"])
+def test_rhs_vjp_fp64_other_ldg_beta(name, beta, gpu):
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m, p, fp, eq, init, dt, probes = make_case(name)
+    fp.ldg_beta = beta
+    s = OracleSystem(m, p, fp, equations=eq)
+    u0 = torch.tensor(init(s.solpt_coords())).permute(0, 2, 1).contiguous()
+    rbar = torch.tensor(np.random.default_rng(33).normal(size=u0.shape))
+    ref = _oracle_vjp(s, u0, rbar)
+    sol = Solver(m, p, fp, equations=eq)
+    ub = torch.zeros_like(u0).to(gpu)
+    sol.rhs_vjp(u0.to(gpu), rbar.to(gpu), ub)
+    err = rel_l2(ub, ref)
+    print(f"{name} beta {beta}: vjp fp64 rel L2 {err:.3e}")
+    assert err <= 1e-10, err
+
+
 @pytest.mark.parametrize("name", ["ns_ogrid", "ns_cgrid_p4"])
 def test_rhs_vjp_fp32(name, gpu):
     from paper_2312_14167_amd import Solver
