@@ -94,22 +94,29 @@ def algorithmic_bytes(info, dim, T, eq, ldg_beta=0.5):
     """Minimum HBM bytes per launch of each kernel (every input read once, every output written
     once; RK kernels averaged over the four stages of a step).  With the one-sided LDG flux
     (beta = +-1/2) only one side of each interior face pair takes the neighbour's u_f and
-    supplies a viscous normal flux, so only that side's values move."""
+    supplies a viscous normal flux, and that side forms the pair's whole common flux inside the
+    Navier-Stokes volume kernel (no face kernel runs)."""
     Ne, NV, Ns, Nf, npair, nbnd, nwall, nmesh = info
     NM = dim * dim + 1
     I = 4
-    sides = 1 if abs(ldg_beta) == 0.5 else 2
+    one_sided = abs(ldg_beta) == 0.5
     b = {}
     b["interp"] = Ne * (NV * Ns + NV * Nf) * T
-    vis = NV * sides if eq == "ns" else 0
-    b["face_flux"] = (npair * ((2 * NV + vis + dim + 1) * T + 2 * I)
-                      + nbnd * ((NV + (NV if eq == "ns" else 0) + dim + 1) * T + I)
-                      + (2 * npair + nbnd) * NV * T)
-    # u, metrics, neighbour codes -> vol; neighbour u_f where the common solution takes it; own
-    # normals and viscous normal flux where the common viscous flux takes it
-    needed = sides * npair + nbnd
-    b["ns_grad"] = (Ne * ((2 * NV * Ns + NM * Ns) * T + Nf * I)
-                    + sides * npair * NV * T + needed * (dim + NV) * T)
+    # u, metrics, neighbour codes -> vol
+    vol_part = Ne * ((2 * NV * Ns + NM * Ns) * T + Nf * I)
+    if eq == "ns" and one_sided:
+        # neighbour u_f on the flux side; normals and |N| there and on boundary points; fvn on
+        # boundary points; every flux point's common flux
+        b["ns_grad"] = (vol_part + npair * NV * T + (npair + nbnd) * (dim + 1) * T + nbnd * NV * T
+                        + Ne * Nf * NV * T)
+        b["face_flux"] = 0.0
+    else:
+        needed = 2 * npair + nbnd
+        b["ns_grad"] = vol_part + 2 * npair * NV * T + needed * (dim + NV) * T
+        vis = 2 * NV if eq == "ns" else 0
+        b["face_flux"] = (npair * ((2 * NV + vis + dim + 1) * T + 2 * I)
+                          + nbnd * ((NV + (NV if eq == "ns" else 0) + dim + 1) * T + I)
+                          + (2 * npair + nbnd) * NV * T)
     rk_rw = (4 * (NV * Ns + NV * Nf + Ns + NV * Ns) + 3 * NV * Ns       # reads: vol/u, fhat, invJ, u0; acc
              + 4 * NV * Nf + 3 * 2 * NV * Ns + NV * Ns) / 4.0            # writes: u_f, acc + stage state / u0
     b["div_rk"] = Ne * (rk_rw * T + I)

@@ -456,7 +456,7 @@ Connectivity build_connectivity(const MeshIn &m, const Ops1D &o, const Geometry 
     throw FrError(FR_ERR_ARG, "mesh too large for 30-bit flux-point codes");
   // element-side view of the same connectivity
   c.nbr.assign((size_t)Ne * Nf, INT32_MIN);
-  c.fnrm.assign((size_t)Ne * d * Nf, 0.0);
+  c.fnrm.assign((size_t)Ne * (d + 1) * Nf, 0.0);
   const int32_t RBIT = 1 << 30;
   for (size_t q = 0; q < c.pairL.size(); ++q) {
     const int32_t L = c.pairL[q], R = c.pairR[q];
@@ -464,10 +464,10 @@ Connectivity build_connectivity(const MeshIn &m, const Ops1D &o, const Geometry 
     c.nbr[R] = L | RBIT;
     const int64_t eL = L / Nf, eR = R / Nf;
     const int fL = L % Nf, fR = R % Nf;
-    for (int j = 0; j < d; ++j) {
+    for (int j = 0; j <= d; ++j) {
       const double nj = c.pair_nrm[q * (d + 1) + j];
-      c.fnrm[((size_t)eL * d + j) * Nf + fL] = nj;
-      c.fnrm[((size_t)eR * d + j) * Nf + fR] = -nj;
+      c.fnrm[((size_t)eL * (d + 1) + j) * Nf + fL] = nj;
+      c.fnrm[((size_t)eR * (d + 1) + j) * Nf + fR] = j < d ? -nj : nj;  // |N| of the pair on both sides
     }
   }
   for (size_t b = 0; b < c.bnd.size(); ++b) {
@@ -475,7 +475,7 @@ Connectivity build_connectivity(const MeshIn &m, const Ops1D &o, const Geometry 
     c.nbr[C] = -(int32_t)b - 1;
     const int64_t e = C / Nf;
     const int fp = C % Nf;
-    for (int j = 0; j < d; ++j) c.fnrm[((size_t)e * d + j) * Nf + fp] = c.bnd_nrm[b * (d + 1) + j];
+    for (int j = 0; j <= d; ++j) c.fnrm[((size_t)e * (d + 1) + j) * Nf + fp] = c.bnd_nrm[b * (d + 1) + j];
   }
   for (size_t k = 0; k < c.nbr.size(); ++k)
     if (c.nbr[k] == INT32_MIN) throw FrError(FR_ERR_MESH, "flux point without a partner or boundary tag");

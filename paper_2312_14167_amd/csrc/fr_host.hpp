@@ -65,7 +65,9 @@ struct Connectivity {
   std::vector<int32_t> elem_mesh;        // [Ne]
   // per element flux point: partner code (bit 30 set on the R side) or -(boundary index + 1)
   std::vector<int32_t> nbr;              // [Ne][Nf]
-  std::vector<double> fnrm;              // [Ne][dim][Nf] outward unit normal (R side: -n_L exactly)
+  // [Ne][dim + 1][Nf] outward unit normal (R side: -n_L exactly), then |N| of the face pair (the L
+  // side's, on both sides) or of the boundary point
+  std::vector<double> fnrm;
 };
 
 Connectivity build_connectivity(const MeshIn &m, const Ops1D &ops, const Geometry &g);

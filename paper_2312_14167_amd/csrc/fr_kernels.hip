@@ -168,11 +168,11 @@ __device__ __forceinline__ int ldg_flux_side(T beta) {
 //   vol = sum_k D~_k F~_k with D~ = D - (interior part of the correction), i.e.
 //   vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}).
 template <int D, int P, typename T>
-__global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
+__global__ __launch_bounds__((GradTile<D, P, T>::BS), 4) void k_ns_grad(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
     const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, T *__restrict__ fvn,
-    T *__restrict__ vol, int64_t Ne) {
+    T *__restrict__ fhat, T *__restrict__ vol, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = GradTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM, NFACE = 2 * D;
@@ -206,7 +206,8 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     if (lane == 0) s_nface = cnt;
   }
   __syncthreads();
-  const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
+  const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;     // LDG common solution: weights of u_L, u_R
+  const T wlf = T(0.5) - ph.beta, wrf = T(0.5) + ph.beta;   // LDG common viscous flux: weights of F_L, F_R
   for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
     const int el = idx / Nf, fp = idx % Nf;
     const int64_t e = e0 + el;
@@ -228,18 +229,49 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
       const int f2 = c % Nf;
       const bool isR = (code & NBR_R_BIT) != 0;
       const T wn = isR ? wl : wr;  // weight of the neighbour's value; zero on the one-sided LDG's other side
+      T un[NV];
       for (int v = 0; v < NV; ++v) {
-        const T un = wn != T(0) ? uf[(e2 * NV + v) * Nf + f2] : T(0);
-        uh[v] = isR ? wl * un + wr * uo[v] : wl * uo[v] + wr * un;
+        un[v] = wn != T(0) ? uf[(e2 * NV + v) * Nf + f2] : T(0);
+        uh[v] = isR ? wl * un[v] + wr * uo[v] : wl * uo[v] + wr * un[v];
+      }
+      if (side != 0 && wn != T(0)) {
+        // flux side of a one-sided pair: inviscid common flux along n_L plus the penalty, x |N|,
+        // into this point's fhat; the flux-point phase adds the viscous part
+        T n[D], F[NV];
+        for (int j = 0; j < D; ++j) n[j] = fnrm[(e * (D + 1) + j) * Nf + fp];
+        const T mag = fnrm[(e * (D + 1) + D) * Nf + fp];
+        if (isR) {
+          for (int j = 0; j < D; ++j) n[j] = -n[j];  // n_L
+          rusanov<D>(un, uo, n, ph.gamma, ph.gm1, F);
+          for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = (F[v] + ph.tau * (un[v] - uo[v])) * mag;
+        } else {
+          rusanov<D>(uo, un, n, ph.gamma, ph.gm1, F);
+          for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
+        }
       }
     } else {
       const int64_t b = -(int64_t)code - 1;
-      if (b < n_wall) {
+      T n[D];
+      for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+      const bool wall = b < n_wall;
+      if (wall) {
         wall_state<D>(uo, uh);
       } else {
-        T n[D];
-        for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
         farfield<D>(uo, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, uh);
+      }
+      if (side != 0) {
+        // boundary flux, inviscid part: Rusanov against the ghost (wall reflection / far-field state)
+        T ug[NV], F[NV];
+        if (wall) {
+          ug[0] = uo[0];
+          for (int j = 0; j < D; ++j) ug[1 + j] = -uo[1 + j];
+          ug[D + 1] = uo[D + 1];
+        } else {
+          for (int v = 0; v < NV; ++v) ug[v] = uh[v];
+        }
+        rusanov<D>(uo, ug, n, ph.gamma, ph.gm1, F);
+        const T mag = bnrm[b * (D + 1) + D];
+        for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = F[v] * mag;
       }
     }
     for (int v = 0; v < NV; ++v) lw[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
@@ -286,7 +318,12 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) lw[((el * D + j) * NV + v) * Ns + i] = gx[j][v];
   __syncthreads();
-  // viscous normal flux at the flux points of the listed faces
+  // Flux points of the listed faces: viscous normal flux fvn = F_vis(u_f, M0 grad_x u) . n_out.
+  // Two-sided LDG: stored for the face kernel.  One-sided LDG: this point's side alone supplies
+  // the viscous part of the common flux and holds both states, so the first phase already put
+  // the inviscid part and the penalty (x |N|) into its fhat; here the viscous part is added and
+  // the finished common flux goes to both sides of the pair (boundary points: own side only).
+  // fvn is stored on boundary points in both modes (wall-force integral).
   const int nfc = s_nface;
   for (int idx = threadIdx.x; idx < nfc * Nfp; idx += blockDim.x) {
     const int fc = s_face[idx / Nfp];
@@ -295,27 +332,28 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
     int base, stride, fs;
     line_of_fpt<D, P>(fp, base, stride, fs);
     const T *lv = fs ? ops.lp : ops.lm;
-    T st[NV], n[D];
+    T uo[NV], st[NV], n[D];
     for (int v = 0; v < NV; ++v) {
       const T *lin = lu + (elf * NV + v) * Ns + base;
       T s = T(0);
 #pragma unroll
       for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-      st[v] = s;
+      uo[v] = s;
     }
-    for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * D + j) * Nf + fp];
+    for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * (D + 1) + j) * Nf + fp];
     const int32_t code = nbr[ef * Nf + fp];
-    bool heat = true;
+    const int mi = elem_mesh[ef];
+    bool heat = true, wall = false;
     if (code < 0) {
-      const int64_t b = -(int64_t)code - 1;
-      T ub[NV];
-      if (b < n_wall) {
-        wall_state<D>(st, ub);
+      wall = (-(int64_t)code - 1) < n_wall;
+      if (wall) {
+        wall_state<D>(uo, st);
         heat = false;
       } else {
-        farfield<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ub);
+        farfield<D>(uo, n, flow[mi], ph.gamma, ph.gm1, st);
       }
-      for (int v = 0; v < NV; ++v) st[v] = ub[v];
+    } else {
+      for (int v = 0; v < NV; ++v) st[v] = uo[v];
     }
     const T *lge = lw + elf * D * NV * Ns + base;
     auto gdir = [&](int d, int v) {
@@ -326,8 +364,32 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS)) void k_ns_grad(
       return s;
     };
     T fv[NV];
-    fvis_normal_stream<D>(st, gdir, n, flow[elem_mesh[ef]].mu, ph, heat, fv);
-    for (int v = 0; v < NV; ++v) fvn[(ef * NV + v) * Nf + fp] = fv[v];
+    fvis_normal_stream<D>(st, gdir, n, flow[mi].mu, ph, heat, fv);
+    if (side == 0 || code < 0)
+      for (int v = 0; v < NV; ++v) fvn[(ef * NV + v) * Nf + fp] = fv[v];
+    if (side == 0) continue;
+    // complete the common flux started in the first phase (same workgroup, ordered by the barriers)
+    const T mag = fnrm[(ef * (D + 1) + D) * Nf + fp];
+    T *fo = fhat + ef * NV * Nf + fp;
+    if (code < 0) {
+      for (int v = 0; v < NV; ++v) fo[v * Nf] = fo[v * Nf] - fv[v] * mag;
+    } else {
+      const int32_t c = code & (NBR_R_BIT - 1);
+      T *fq = fhat + (int64_t)(c / Nf) * NV * Nf + c % Nf;
+      if (code & NBR_R_BIT) {  // F^ . n_L = ... + (1/2 + b) fvn_R
+        for (int v = 0; v < NV; ++v) {
+          const T t = fo[v * Nf] + wrf * fv[v] * mag;
+          fo[v * Nf] = -t;
+          fq[v * Nf] = t;
+        }
+      } else {                 // F^ . n_L = ... - (1/2 - b) fvn_L
+        for (int v = 0; v < NV; ++v) {
+          const T t = fo[v * Nf] - wlf * fv[v] * mag;
+          fo[v * Nf] = t;
+          fq[v * Nf] = -t;
+        }
+      }
+    }
   }
   // transformed flux F~_k = S_k . (F_inv - F_vis) at the own solution point, from the gradient
   // held in LDS (no transformed flux is live in registers through the flux-point phase)
@@ -736,6 +798,11 @@ struct Engine {
   using S = Shape<D, P>;
 
   static OpsDev<T, P> ops(const fr_solver *s) { return make_ops<T, P>(s->ops); }
+  // same test as ldg_flux_side() in the kernels, in the same precision
+  static bool ldg_two_sided(const fr_solver *s) {
+    const T b = (T)s->beta;
+    return !(b == T(0.5) || b == T(-0.5));
+  }
   static PhysDev<T> phys(const fr_solver *s) {
     PhysDev<T> p;
     p.gamma = (T)s->gamma;
@@ -767,14 +834,14 @@ struct Engine {
         ProfScope ps(s, 2, st);
         k_ns_grad<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, uf, s->nbr, (const T *)s->fnrm,
                                                                    (const T *)s->bnd_nrm, s->n_wall, metric,
-                                                                   s->elem_mesh, fl, o, ph, fvn, vol, s->Ne);
+                                                                   s->elem_mesh, fl, o, ph, fvn, fhat, vol, s->Ne);
       }
       if (force_sample && s->forces && s->n_wall > 0) {
         ProfScope ps(s, 7, st);
         k_wall_force<D, P, T><<<s->n_mesh, 256, 0, st>>>(uf, fvn, s->bnd, (const T *)s->bnd_nrm, s->bnd_w,
                                                           s->wall_mesh_begin, ph, s->force_acc);
       }
-      {
+      if (ldg_two_sided(s)) {  // one-sided LDG: the common flux was formed inside k_ns_grad
         ProfScope ps(s, 3, st);
         k_face_flux<D, P, T, true><<<nblk(nface, 256), 256, 0, st>>>(
             uf, fvn, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,

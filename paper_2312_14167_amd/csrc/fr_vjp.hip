@@ -536,7 +536,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       fb[v] = fvnbar[(ef * NV + v) * Nf + fpl];
       stb[v] = T(0);
     }
-    for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * D + j) * Nf + fpl];
+    for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * (D + 1) + j) * Nf + fpl];
     const int32_t code = nbr[ef * Nf + fpl];
     T ub[NV];
     bool heat = true, wall = false;
