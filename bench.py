@@ -328,6 +328,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 192,000 hexes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--only", choices=["adjoint", "drift", "batched"],
+                    help="run one secondary measurement alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -348,6 +350,17 @@ def main():
         sys.exit(1)
     from paper_2312_14167_amd import Solver  # noqa: F401  (fails loudly without libfrmi.so)
     K, W = args.steps, args.warmup
+    if args.only:
+        if args.only == "adjoint":
+            r = adjoint_ratio()
+        elif args.only == "drift":
+            r = cylinder_precision_drift()
+        else:
+            bm, bfp, bprobes, counts = cavity_batch()
+            r = run_variant(bm, bfp, "fp32", K, W, probes=bprobes, probe_mesh=np.arange(16))
+            r = {k: v for k, v in r.items() if k in ("gdofs", "ms_per_step")}
+        print(json.dumps({"only": args.only, **r}), flush=True)
+        return
     log("building the 3-D C-grid workload")
     t0 = time.perf_counter()
     mesh, fp, aoa = naca_workload(scale=args.scale)

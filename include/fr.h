@@ -177,10 +177,13 @@ fr_status fr_profile_read(fr_solver *s, double *total_ms, int64_t *launches, voi
  * (interpolated conserved state, then Eq. (5)).  p_bar: device FP64 [n_probe]. */
 fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, void *stream);
 
-/* One classical RK4 step of u (device state, in place, no sampling) that also stores the three
- * intermediate stage states y2 = u + dt/2 k1, y3 = u + dt/2 k2, y4 = u + dt k3 of the step in
- * stages[3][n_elem][nv][Ns] (device, state dtype), for use by fr_rk_step_vjp. */
-fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, void *stages, void *stream);
+/* n_steps classical RK4 steps of u (device state, in place, no sampling) that also store, for
+ * every step n, the base state u_n in states[n][n_elem][nv][Ns] (skipped when states is NULL) and
+ * the three intermediate stage states y2 = u_n + dt/2 k1, y3 = u_n + dt/2 k2, y4 = u_n + dt k3 in
+ * stages[n][3][n_elem][nv][Ns] (device, state dtype), for use by fr_rk_step_vjp.  states must not
+ * alias u.  FR_ERR_ARG for n_steps < 1 or NULL u / dt / stages. */
+fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_steps, void *states, void *stages,
+                            void *stream);
 
 /* Adjoint of one RK4 step u_n -> u_{n+1}: on entry u_bar holds dJ/du_{n+1}, on return dJ/du_n
  * (= (du_{n+1}/du_n)^T u_bar).  stages: the step's stage states from fr_rk_step_stages, or NULL

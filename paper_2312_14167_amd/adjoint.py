@@ -3,7 +3,7 @@
 Forward: K RK4 steps of the FR residual from u_0 with the probe pressure sampled before every
 step (p_n = p(u_n), n = 0..K-1), keeping the state every `checkpoint_every` steps.  Backward:
 segment by segment in reverse, the segment's states and RK stage states are recomputed from its
-checkpoint (fr_rk_step_stages), then each step is reversed with fr_rk_step_vjp and the probe
+checkpoint in one fr_rk_step_stages call, then each step is reversed with fr_rk_step_vjp and the probe
 adjoint fr_probe_vjp:  u_bar_n = (du_{n+1}/du_n)^T u_bar_{n+1} + (dp_n/du_n)^T p_bar_n.
 All arithmetic runs in the library's kernels; torch provides the tensors and the tape.
 """
@@ -40,9 +40,7 @@ class FRTrajectory(torch.autograd.Function):
         for s0 in reversed(range(0, K, C)):
             s1 = min(s0 + C, K)
             u = ctx.ckpts[s0].clone()
-            for n in range(s0, s1):
-                states[n - s0].copy_(u)
-                sol.rk_step_stages(u, dt, stages[n - s0])
+            sol.rk_step_stages(u, dt, stages[:s1 - s0], states=states[:s1 - s0])
             for n in reversed(range(s0, s1)):
                 sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0])
                 sol.probe_vjp(states[n - s0], p_bar[n], ub)

@@ -15,7 +15,7 @@ namespace frmi {
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
-  void (*step_record)(const fr_solver *, void *, const double *, void *, hipStream_t);
+  void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, hipStream_t);
   void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
   void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
                          const double *, hipStream_t);
@@ -25,7 +25,8 @@ bool get_dispatch(int dim, int p, int precision, Dispatch &out);
 void launch_fill(double *p, int64_t n, double v, hipStream_t st);
 void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st);
 size_t vjp_work_elems(const fr_solver *s);
-bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, hipStream_t st);
+bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, const void *rk_a,
+                void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, hipStream_t st);
 }  // namespace frmi
 
 using namespace frmi;
@@ -423,7 +424,8 @@ fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar
       s->vjp_work = dalloc(s, need);  // kept until fr_destroy
       s->vjp_bytes = need;
     }
-    if (!launch_vjp(s, u, r_bar, u_bar, s->vjp_work, (hipStream_t)stream))
+    if (!launch_vjp(s, u, r_bar, u_bar, s->vjp_work, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr,
+                    (hipStream_t)stream))
       throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
@@ -444,11 +446,14 @@ fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u
   return FR_OK;
 }
 
-fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, void *stages, void *stream) {
+fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_steps, void *states, void *stages,
+                            void *stream) {
   if (!s || !u || !dt || !stages) return fail(FR_ERR_ARG, "NULL argument");
+  if (n_steps < 1) return fail(FR_ERR_ARG, "n_steps must be >= 1");
+  if (states == u) return fail(FR_ERR_ARG, "states must not alias u");
   try {
     Dispatch d = dispatch_of(s);
-    d.step_record(s, u, dt, stages, (hipStream_t)stream);
+    d.step_record(s, u, dt, n_steps, states, stages, (hipStream_t)stream);
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
@@ -473,7 +478,7 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
     const char *Y = (const char *)stages;
     if (!Y) {  // recompute the stage states from u_n on a copy
       HIP_OK(hipMemcpyAsync(TMP, u_n, nb, hipMemcpyDeviceToDevice, st));
-      d.step_record(s, TMP, dt, STG, st);
+      d.step_record(s, TMP, dt, 1, nullptr, STG, st);
       Y = STG;
     }
     // u_{n+1} = u_n + dt/6 (k1 + 2 k2 + 2 k3 + k4); k_{s} = R(y_s), y1 = u_n, y2 = u_n + dt/2 k1,
@@ -484,10 +489,11 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
     const double cA[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     const double cZ[4] = {0.5, 0.5, 1.0, 0.0};
     d.rk_adj_combine(s, A, nullptr, KB, u_bar, Z, cA[3], 0.0, dt, st);  // A = a, KB = dt/6 a, Z = 0
-    for (int k = 3; k >= 0; --k) {
-      if (!launch_vjp(s, ys[k], KB, Z, s->vjp_work, st)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
-      d.rk_adj_combine(s, A, Z, KB, u_bar, nullptr, k > 0 ? cA[k - 1] : 0.0, k > 0 ? cZ[k - 1] : 0.0, dt, st);
-    }
+    // each stage's VJP ends in the RK epilogue: u_bar += z_s, KB = k_{s-1}_bar
+    for (int k = 3; k >= 0; --k)
+      if (!launch_vjp(s, ys[k], KB, Z, s->vjp_work, A, KB, u_bar, k > 0 ? cA[k - 1] : 0.0, k > 0 ? cZ[k - 1] : 0.0,
+                      dt, st))
+        throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());

@@ -446,6 +446,7 @@ struct RKArgs {
   int first, last;
   T *uf_next;        // flux-point values of the new stage state, or nullptr
   T *ustage_copy;    // optional second copy of the new stage state (adjoint recording)
+  T *u0_copy;        // optional copy of the base state (adjoint recording, first stage)
 };
 
 // shared epilogue: R at (el, i) for all variables -> rhs output or RK update; the new stage
@@ -464,6 +465,7 @@ __device__ __forceinline__ void rk_epilogue(const T *R, int64_t e, int i, const 
     const int64_t o = (e * NV + v) * Ns + i;
     const T a = rk.first ? T(0) : rk.acc[o];
     const T u0 = rk.u0[o];
+    if (rk.u0_copy) rk.u0_copy[o] = u0;
     if (!rk.last) {
       rk.acc[o] = a + rk.cB * dt * R[v];
       w[v] = u0 + rk.cA * dt * R[v];
@@ -880,7 +882,7 @@ struct Engine {
   // one classical RK4 step of u in place; `fresh`: s->uf does not hold u_f of u yet (first step
   // of a call); later steps reuse the flux-point values written by the previous last stage
   static void step(const fr_solver *s, T *u, const double *dt, bool sample, bool fresh, hipStream_t st,
-                   T *record = nullptr) {
+                   T *record = nullptr, T *record_u0 = nullptr) {
     static const double cA[4] = {0.5, 0.5, 1.0, 0.0};
     static const double cB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     if (sample) probe(s, u, st);
@@ -897,6 +899,7 @@ struct Engine {
       rk.last = k == 3;
       rk.uf_next = (T *)s->uf;
       rk.ustage_copy = (record && k < 3) ? record + (int64_t)k * s->Ne * S::NV * S::Ns : nullptr;
+      rk.u0_copy = k == 0 ? record_u0 : nullptr;
       const T *ust = k == 0 ? u : (const T *)s->ustage;
       stage(s, ust, rk, st, sample && k == 0);
     }
@@ -907,7 +910,7 @@ struct Engine {
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
-  void (*step_record)(const fr_solver *, void *, const double *, void *, hipStream_t);
+  void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, hipStream_t);
   void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
   void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
                          const double *, hipStream_t);
@@ -923,8 +926,14 @@ Dispatch make_dispatch() {
   d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
     Engine<D, P, T>::step(s, (T *)u, dt, sample, fresh, st);
   };
-  d.step_record = [](const fr_solver *s, void *u, const double *dt, void *rec, hipStream_t st) {
-    Engine<D, P, T>::step(s, (T *)u, dt, false, true, st, (T *)rec);
+  // n steps recording each step's base state (states, optional) and its three stage states;
+  // flux-point values carry over between the steps of one call, as in fr_rk_step
+  d.step_record = [](const fr_solver *s, void *u, const double *dt, int n, void *states, void *stages,
+                     hipStream_t st) {
+    const int64_t nb = s->Ne * Shape<D, P>::NV * Shape<D, P>::Ns;
+    for (int k = 0; k < n; ++k)
+      Engine<D, P, T>::step(s, (T *)u, dt, false, k == 0, st, (T *)stages + 3 * nb * k,
+                            states ? (T *)states + nb * k : nullptr);
   };
   d.probe_vjp = [](const fr_solver *s, const void *u, const double *pbar, void *ub, hipStream_t st) {
     if (s->n_probe > 0)

@@ -250,27 +250,6 @@ __device__ __forceinline__ void wall_state_vjp(const T *uB, const T *wb, T *uBb)
 }
 
 // ------------------------------------------------------------------------------------ kernels
-// u_f = M0 u (forward values at the linearisation point)
-template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void k_vjp_interp(const T *__restrict__ u, T *__restrict__ uf, OpsDev<T, P> ops,
-                                                    int64_t Ne) {
-  using S = Shape<D, P>;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= Ne * S::Nf) return;
-  const int64_t e = gid / S::Nf;
-  const int fp = (int)(gid % S::Nf);
-  int base, stride, side;
-  line_of_fpt<D, P>(fp, base, stride, side);
-  const T *lv = side ? ops.lp : ops.lm;
-  for (int v = 0; v < S::NV; ++v) {
-    const T *ue = u + (e * S::NV + v) * S::Ns + base;
-    T s = T(0);
-#pragma unroll
-    for (int a = 0; a < P; ++a) s += lv[a] * ue[a * stride];
-    uf[(e * S::NV + v) * S::Nf + fp] = s;
-  }
-}
-
 template <int D, int P, typename T>
 struct VjpDivTile {
   using S = Shape<D, P>;
@@ -279,20 +258,25 @@ struct VjpDivTile {
   static constexpr int BS = round64(E * S::Ns);
 };
 
-// w = -(1/J) r_bar -> vol_bar (solution points) and F^_bar = Lift^T w (flux points)
+// w = -(1/J) r_bar -> vol_bar (solution points) and F^_bar = Lift^T w (flux points); also the
+// forward flux-point values u_f = M0 u at the linearisation point (read by the face adjoint)
 template <int D, int P, typename T>
 __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *__restrict__ rbar,
+                                                                       const T *__restrict__ u,
                                                                        const T *__restrict__ metric,
                                                                        OpsDev<T, P> ops_arg, T *__restrict__ volbar,
-                                                                       T *__restrict__ fhatbar, int64_t Ne) {
+                                                                       T *__restrict__ fhatbar, T *__restrict__ uf,
+                                                                       int64_t Ne) {
   using S = Shape<D, P>;
   using TL = VjpDivTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lw[E * TL::LE];
+  __shared__ __attribute__((aligned(16))) T lu[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
   stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   if (el < ne) {
     const int64_t e = e0 + el;
@@ -309,11 +293,17 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
     int base, stride, side;
     line_of_fpt<D, P>(fp, base, stride, side);
     const T *g = side ? ops.gp : ops.gm;
+    const T *lv = side ? ops.lp : ops.lm;
     const T *lin = lw + rest * Ns + base;
-    T s = T(0);
+    const T *lun = lu + rest * Ns + base;
+    T s = T(0), su = T(0);
 #pragma unroll
-    for (int a = 0; a < P; ++a) s += g[a] * lin[a * stride];
+    for (int a = 0; a < P; ++a) {
+      s += g[a] * lin[a * stride];
+      su += lv[a] * lun[a * stride];
+    }
     fhatbar[e0 * NV * Nf + idx] = s;
+    uf[e0 * NV * Nf + idx] = su;
   }
 }
 
@@ -720,12 +710,22 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_euler_vol(con
   for (int v = 0; v < NV; ++v) ubvol[(e * NV + v) * Ns + i] = ubs[v];
 }
 
-// u_bar += ubvol + M0^T (ufb_own + ufb_nbr)
+// RK4-step adjoint epilogue of the VJP: with z = (dR/du)^T k_bar of this stage,
+// u_bar += z and the previous stage's k_bar = dt (ca a + cz z) (a = dJ/du_{n+1})
+template <typename T>
+struct AdjRK {
+  T *a, *kb, *ub;
+  const double *dt;  // per mesh
+  const int32_t *elem_mesh;
+  T ca, cz;
+};
+
+// z = ubvol + M0^T (ufb_own + ufb_nbr); u_bar += z, or the RK epilogue when rk.ub is set
 template <int D, int P, typename T>
 __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_final(const T *ubvol, const T *__restrict__ ufb_own,
                                                                          const T *__restrict__ ufb_nbr,
                                                                          OpsDev<T, P> ops_arg, T *__restrict__ ubar,
-                                                                         int64_t Ne) {
+                                                                         AdjRK<T> rk, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = VjpDivTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV;
@@ -737,6 +737,7 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_final(const T
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   if (el >= ne) return;
   const int64_t e = e0 + el;
+  const T dt = rk.ub ? (T)rk.dt[rk.elem_mesh[e]] : T(0);
   for (int v = 0; v < NV; ++v) {
     T s = ubvol[(e * NV + v) * Ns + i];
     const T *fo = ufb_own + (e * NV + v) * Nf;
@@ -752,7 +753,13 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_final(const T
       }
       s += ops.lm[ik] * am + ops.lp[ik] * ap;
     }
-    ubar[(e * NV + v) * Ns + i] += s;
+    const int64_t o = (e * NV + v) * Ns + i;
+    if (rk.ub) {
+      rk.ub[o] += s;
+      rk.kb[o] = dt * (rk.ca * rk.a[o] + rk.cz * s);
+    } else {
+      ubar[o] += s;
+    }
   }
 }
 
@@ -762,7 +769,8 @@ static inline unsigned vblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) 
 template <int D, int P, typename T>
 struct VjpEngine {
   using S = Shape<D, P>;
-  static void run(const fr_solver *s, const T *u, const T *rbar, T *ubar, T *work, hipStream_t st) {
+  static void run(const fr_solver *s, const T *u, const T *rbar, T *ubar, T *work, const AdjRK<T> &rk,
+                  hipStream_t st) {
     const OpsDev<T, P> o = make_ops<T, P>(s->ops);
     PhysDev<T> ph;
     ph.gamma = (T)s->gamma;
@@ -779,9 +787,8 @@ struct VjpEngine {
     T *uf = (T *)s->uf;
     const T *metric = (const T *)s->metric;
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
-    k_vjp_interp<D, P, T><<<vblk(Ne * S::Nf, 256), 256, 0, st>>>(u, uf, o, Ne);
     using TD = VjpDivTile<D, P, T>;
-    k_vjp_div<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, metric, o, volbar, fhatbar, Ne);
+    k_vjp_div<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, u, metric, o, volbar, fhatbar, uf, Ne);
     const int64_t nface = s->npair + s->nbnd;
     if (s->equations == 1) {
       k_vjp_face<D, P, T, true><<<vblk(nface, 256), 256, 0, st>>>(
@@ -791,13 +798,13 @@ struct VjpEngine {
       k_vjp_ns_vol<D, P, T><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
           u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
           volbar, fvnbar, ufbface, volbar, fhatbar, ufbnbr, Ne);
-      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, fhatbar, ufbnbr, o, ubar, Ne);
+      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, fhatbar, ufbnbr, o, ubar, rk, Ne);
     } else {
       k_vjp_face<D, P, T, false><<<vblk(nface, 256), 256, 0, st>>>(
           uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
           s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr);
       k_vjp_euler_vol<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(u, metric, o, ph, volbar, volbar, Ne);
-      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, nullptr, o, ubar, Ne);
+      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, nullptr, o, ubar, rk, Ne);
     }
   }
 };
@@ -807,15 +814,24 @@ size_t vjp_work_elems(const fr_solver *s) {
   return (size_t)s->Ne * s->NV * (s->Ns + 4 * s->Nf);
 }
 
-bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, hipStream_t st) {
+// u_bar += (dR/du (u))^T r_bar when rk_a is NULL.  Otherwise the RK4-step adjoint epilogue:
+// with z = (dR/du (u))^T r_bar, rk_ub += z and rk_kb = dt (ca rk_a + cz z) (rk_kb may be r_bar:
+// it is read by the first kernel and written by the last).
+bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, const void *rk_a,
+                void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, hipStream_t st) {
 #define FR_VCASE(DD, PP)                                                                              \
   if (s->dim == DD && s->p + 1 == PP) {                                                               \
-    if (s->precision == 0)                                                                            \
+    if (s->precision == 0) {                                                                          \
+      AdjRK<double> rk{(double *)rk_a, (double *)rk_kb, (double *)(rk_a ? rk_ub : nullptr), dt,       \
+                       s->elem_mesh, ca, cz};                                                         \
       VjpEngine<DD, PP, double>::run(s, (const double *)u, (const double *)rbar, (double *)ubar,      \
-                                     (double *)work, st);                                             \
-    else                                                                                              \
+                                     (double *)work, rk, st);                                         \
+    } else {                                                                                          \
+      AdjRK<float> rk{(float *)rk_a, (float *)rk_kb, (float *)(rk_a ? rk_ub : nullptr), dt,           \
+                      s->elem_mesh, (float)ca, (float)cz};                                            \
       VjpEngine<DD, PP, float>::run(s, (const float *)u, (const float *)rbar, (float *)ubar,          \
-                                    (float *)work, st);                                               \
+                                    (float *)work, rk, st);                                           \
+    }                                                                                                 \
     return true;                                                                                      \
   }
   FR_VCASE(2, 2) FR_VCASE(2, 3) FR_VCASE(2, 4) FR_VCASE(2, 5)

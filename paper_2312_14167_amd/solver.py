@@ -154,14 +154,24 @@ class Solver:
                                  C.c_void_p(u_bar.data_ptr()), _stream(stream)))
         return u_bar
 
-    def rk_step_stages(self, u: torch.Tensor, dt: torch.Tensor, stages: torch.Tensor, stream=None):
-        """One RK4 step of u in place, recording y2, y3, y4 into stages [3, *shape]."""
+    def rk_step_stages(self, u: torch.Tensor, dt: torch.Tensor, stages: torch.Tensor, states=None, stream=None):
+        """RK4 steps of u in place, recording each step's stage states y2, y3, y4 into stages
+        ([3, *shape] for one step, [n, 3, *shape] for n steps) and, if given, each step's base
+        state into states ([n, *shape])."""
         self._check_state(u, "u")
         self._check_dt(dt)
-        if not (stages.is_cuda and stages.dtype == self.dtype and tuple(stages.shape) == (3,) + self.shape
-                and stages.is_contiguous()):
-            raise ValueError("stages must be a contiguous CUDA tensor of shape (3,) + state shape")
-        check(lib().fr_rk_step_stages(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()),
+        one = tuple(stages.shape) == (3,) + self.shape
+        n = 1 if one else int(stages.shape[0])
+        if not (stages.is_cuda and stages.dtype == self.dtype and stages.is_contiguous()
+                and (one or tuple(stages.shape) == (n, 3) + self.shape)):
+            raise ValueError("stages must be a contiguous CUDA tensor of shape (3,) + state shape or (n, 3) + state shape")
+        sp = None
+        if states is not None:
+            if not (states.is_cuda and states.dtype == self.dtype and states.is_contiguous()
+                    and tuple(states.shape) == (n,) + self.shape):
+                raise ValueError("states must be a contiguous CUDA tensor of shape (n,) + state shape")
+            sp = C.c_void_p(states.data_ptr())
+        check(lib().fr_rk_step_stages(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), n, sp,
                                       C.c_void_p(stages.data_ptr()), _stream(stream)))
         return u
 

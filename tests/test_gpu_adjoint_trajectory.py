@@ -96,6 +96,30 @@ def test_rk_step_vjp_recompute_equals_recorded_stages(gpu):
     assert torch.equal(b1, b2)
 
 
+def test_multi_step_recording_equals_single_steps(gpu):
+    """fr_rk_step_stages over n steps in one call (flux-point values carried between steps, base
+    states copied by the first stage kernel) equals n single recording steps, bit for bit."""
+    from paper_2312_14167_amd import Solver
+    m, p, fp, probes = _case()
+    sol = Solver(m, p, fp, equations="ns")
+    x = sol.solpt_coords()
+    u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (4,), 6, 1e-2)).permute(0, 2, 1)
+    u0 = u0.contiguous().to(gpu)
+    dtt = torch.tensor([2e-4], dtype=torch.float64, device=gpu)
+    n = 3
+    states = torch.empty((n,) + sol.shape, dtype=torch.float64, device=gpu)
+    stages = torch.empty((n, 3) + sol.shape, dtype=torch.float64, device=gpu)
+    u = u0.clone()
+    sol.rk_step_stages(u, dtt, stages, states=states)
+    v = u0.clone()
+    for k in range(n):
+        assert torch.equal(states[k], v)
+        st1 = torch.empty((3,) + sol.shape, dtype=torch.float64, device=gpu)
+        sol.rk_step_stages(v, dtt, st1)
+        assert torch.equal(stages[k], st1)
+    assert torch.equal(u, v)
+
+
 def test_adjoint_full_size_cylinder_80x64(gpu):
     """The adjoint workload at full size: cylinder O-grid 80 x 64, p = 3, FP64.
     (a) 200 RK4 steps with checkpoints every 20: the adjoint directional derivative against central
