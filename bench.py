@@ -235,12 +235,12 @@ def adjoint_ratio(K=200, C=20):
     dt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
     # warm-up (graph capture, work allocation)
     ug = u0.clone().requires_grad_(True)
-    P = FRTrajectory.apply(ug, sol, dt, 4, 2)
+    P = FRTrajectory.apply(ug, sol, dt, 4, 2, None)
     ((P - P.mean(0)) ** 2).mean(0).sum().backward()
     torch.cuda.synchronize()
     ug = u0.clone().requires_grad_(True)
     t0 = time.perf_counter()
-    P = FRTrajectory.apply(ug, sol, dt, K, C)
+    P = FRTrajectory.apply(ug, sol, dt, K, C, None)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     J = ((P - P.mean(0)) ** 2).mean(0).sum()

@@ -147,8 +147,10 @@ fr_status fr_reset_accumulators(fr_solver *s, void *stream);
  * u_bar += (dR/du)^T r_bar.  u, r_bar, u_bar: device state arrays of the solver's dtype;
  * u_bar may not alias u or r_bar.  Overwrites the solver's flux-point work arrays (later
  * fr_rhs / fr_rk_step calls recompute them); allocates an adjoint work area on first use.
- * x_bar (sensitivity to the mesh node coordinates) must be NULL: FR_ERR_UNSUPPORTED
- * otherwise. */
+ * x_bar: NULL, or device FP64 [n_node][dim] that receives += (dR/dX)^T r_bar, the sensitivity to
+ * the mesh node coordinates X through the metric terms (S = adj(dx/dxi), 1/J, Eq. (1) in
+ * transformed form) and the face normals; with x_bar the call also evaluates the residual at u
+ * and allocates the geometric adjoint tables on first use. */
 fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream);
 
 /* Counts of the discretisation: info[0..7] = {n_elem, nv, Ns, Nf, n_face_pairs (interior and
@@ -174,8 +176,10 @@ fr_status fr_profile_enable(fr_solver *s, int32_t enable);
 fr_status fr_profile_read(fr_solver *s, double *total_ms, int64_t *launches, void *stream);
 
 /* Adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du with p_a the probe pressure
- * (interpolated conserved state, then Eq. (5)).  p_bar: device FP64 [n_probe]. */
-fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, void *stream);
+ * (interpolated conserved state, then Eq. (5)).  p_bar: device FP64 [n_probe].  x_bar: NULL, or
+ * device FP64 [n_node][dim] += sum_a p_bar[a] dp_a/dX: the probe is fixed in physical space, so
+ * its reference coordinates follow the nodes of its element. */
+fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, double *x_bar, void *stream);
 
 /* n_steps classical RK4 steps of u (device state, in place, no sampling) that also store, for
  * every step n, the base state u_n in states[n][n_elem][nv][Ns] (skipped when states is NULL) and
@@ -187,9 +191,11 @@ fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_s
 
 /* Adjoint of one RK4 step u_n -> u_{n+1}: on entry u_bar holds dJ/du_{n+1}, on return dJ/du_n
  * (= (du_{n+1}/du_n)^T u_bar).  stages: the step's stage states from fr_rk_step_stages, or NULL
- * to recompute them from u_n.  dt: device FP64 [n_mesh].  Allocates its work area on first use. */
+ * to recompute them from u_n.  dt: device FP64 [n_mesh].  x_bar: NULL, or device FP64
+ * [n_node][dim] += (du_{n+1}/dX)^T u_bar (entry value of u_bar) through the residuals of the
+ * four stages.  Allocates its work area on first use. */
 fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, void *u_bar,
-                         void *stream);
+                         double *x_bar, void *stream);
 
 /* Release everything the handle owns (NULL is a no-op). */
 void fr_destroy(fr_solver *s);

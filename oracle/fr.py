@@ -57,6 +57,7 @@ class OracleSystem:
             elem_mesh[mesh.mesh_elem_begin[m]:mesh.mesh_elem_begin[m + 1]] = m
         self.elem_mesh = torch.as_tensor(elem_mesh)
         nodes = torch.as_tensor(mesh.node_xyz, dtype=DT) if node_xyz is None else node_xyz
+        self.nodes = nodes
         geo = self.geometry(nodes)
         scale = float(np.ptp(mesh.node_xyz, axis=0).max())
         (eL, fL, eR, fR), (bE, bF, bT) = match_faces(
@@ -72,8 +73,10 @@ class OracleSystem:
         self.mu = t(flow.mu)
         # probes
         self.probes = []
+        self.probe_xyz = []
         if probes is not None:
             probes = np.atleast_2d(np.asarray(probes, float))
+            self.probe_xyz = list(probes)
             pm = np.zeros(len(probes), dtype=np.int64) if probe_mesh is None else np.asarray(probe_mesh)
             for a, xp in enumerate(probes):
                 lo, hi = mesh.mesh_elem_begin[pm[a]], mesh.mesh_elem_begin[pm[a] + 1]
@@ -96,8 +99,34 @@ class OracleSystem:
         return {"x_s": x_s, "x_f": x_f, "J": J, "S": S, "N": N, "magN": magN, "n": N / magN[..., None]}
 
     def set_nodes(self, nodes: torch.Tensor):
-        """Recompute the metrics from (possibly differentiable) node coordinates; topology is kept."""
+        """Recompute the metrics from (possibly differentiable) node coordinates; topology and the
+        probes' elements are kept."""
+        self.nodes = nodes
         self.geo = self.geometry(nodes)
+
+    def _probe_weights(self, a: int) -> torch.Tensor:
+        """Tensor Lagrange weights of probe a.  The probe is fixed in physical space, so when the
+        node coordinates carry gradients its reference coordinates xi follow them: one Newton
+        correction xi = xi0 - A^{-1} (x(xi0) - x_p) from the converged point (residual ~ 0) has
+        the implicit-function derivative d xi / d X_n = -A^{-1} phi_n(xi)."""
+        e, xi0, _ = self.probes[a]
+        if not (isinstance(self.nodes, torch.Tensor) and self.nodes.requires_grad):
+            return torch.as_tensor(self.ops.interp_weights(xi0), dtype=DT)
+        d = self.dim
+        phi, dphi = geometry_basis(d, self.mesh.q, np.asarray(xi0, float)[None, :])
+        Xe = self.nodes[torch.as_tensor(self.mesh.elem_nodes[e])]
+        x = torch.as_tensor(phi[0]) @ Xe
+        A = torch.stack([torch.as_tensor(dphi[k, 0]) @ Xe for k in range(d)], dim=1)      # A[j, k]
+        xi = torch.as_tensor(np.asarray(xi0, float)) - torch.linalg.solve(
+            A, x - torch.as_tensor(self.probe_xyz[a], dtype=DT))
+        nodes1 = torch.as_tensor(self.ops.xi, dtype=DT)
+        w = torch.ones(self.ops.Ns, dtype=DT)
+        for k in range(d):
+            lk = torch.stack([torch.prod(torch.stack([(xi[k] - nodes1[m]) / (nodes1[b] - nodes1[m])
+                                                      for m in range(self.ops.P) if m != b]))
+                              for b in range(self.ops.P)])
+            w = w * lk[torch.as_tensor(self.ops.sol_idx[:, k])]
+        return w
 
     def solpt_coords(self) -> np.ndarray:
         return self.geo["x_s"].detach().numpy()            # [Ne, Ns, d]
@@ -191,8 +220,8 @@ class OracleSystem:
         if not self.probes:
             return torch.zeros(0, dtype=DT)
         vals = []
-        for e, xi, _ in self.probes:
-            w = torch.as_tensor(self.ops.interp_weights(xi), dtype=DT)
+        for a, (e, xi, _) in enumerate(self.probes):
+            w = self._probe_weights(a)
             up = (u[e] * w[None, :]).sum(-1)
             vals.append(pressure(up, self.flow.gamma))
         return torch.stack(vals)

@@ -63,9 +63,9 @@ def lib() -> C.CDLL:
     L.fr_solver_info.argtypes = [vp, vp]
     L.fr_profile_enable.argtypes = [vp, i32]
     L.fr_profile_read.argtypes = [vp, vp, vp, vp]
-    L.fr_probe_vjp.argtypes = [vp, vp, vp, vp, vp]
+    L.fr_probe_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fr_rk_step_stages.argtypes = [vp, vp, vp, i32, vp, vp, vp]
-    L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.fr_destroy.argtypes = [vp]
     L.fr_destroy.restype = None
     L.fr_last_error.argtypes = []

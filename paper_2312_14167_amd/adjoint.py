@@ -13,11 +13,20 @@ import torch
 
 
 class FRTrajectory(torch.autograd.Function):
-    """p = FRTrajectory.apply(u0, solver, dt, n_steps, checkpoint_every) -> [n_steps, n_probe] FP64."""
+    """p = FRTrajectory.apply(u0, solver, dt, n_steps, checkpoint_every, nodes)
+    -> [n_steps, n_probe] FP64.
+
+    ``nodes``: None, or a float64 CUDA tensor [n_node, dim] equal to the solver's mesh node
+    coordinates; when it requires grad, backward also returns dJ/dX through every stage residual
+    (metrics and normals) and through the probe location (fixed in physical space)."""
 
     @staticmethod
-    def forward(ctx, u0, solver, dt, n_steps: int, checkpoint_every: int = 20):
+    def forward(ctx, u0, solver, dt, n_steps: int, checkpoint_every: int, nodes):
         C = max(1, int(checkpoint_every))
+        if nodes is not None:
+            ref = torch.as_tensor(solver.node_xyz, dtype=torch.float64)
+            if tuple(nodes.shape) != tuple(ref.shape) or not torch.equal(nodes.detach().cpu(), ref):
+                raise ValueError("nodes must equal the solver's mesh node coordinates")
         u = u0.detach().clone()
         ckpts = {0: u.clone()}
         solver.reset_accumulators()
@@ -27,6 +36,7 @@ class FRTrajectory(torch.autograd.Function):
                 ckpts[n + 1] = u.clone()
         series = solver.probe_series(n_steps)                    # [n_probe, K]
         ctx.solver, ctx.dt, ctx.K, ctx.C, ctx.ckpts = solver, dt, n_steps, C, ckpts
+        ctx.with_nodes = nodes is not None
         return torch.tensor(series.T.copy(), dtype=torch.float64, device=u0.device)
 
     @staticmethod
@@ -35,6 +45,9 @@ class FRTrajectory(torch.autograd.Function):
         p_bar = p_bar.detach().to(torch.float64).contiguous()
         dev = p_bar.device
         ub = torch.zeros(sol.shape, dtype=sol.dtype, device=dev)   # dJ/du_K = 0
+        xb = None
+        if ctx.with_nodes and ctx.needs_input_grad[5]:
+            xb = torch.zeros((sol.n_node, sol.dim), dtype=torch.float64, device=dev)
         states = torch.empty((C,) + sol.shape, dtype=sol.dtype, device=dev)      # reused by every segment
         stages = torch.empty((C, 3) + sol.shape, dtype=sol.dtype, device=dev)
         for s0 in reversed(range(0, K, C)):
@@ -42,16 +55,19 @@ class FRTrajectory(torch.autograd.Function):
             u = ctx.ckpts[s0].clone()
             sol.rk_step_stages(u, dt, stages[:s1 - s0], states=states[:s1 - s0])
             for n in reversed(range(s0, s1)):
-                sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0])
-                sol.probe_vjp(states[n - s0], p_bar[n], ub)
-        return ub, None, None, None, None
+                sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0], x_bar=xb)
+                sol.probe_vjp(states[n - s0], p_bar[n], ub, x_bar=xb)
+        return ub, None, None, None, None, xb
 
 
-def probe_variance_gradient(solver, u0, dt, n_steps: int, checkpoint_every: int = 20):
+def probe_variance_gradient(solver, u0, dt, n_steps: int, checkpoint_every: int = 20, with_nodes: bool = False):
     """J = sum over probes of (1/K) sum_n (p_n - mean p)^2 (the time-mean square of the probe
-    pressure fluctuation) and dJ/du0."""
+    pressure fluctuation), dJ/du0 and (with_nodes) dJ/dX for the mesh node coordinates."""
     u = u0.detach().clone().requires_grad_(True)
-    p = FRTrajectory.apply(u, solver, dt, n_steps, checkpoint_every)
+    X = None
+    if with_nodes:
+        X = torch.tensor(solver.node_xyz, dtype=torch.float64, device=u0.device, requires_grad=True)
+    p = FRTrajectory.apply(u, solver, dt, n_steps, checkpoint_every, X)
     J = ((p - p.mean(dim=0, keepdim=True)) ** 2).mean(dim=0).sum()
     J.backward()
-    return float(J), u.grad
+    return (float(J.detach()), u.grad, X.grad) if with_nodes else (float(J.detach()), u.grad)

@@ -9,25 +9,7 @@
 #include <vector>
 
 #include "../../include/fr.h"
-#include "fr_solver.hpp"
-
-namespace frmi {
-struct Dispatch {
-  void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
-  void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
-  void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, hipStream_t);
-  void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
-  void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
-                         const double *, hipStream_t);
-  void (*zero)(const fr_solver *, void *, hipStream_t);
-};
-bool get_dispatch(int dim, int p, int precision, Dispatch &out);
-void launch_fill(double *p, int64_t n, double v, hipStream_t st);
-void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st);
-size_t vjp_work_elems(const fr_solver *s);
-bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, const void *rk_a,
-                void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, hipStream_t st);
-}  // namespace frmi
+#include "fr_dispatch.hpp"
 
 using namespace frmi;
 
@@ -105,6 +87,36 @@ void destroy(fr_solver *s) {
   for (void *p : s->owned) (void)hipFree(p);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
+}
+
+// mesh-node adjoint tables and work arrays, on first use
+void ensure_geo(fr_solver *s) {
+  if (s->geo_Gm) return;
+  MeshIn m;
+  m.dim = s->dim;
+  m.p = s->p;
+  m.q = s->geom_q;
+  m.n_elem = s->Ne;
+  m.n_node = s->n_node;
+  m.node_xyz = s->h_node_xyz.data();
+  m.elem_nodes = s->h_elem_nodes.data();
+  GeoAdj g = build_geo_adj(m, s->ops);
+  if (g.nn != s->geo_nn) throw FrError(FR_ERR_MESH, "inconsistent geometry degree");
+  const size_t T = s->tsize;
+  s->geo_Xe = (double *)upload(s, g.Xe);
+  s->geo_dphi_s = (double *)upload(s, g.dphi_s);
+  s->geo_dphi_f = (double *)upload(s, g.dphi_f);
+  s->geo_inc_ptr = (int32_t *)upload(s, g.inc_ptr);
+  s->geo_inc = (int32_t *)upload(s, g.inc);
+  s->geo_Xeb = (double *)dalloc(s, (size_t)s->Ne * g.nn * s->dim * sizeof(double));
+  s->geo_R = dalloc(s, (size_t)s->Ne * s->NV * s->Ns * T);
+  s->geo_Gn = dalloc(s, (size_t)s->Ne * (s->dim + 1) * s->Nf * T);
+  s->geo_Gm = dalloc(s, (size_t)s->Ne * (s->dim * s->dim + 1) * s->Ns * T);
+}
+
+void zero_geo(fr_solver *s, hipStream_t st) {
+  launch_fill_state(s, s->geo_Gm, s->Ne * (s->dim * s->dim + 1) * s->Ns, st);
+  launch_fill_state(s, s->geo_Gn, s->Ne * (s->dim + 1) * s->Nf, st);
 }
 
 Dispatch dispatch_of(const fr_solver *s) {
@@ -194,15 +206,28 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->n_probe = prm->n_probe;
     s->cap = prm->n_probe > 0 ? prm->max_samples : 1;
     s->forces = (prm->forces && s->equations == FR_NAVIER_STOKES) ? 1 : 0;
-    std::vector<int64_t> pe;
-    std::vector<double> pw, pinf;
+    std::vector<int64_t> pe, pnodes;
+    std::vector<double> pw, pinf, pdw, pdxi;
     for (int a = 0; a < prm->n_probe; ++a) {
       int pm = prm->probe_mesh ? prm->probe_mesh[a] : 0;
       if (pm < 0 || pm >= n_mesh) throw FrError(FR_ERR_ARG, "probe mesh out of range");
       Probe pr = locate_probe(m, s->ops, prm->probe_xyz + (size_t)a * s->dim, pm);
       pe.push_back(pr.elem);
       pw.insert(pw.end(), pr.weights.begin(), pr.weights.end());
+      pdw.insert(pdw.end(), pr.dweights.begin(), pr.dweights.end());
+      pdxi.insert(pdxi.end(), pr.dxi.begin(), pr.dxi.end());
+      pnodes.insert(pnodes.end(), pr.nodes.begin(), pr.nodes.end());
       pinf.push_back(prm->p_inf[pm]);
+    }
+    // host copy of the mesh for the mesh-node adjoint
+    {
+      int nn = 1;
+      for (int k = 0; k < s->dim; ++k) nn *= mesh->geom_q + 1;
+      s->geom_q = mesh->geom_q;
+      s->n_node = mesh->n_node;
+      s->geo_nn = nn;
+      s->h_node_xyz.assign(mesh->node_xyz, mesh->node_xyz + mesh->n_node * s->dim);
+      s->h_elem_nodes.assign(mesh->elem_nodes, mesh->elem_nodes + mesh->n_elem * nn);
     }
     s->xsol = std::move(g.xsol);
     s->metric = upload_real(s, g.metric);
@@ -237,6 +262,9 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->probe_elem = (int64_t *)upload(s, pe);
     s->probe_w = (double *)upload(s, pw);
     s->probe_pinf = (double *)upload(s, pinf);
+    s->probe_dw = (double *)upload(s, pdw);
+    s->probe_dxi = (double *)upload(s, pdxi);
+    s->probe_nodes = (int64_t *)upload(s, pnodes);
     s->series = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * s->cap * sizeof(double));
     s->sums = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * 2 * sizeof(double));
     s->force_acc = (double *)dalloc(s, (size_t)n_mesh * s->dim * sizeof(double));
@@ -417,16 +445,23 @@ fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl
 fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream) {
   if (!s || !u || !r_bar || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
   if (u_bar == u || u_bar == r_bar) return fail(FR_ERR_ARG, "u_bar must not alias u or r_bar");
-  if (x_bar) return fail(FR_ERR_UNSUPPORTED, "mesh-node sensitivities (x_bar) are not built; pass NULL");
+  hipStream_t st = (hipStream_t)stream;
   try {
     const size_t need = vjp_work_elems(s) * s->tsize;
     if (!s->vjp_work || s->vjp_bytes < need) {
       s->vjp_work = dalloc(s, need);  // kept until fr_destroy
       s->vjp_bytes = need;
     }
-    if (!launch_vjp(s, u, r_bar, u_bar, s->vjp_work, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr,
-                    (hipStream_t)stream))
+    GeoVjpArgs geo;
+    if (x_bar) {
+      ensure_geo(s);
+      zero_geo(s, st);
+      dispatch_of(s).rhs_two_sided(s, u, s->geo_R, st);  // forward residual and common flux at u
+      geo = GeoVjpArgs{s->geo_Gm, s->geo_Gn, s->geo_R, s->fhat};
+    }
+    if (!launch_vjp(s, u, r_bar, u_bar, s->vjp_work, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, geo, st))
       throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+    if (x_bar && !launch_geo_nodes(s, x_bar, st)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported geometry degree");
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
@@ -434,11 +469,11 @@ fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar
   return FR_OK;
 }
 
-fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, void *stream) {
+fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, double *x_bar, void *stream) {
   if (!s || !u || !u_bar || (s->n_probe > 0 && !p_bar)) return fail(FR_ERR_ARG, "NULL argument");
   try {
     Dispatch d = dispatch_of(s);
-    d.probe_vjp(s, u, p_bar, u_bar, (hipStream_t)stream);
+    d.probe_vjp(s, u, p_bar, u_bar, x_bar, (hipStream_t)stream);
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
@@ -462,7 +497,7 @@ fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_s
 }
 
 fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, void *u_bar,
-                         void *stream) {
+                         double *x_bar, void *stream) {
   if (!s || !u_n || !dt || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
   if (u_bar == u_n) return fail(FR_ERR_ARG, "u_bar must not alias u_n");
   hipStream_t st = (hipStream_t)stream;
@@ -488,12 +523,24 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
     const void *ys[4] = {u_n, Y, Y + nb, Y + 2 * nb};
     const double cA[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     const double cZ[4] = {0.5, 0.5, 1.0, 0.0};
+    if (x_bar) {
+      ensure_geo(s);
+      zero_geo(s, st);
+    }
     d.rk_adj_combine(s, A, nullptr, KB, u_bar, Z, cA[3], 0.0, dt, st);  // A = a, KB = dt/6 a, Z = 0
-    // each stage's VJP ends in the RK epilogue: u_bar += z_s, KB = k_{s-1}_bar
-    for (int k = 3; k >= 0; --k)
+    // each stage's VJP ends in the RK epilogue: u_bar += z_s, KB = k_{s-1}_bar; with x_bar the
+    // metric adjoints of the four stages accumulate, then go to the nodes once
+    for (int k = 3; k >= 0; --k) {
+      GeoVjpArgs geo;
+      if (x_bar) {
+        d.rhs_two_sided(s, ys[k], s->geo_R, st);
+        geo = GeoVjpArgs{s->geo_Gm, s->geo_Gn, s->geo_R, s->fhat};
+      }
       if (!launch_vjp(s, ys[k], KB, Z, s->vjp_work, A, KB, u_bar, k > 0 ? cA[k - 1] : 0.0, k > 0 ? cZ[k - 1] : 0.0,
-                      dt, st))
+                      dt, geo, st))
         throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+    }
+    if (x_bar && !launch_geo_nodes(s, x_bar, st)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported geometry degree");
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());

@@ -1,0 +1,42 @@
+// Host-side entry points of the kernel engines, shared by the API layer and the engines.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fr_solver.hpp"
+
+namespace frmi {
+
+// per (dim, p, precision) function table of the forward engine
+struct Dispatch {
+  void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
+  void (*rhs_two_sided)(const fr_solver *, const void *, void *, hipStream_t);
+  void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
+  void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, hipStream_t);
+  void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, double *, hipStream_t);
+  void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
+                         const double *, hipStream_t);
+  void (*zero)(const fr_solver *, void *, hipStream_t);
+};
+bool get_dispatch(int dim, int p, int precision, Dispatch &out);
+void launch_fill(double *p, int64_t n, double v, hipStream_t st);
+void launch_fill_state(const fr_solver *s, void *p, int64_t n, hipStream_t st);
+void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st);
+
+// adjoint engine (fr_vjp.hip)
+size_t vjp_work_elems(const fr_solver *s);
+// geometric adjoint arrays of one residual VJP: metric and normal adjoints accumulate (+=) into
+// Gm / Gn; R and fhat are the forward residual and common flux of the linearisation state
+struct GeoVjpArgs {
+  void *Gm = nullptr, *Gn = nullptr;
+  const void *R = nullptr, *fhat = nullptr;
+};
+bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, const void *rk_a,
+                void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, const GeoVjpArgs &geo,
+                hipStream_t st);
+
+// mesh-node adjoint (fr_geo.hip): x_bar += (d metrics / d X)^T (Gm, Gn)
+bool launch_geo_nodes(const fr_solver *s, double *x_bar, hipStream_t st);
+
+}  // namespace frmi

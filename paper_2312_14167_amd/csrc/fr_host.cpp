@@ -543,14 +543,61 @@ Probe locate_probe(const MeshIn &m, const Ops1D &o, const double *xp, int mesh) 
       pr.xi.assign(xi, xi + d);
       int P = o.P, Ns = (d == 2) ? P * P : P * P * P;
       pr.weights.assign(Ns, 1.0);
+      pr.dweights.assign((size_t)d * Ns, 1.0);
       for (int i = 0; i < Ns; ++i) {
         int ii[3] = {i % P, (i / P) % P, i / (P * P)};
-        for (int k = 0; k < d; ++k) pr.weights[i] *= lagrange_1d(o.xi, ii[k], xi[k]);
+        for (int k = 0; k < d; ++k) {
+          const double l = lagrange_1d(o.xi, ii[k], xi[k]), dl = lagrange_1d_deriv(o.xi, ii[k], xi[k]);
+          pr.weights[i] *= l;
+          for (int kd = 0; kd < d; ++kd) pr.dweights[(size_t)kd * Ns + i] *= (kd == k ? dl : l);
+        }
+      }
+      // d xi / d X_n = -A^{-1} phi_n(xi) at the located point
+      std::vector<double> ref(xi, xi + d);
+      GeoBasis b = geo_basis(d, m.q, ref);
+      double x[3], A[9], adj[9];
+      map_point(d, b, 0, Xe, x, A);
+      const double J = adjugate(d, A, adj);
+      pr.dxi.assign((size_t)nn * d * d, 0.0);
+      pr.nodes.resize(nn);
+      for (int n = 0; n < nn; ++n) {
+        pr.nodes[n] = m.elem_nodes[e * nn + n];
+        for (int j = 0; j < d; ++j)
+          for (int k = 0; k < d; ++k) pr.dxi[((size_t)n * d + j) * d + k] = -adj[k * d + j] / J * b.phi[n];
       }
       return pr;
     }
   }
   throw FrError(FR_ERR_MESH, "probe is outside every element of its mesh");
+}
+
+GeoAdj build_geo_adj(const MeshIn &m, const Ops1D &o) {
+  const int d = m.dim, Q = m.q + 1;
+  int nn = 1;
+  for (int k = 0; k < d; ++k) nn *= Q;
+  GeoAdj g;
+  g.nn = nn;
+  GeoBasis bs = geo_basis(d, m.q, ref_solpts(d, o));
+  GeoBasis bf = geo_basis(d, m.q, ref_fpts(d, o));
+  g.dphi_s = bs.dphi;
+  g.dphi_f = bf.dphi;
+  g.Xe.resize((size_t)m.n_elem * nn * d);
+  std::vector<int32_t> cnt(m.n_node + 1, 0);
+  for (int64_t e = 0; e < m.n_elem; ++e)
+    for (int n = 0; n < nn; ++n) {
+      const int64_t id = m.elem_nodes[e * nn + n];
+      if (id < 0 || id >= m.n_node) throw FrError(FR_ERR_MESH, "element node id out of range");
+      for (int j = 0; j < d; ++j) g.Xe[((size_t)e * nn + n) * d + j] = m.node_xyz[id * d + j];
+      cnt[id + 1]++;
+    }
+  if ((int64_t)m.n_elem * nn >= ((int64_t)1 << 31)) throw FrError(FR_ERR_ARG, "mesh too large for the node incidence");
+  for (int64_t i = 0; i < m.n_node; ++i) cnt[i + 1] += cnt[i];
+  g.inc_ptr = cnt;
+  g.inc.resize((size_t)m.n_elem * nn);
+  std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t e = 0; e < m.n_elem; ++e)
+    for (int n = 0; n < nn; ++n) g.inc[pos[m.elem_nodes[e * nn + n]]++] = (int32_t)(e * nn + n);
+  return g;
 }
 
 }  // namespace frmi

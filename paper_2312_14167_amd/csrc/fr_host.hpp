@@ -77,8 +77,26 @@ struct Probe {
   int mesh = 0;
   std::vector<double> xi;       // reference coordinates
   std::vector<double> weights;  // [Ns] tensor Lagrange weights
+  // derivatives for the mesh-node adjoint (the probe is fixed in physical space, so its
+  // reference coordinates move with the element's nodes: d xi / d X_n = -A^{-1} phi_n(xi))
+  std::vector<double> dweights;  // [dim][Ns] d weights / d xi_k
+  std::vector<double> dxi;       // [nn][dim][dim]: [n][j][k] = d xi_k / d X_{n,j}
+  std::vector<int64_t> nodes;    // [nn] global ids of the element's nodes
 };
 
 Probe locate_probe(const MeshIn &m, const Ops1D &ops, const double *xp, int mesh);
+
+// Tables of the mesh-node adjoint: element node coordinates, derivatives of the geometry basis
+// at solution and flux points, and the node -> (element, local node) incidence in a fixed order.
+struct GeoAdj {
+  int nn = 0;
+  std::vector<double> Xe;        // [Ne][nn][dim]
+  std::vector<double> dphi_s;    // [dim][Ns][nn]
+  std::vector<double> dphi_f;    // [dim][Nf][nn]
+  std::vector<int32_t> inc_ptr;  // [n_node + 1]
+  std::vector<int32_t> inc;      // element * nn + local node, grouped by node, increasing
+};
+
+GeoAdj build_geo_adj(const MeshIn &m, const Ops1D &ops);
 
 }  // namespace frmi

@@ -27,6 +27,7 @@
 #include <cstdint>
 
 #include "fr_device.hpp"
+#include "fr_dispatch.hpp"
 
 namespace frmi {
 
@@ -151,14 +152,6 @@ struct EulerTile {
   static constexpr int BS = round64(E * S::Ns);
 };
 
-// Which side of an interior face pair supplies the viscous normal flux of the LDG common flux
-// F^_vis = (1/2 - b) F_L + (1/2 + b) F_R: +1 (b = 1/2: the R side only), -1 (b = -1/2: the L side
-// only), 0 (both).  The same side is the one whose common solution u^ takes the neighbour's value.
-template <typename T>
-__device__ __forceinline__ int ldg_flux_side(T beta) {
-  return beta == T(0.5) ? 1 : (beta == T(-0.5) ? -1 : 0);
-}
-
 // NS volume kernel.  Per element tile:
 //   own u_f = M0 u; LDG common solution from the neighbour's u_f (or the boundary state);
 //   corrected gradient grad_xi u = D_k u + s_f g_R'(s_f xi)(u^ - u_f); grad_x u = J^-1 S^T grad_xi u;
@@ -186,7 +179,7 @@ __global__ __launch_bounds__((GradTile<D, P, T>::BS), 4) void k_ns_grad(
   T *lu = lds;                // [E][NV][Ns]
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][D][NV][Ns] gradient / F~
   tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
-  const int side = ldg_flux_side(ph.beta);
+  const int side = ph.side;
   // list of faces whose viscous normal flux is consumed (boundary faces, and interior faces on
   // the flux side); every flux point of a face shares its partner face and its side
   if (threadIdx.x < 64) {
@@ -682,28 +675,38 @@ __global__ __launch_bounds__(256) void k_wall_force(const T *__restrict__ uf, co
 }
 
 // adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du (one workgroup, probes in order)
+// u_bar += p_bar dp/du at every probe.  With x_bar: the probe is fixed in physical space, so its
+// reference coordinates xi move with its element's nodes (d xi / d X_n = -A^{-1} phi_n, tabulated
+// per probe), and x_bar += p_bar (dp/dxi) (d xi / d X).  One workgroup, probes in a fixed order.
 template <int D, int P, typename T>
 __global__ __launch_bounds__(256) void k_probe_vjp(const T *__restrict__ u, const int64_t *__restrict__ pelem,
-                                                   const double *__restrict__ pw, int n_probe, double gm1,
-                                                   const double *__restrict__ pbar, T *ubar) {
+                                                   const double *__restrict__ pw, const double *__restrict__ pdw,
+                                                   const double *__restrict__ pdxi, const int64_t *__restrict__ pnodes,
+                                                   int nn, int n_probe, double gm1, const double *__restrict__ pbar,
+                                                   T *ubar, double *xbar) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Ns = S::Ns;
   __shared__ double red[256];
   __shared__ double dpdu[NV];
+  __shared__ double xib[D];
+  auto block_sum = [&](double s) {
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  };
   for (int a = 0; a < n_probe; ++a) {
     const int64_t e = pelem[a];
     double up[NV];
     for (int v = 0; v < NV; ++v) {
       double s = 0.0;
       for (int i = threadIdx.x; i < Ns; i += blockDim.x) s += pw[(int64_t)a * Ns + i] * (double)u[(e * NV + v) * Ns + i];
-      red[threadIdx.x] = s;
-      __syncthreads();
-      for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-      }
-      up[v] = red[0];
-      __syncthreads();
+      up[v] = block_sum(s);
     }
     if (threadIdx.x == 0) {
       // p = (gamma-1)(E - |m|^2 / (2 rho)) at the interpolated state
@@ -718,6 +721,24 @@ __global__ __launch_bounds__(256) void k_probe_vjp(const T *__restrict__ u, cons
     for (int idx = threadIdx.x; idx < NV * Ns; idx += blockDim.x) {
       const int v = idx / Ns, i = idx % Ns;
       ubar[(e * NV + v) * Ns + i] += (T)(pb * dpdu[v] * pw[(int64_t)a * Ns + i]);
+    }
+    if (xbar) {
+      for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+        for (int idx = threadIdx.x; idx < NV * Ns; idx += blockDim.x) {
+          const int v = idx / Ns, i = idx % Ns;
+          s += dpdu[v] * pdw[((int64_t)a * D + k) * Ns + i] * (double)u[(e * NV + v) * Ns + i];
+        }
+        s = block_sum(s);
+        if (threadIdx.x == 0) xib[k] = pb * s;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < nn * D; idx += blockDim.x) {
+        const int n = idx / D, j = idx % D;
+        double s = 0.0;
+        for (int k = 0; k < D; ++k) s += pdxi[(((int64_t)a * nn + n) * D + j) * D + k] * xib[k];
+        xbar[pnodes[(int64_t)a * nn + n] * D + j] += s;
+      }
     }
     __syncthreads();
   }
@@ -800,11 +821,6 @@ struct Engine {
   using S = Shape<D, P>;
 
   static OpsDev<T, P> ops(const fr_solver *s) { return make_ops<T, P>(s->ops); }
-  // same test as ldg_flux_side() in the kernels, in the same precision
-  static bool ldg_two_sided(const fr_solver *s) {
-    const T b = (T)s->beta;
-    return !(b == T(0.5) || b == T(-0.5));
-  }
   static PhysDev<T> phys(const fr_solver *s) {
     PhysDev<T> p;
     p.gamma = (T)s->gamma;
@@ -812,6 +828,7 @@ struct Engine {
     p.prandtl = (T)s->prandtl;
     p.beta = (T)s->beta;
     p.tau = (T)s->tau;
+    p.side = ldg_side_of<T>(s->beta);
     return p;
   }
 
@@ -822,9 +839,13 @@ struct Engine {
 
   // one residual evaluation of `u` whose flux-point values are already in s->uf; the epilogue
   // `rk` decides what is written
-  static void stage(const fr_solver *s, const T *u, const RKArgs<T> &rk, hipStream_t st, bool force_sample) {
+  // two_sided: store the viscous normal flux at every flux point and form the common flux in the
+  // face kernel whatever beta is (the mesh-node adjoint reads both)
+  static void stage(const fr_solver *s, const T *u, const RKArgs<T> &rk, hipStream_t st, bool force_sample,
+                    bool two_sided = false) {
     const OpsDev<T, P> o = ops(s);
-    const PhysDev<T> ph = phys(s);
+    PhysDev<T> ph = phys(s);
+    if (two_sided) ph.side = 0;
     const int64_t nface = s->npair + s->nbnd;
     T *uf = (T *)s->uf, *fhat = (T *)s->fhat;
     const T *metric = (const T *)s->metric;
@@ -843,7 +864,7 @@ struct Engine {
         k_wall_force<D, P, T><<<s->n_mesh, 256, 0, st>>>(uf, fvn, s->bnd, (const T *)s->bnd_nrm, s->bnd_w,
                                                           s->wall_mesh_begin, ph, s->force_acc);
       }
-      if (ldg_two_sided(s)) {  // one-sided LDG: the common flux was formed inside k_ns_grad
+      if (ph.side == 0) {  // one-sided LDG: the common flux was formed inside k_ns_grad
         ProfScope ps(s, 3, st);
         k_face_flux<D, P, T, true><<<nblk(nface, 256), 256, 0, st>>>(
             uf, fvn, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
@@ -866,11 +887,11 @@ struct Engine {
     }
   }
 
-  static void rhs(const fr_solver *s, const T *u, T *r, hipStream_t st) {
+  static void rhs(const fr_solver *s, const T *u, T *r, hipStream_t st, bool two_sided = false) {
     interp(s, u, (T *)s->uf, st);
     RKArgs<T> rk{};
     rk.r_out = r;
-    stage(s, u, rk, st, false);
+    stage(s, u, rk, st, false, two_sided);
   }
 
   static void probe(const fr_solver *s, const T *u, hipStream_t st) {
@@ -907,21 +928,16 @@ struct Engine {
 };
 
 // ------------------------------------------------------------------------------------ dispatch
-struct Dispatch {
-  void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
-  void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
-  void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, hipStream_t);
-  void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, hipStream_t);
-  void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
-                         const double *, hipStream_t);
-  void (*zero)(const fr_solver *, void *, hipStream_t);
-};
+
 
 template <int D, int P, typename T>
 Dispatch make_dispatch() {
   Dispatch d;
   d.rhs = [](const fr_solver *s, const void *u, void *r, hipStream_t st) {
     Engine<D, P, T>::rhs(s, (const T *)u, (T *)r, st);
+  };
+  d.rhs_two_sided = [](const fr_solver *s, const void *u, void *r, hipStream_t st) {
+    Engine<D, P, T>::rhs(s, (const T *)u, (T *)r, st, true);
   };
   d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
     Engine<D, P, T>::step(s, (T *)u, dt, sample, fresh, st);
@@ -935,10 +951,11 @@ Dispatch make_dispatch() {
       Engine<D, P, T>::step(s, (T *)u, dt, false, k == 0, st, (T *)stages + 3 * nb * k,
                             states ? (T *)states + nb * k : nullptr);
   };
-  d.probe_vjp = [](const fr_solver *s, const void *u, const double *pbar, void *ub, hipStream_t st) {
+  d.probe_vjp = [](const fr_solver *s, const void *u, const double *pbar, void *ub, double *xbar, hipStream_t st) {
     if (s->n_probe > 0)
-      k_probe_vjp<D, P, T><<<1, 256, 0, st>>>((const T *)u, s->probe_elem, s->probe_w, s->n_probe,
-                                              s->gamma - 1.0, pbar, (T *)ub);
+      k_probe_vjp<D, P, T><<<1, 256, 0, st>>>((const T *)u, s->probe_elem, s->probe_w, s->probe_dw, s->probe_dxi,
+                                              s->probe_nodes, s->geo_nn, s->n_probe, s->gamma - 1.0, pbar,
+                                              (T *)ub, xbar);
   };
   d.rk_adj_combine = [](const fr_solver *s, void *a, void *z, void *kb, void *ub, void *zz, double ca, double cz,
                         const double *dt, hipStream_t st) {
@@ -969,6 +986,15 @@ bool get_dispatch(int dim, int p, int precision, Dispatch &out) {
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t st) {
   if (n > 0) k_fill_f64<<<nblk(n, 256), 256, 0, st>>>(p, n, v);
+}
+
+// zero n values of the state precision
+void launch_fill_state(const fr_solver *s, void *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  if (s->precision == 0)
+    k_fill_t<double><<<nblk(n, 256), 256, 0, st>>>((double *)p, n);
+  else
+    k_fill_t<float><<<nblk(n, 256), 256, 0, st>>>((float *)p, n);
 }
 
 void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st) {

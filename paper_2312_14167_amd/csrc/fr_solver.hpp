@@ -46,7 +46,17 @@ inline OpsDev<T, P> make_ops(const Ops1D &h) {
 template <typename T>
 struct PhysDev {
   T gamma, gm1, prandtl, beta, tau;
+  // side of an interior face pair that supplies the viscous part of the LDG common flux:
+  // +1 (beta = 1/2: R), -1 (beta = -1/2: L), 0 (both sides, any other beta)
+  int side;
 };
+
+// LDG flux side for beta in precision T
+template <typename T>
+inline int ldg_side_of(double beta) {
+  const T b = (T)beta;
+  return b == T(0.5) ? 1 : (b == T(-0.5) ? -1 : 0);
+}
 
 }  // namespace frmi
 
@@ -110,6 +120,24 @@ struct fr_solver {
   mutable std::vector<hipEvent_t> prof_pool;
   double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t prof_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // mesh-node adjoint: host copy of the mesh; tables and work arrays uploaded / allocated on first use
+  int geom_q = 1;
+  int64_t n_node = 0;
+  std::vector<double> h_node_xyz;
+  std::vector<int64_t> h_elem_nodes;
+  int geo_nn = 0;
+  double *geo_Xe = nullptr;       // [Ne][nn][dim] element node coordinates
+  double *geo_dphi_s = nullptr;   // [dim][Ns][nn]
+  double *geo_dphi_f = nullptr;   // [dim][Nf][nn]
+  double *geo_Xeb = nullptr;      // [Ne][nn][dim] per-element node adjoint
+  int32_t *geo_inc_ptr = nullptr, *geo_inc = nullptr;
+  void *geo_Gm = nullptr;         // [Ne][dim*dim+1][Ns] adjoint of S rows and 1/J (state precision)
+  void *geo_Gn = nullptr;         // [Ne][dim+1][Nf] adjoint of the unit normal and |N| at own flux points
+  void *geo_R = nullptr;          // [Ne][nv][Ns] forward residual at the linearisation state
+  double *probe_dw = nullptr;     // [n_probe][dim][Ns] d weights / d xi
+  double *probe_dxi = nullptr;    // [n_probe][nn][dim][dim] d xi_k / d X_{n,j}
+  int64_t *probe_nodes = nullptr; // [n_probe][nn]
 
   // VJP work arrays (allocated on first use)
   void *vjp_work = nullptr;

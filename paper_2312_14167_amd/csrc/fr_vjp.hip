@@ -16,6 +16,7 @@
 #include <cstdint>
 
 #include "fr_device.hpp"
+#include "fr_dispatch.hpp"
 
 namespace frmi {
 
@@ -167,7 +168,7 @@ __device__ __forceinline__ void fvis_vjp(const T *st, const T *g, const T *m, T 
 // adjoint of farfield(): uLb += (d ub / d uL)^T ubb
 template <int D, typename T>
 __device__ __forceinline__ void farfield_vjp(const T *uL, const T *n, const FlowDev<T> &fl, T gamma, T gm1,
-                                             const T *ubb, T *uLb) {
+                                             const T *ubb, T *uLb, T *nb = nullptr) {
   // forward recompute
   const T rL = uL[0];
   T vL[D], m2 = T(0);
@@ -209,6 +210,16 @@ __device__ __forceinline__ void farfield_vjp(const T *uL, const T *n, const Flow
   const T sb = -Xb * X / s;
   T vnb = T(0);
   for (int j = 0; j < D; ++j) vnb += vb[j] * n[j];
+  if (nb) {
+    // n enters through v = w + (vn - vn_w) n (w = v_L or v_inf by the branch), vn and c; the
+    // branch itself (sign of vn) is piecewise constant
+    const T vnw = out ? vnL : vni;
+    for (int m = 0; m < D; ++m) {
+      const T dvn = T(0.5) * (vL[m] + fl.v[m]), dc = T(0.25) * gm1 * (vL[m] - fl.v[m]);
+      const T dvw = out ? vL[m] : fl.v[m];
+      nb[m] += (dvn - dvw) * vnb + (vn - vnw) * vb[m] + cb * dc;
+    }
+  }
   const T Rpb = T(0.5) * vnb + T(0.25) * gm1 * cb;
   T vnLb = Rpb;
   T cLb = T(2) * Rpb / gm1;
@@ -249,6 +260,88 @@ __device__ __forceinline__ void wall_state_vjp(const T *uB, const T *wb, T *uBb)
   uBb[D + 1] += wb[D + 1];
 }
 
+// row k of a small matrix without dynamic indexing into a private array (k is a loop counter of
+// a loop the compiler keeps rolled)
+template <int D, typename T>
+__device__ __forceinline__ void pick_row(const T (&M)[D][D], int k, T (&r)[D]) {
+  for (int j = 0; j < D; ++j) {
+    r[j] = M[0][j];
+    for (int q = 1; q < D; ++q)
+      if (k == q) r[j] = M[q][j];
+  }
+}
+
+// ------------------------------------------------------------------------------------ geometric adjoints
+// nb += d(Fb . rusanov(uL, uR, n)) / dn with the states held fixed (the wave-speed max follows
+// the tie rule of rusanov_vjp)
+template <int D, typename T>
+__device__ __forceinline__ void rusanov_n_vjp(const T *uL, const T *uR, const T *n, T gamma, T gm1, const T *Fb,
+                                              T *nb) {
+  constexpr int NV = D + 2;
+  T rL, vL[D], pL, rR, vR[D], pR;
+  primitives<D>(uL, gm1, rL, vL, pL);
+  primitives<D>(uR, gm1, rR, vR, pR);
+  // 1/2 (F_inv(uL) + F_inv(uR)) . n: column j dotted with Fb
+  for (int j = 0; j < D; ++j) {
+    T s = Fb[0] * (uL[1 + j] + uR[1 + j]) + Fb[D + 1] * (vL[j] * (uL[D + 1] + pL) + vR[j] * (uR[D + 1] + pR));
+    for (int i = 0; i < D; ++i) s += Fb[1 + i] * (uL[1 + i] * vL[j] + uR[1 + i] * vR[j]);
+    s += Fb[1 + j] * (pL + pR);
+    nb[j] += T(0.5) * s;
+  }
+  T vnL = T(0), vnR = T(0), lamb = T(0);
+  for (int j = 0; j < D; ++j) { vnL += vL[j] * n[j]; vnR += vR[j] * n[j]; }
+  for (int v = 0; v < NV; ++v) lamb -= T(0.5) * Fb[v] * (uR[v] - uL[v]);
+  const T aL = fabs(vnL) + sqrt(gamma * pL / rL), aR = fabs(vnR) + sqrt(gamma * pR / rR);
+  const T tol = (sizeof(T) == 8 ? T(1e-12) : T(1e-5)) * (aL >= aR ? aL : aR);
+  const T wL = aL - aR > tol ? T(1) : (aR - aL > tol ? T(0) : T(0.5));
+  const T sL = vnL > T(0) ? T(1) : (vnL < T(0) ? T(-1) : T(0));
+  const T sR = vnR > T(0) ? T(1) : (vnR < T(0) ? T(-1) : T(0));
+  for (int j = 0; j < D; ++j) nb[j] += lamb * (wL * sL * vL[j] + (T(1) - wL) * sR * vR[j]);
+}
+
+// out[j] += sum_v w[v] F_vis,j[v] (viscous flux column j, from the viscous state vs)
+template <int D, typename T>
+__device__ __forceinline__ void fvis_columns_dot(const Visc<D, T> &vs, const T *w, T *out) {
+  for (int j = 0; j < D; ++j) {
+    T s = T(0), en = T(0);
+    for (int i = 0; i < D; ++i) {
+      s += w[1 + i] * vs.tau[i][j];
+      en += vs.v[i] * vs.tau[i][j];
+    }
+    out[j] += s + w[D + 1] * (en - vs.q[j]);
+  }
+}
+
+// out[j] += sum_v w[v] F_inv,j[v] (inviscid flux column j)
+template <int D, typename T>
+__device__ __forceinline__ void finv_columns_dot(const T *u, T gm1, const T *w, T *out) {
+  T rho, v[D], p;
+  primitives<D>(u, gm1, rho, v, p);
+  for (int j = 0; j < D; ++j) {
+    T s = w[0] * u[1 + j] + w[D + 1] * v[j] * (u[D + 1] + p) + w[1 + j] * p;
+    for (int i = 0; i < D; ++i) s += w[1 + i] * u[1 + i] * v[j];
+    out[j] += s;
+  }
+}
+
+// A = adj(S) (1/J)^(D-2) from the stored metric (S = adj(A)), A[j][k] = dx_j/dxi_k
+template <int D, typename T>
+__device__ __forceinline__ void jacobian_from_metric(const T (&Sm)[D][D], T invJ, T (&A)[D][D]) {
+  if (D == 2) {
+    A[0][0] = Sm[1][1];
+    A[0][1] = -Sm[0][1];
+    A[1][0] = -Sm[1][0];
+    A[1][1] = Sm[0][0];
+  } else {
+    for (int r = 0; r < D; ++r) {
+      const int a = (r + 1) % D, b = (r + 2) % D;  // row r of adj(S) = column a x column b of S
+      A[r][0] = (Sm[1][a] * Sm[2][b] - Sm[2][a] * Sm[1][b]) * invJ;
+      A[r][1] = (Sm[2][a] * Sm[0][b] - Sm[0][a] * Sm[2][b]) * invJ;
+      A[r][2] = (Sm[0][a] * Sm[1][b] - Sm[1][a] * Sm[0][b]) * invJ;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------ kernels
 template <int D, int P, typename T>
 struct VjpDivTile {
@@ -260,12 +353,14 @@ struct VjpDivTile {
 
 // w = -(1/J) r_bar -> vol_bar (solution points) and F^_bar = Lift^T w (flux points); also the
 // forward flux-point values u_f = M0 u at the linearisation point (read by the face adjoint)
-template <int D, int P, typename T>
+// GEO: also the adjoint of 1/J, r_bar . R / (1/J) (R the forward residual), into Gm
+template <int D, int P, typename T, bool GEO>
 __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *__restrict__ rbar,
                                                                        const T *__restrict__ u,
                                                                        const T *__restrict__ metric,
                                                                        OpsDev<T, P> ops_arg, T *__restrict__ volbar,
                                                                        T *__restrict__ fhatbar, T *__restrict__ uf,
+                                                                       const T *__restrict__ Rf, T *__restrict__ Gm,
                                                                        int64_t Ne) {
   using S = Shape<D, P>;
   using TL = VjpDivTile<D, P, T>;
@@ -281,11 +376,15 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
   if (el < ne) {
     const int64_t e = e0 + el;
     const T invJ = metric[(e * NM + D * D) * Ns + i];
+    T gj = T(0);
     for (int v = 0; v < NV; ++v) {
-      const T w = -invJ * rbar[(e * NV + v) * Ns + i];
+      const T rb = rbar[(e * NV + v) * Ns + i];
+      const T w = -invJ * rb;
       lw[(el * NV + v) * Ns + i] = w;
       volbar[(e * NV + v) * Ns + i] = w;
+      if (GEO) gj += rb * Rf[(e * NV + v) * Ns + i];
     }
+    if (GEO) Gm[(e * NM + D * D) * Ns + i] += gj / invJ;
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) {
@@ -308,14 +407,17 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
 }
 
 // adjoint of the common-flux kernel: u_f_bar of both sides and (NS) the viscous-normal-flux adjoints
-template <int D, int P, typename T, bool NS>
+// GEO: also the adjoints of the unit normal (Rusanov, far-field ghost) and of |N| (from the
+// forward common flux fhatf) at the owning point (L side / boundary point), into Gn
+template <int D, int P, typename T, bool NS, bool GEO>
 __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, const T *__restrict__ fhatbar,
                                                   const int32_t *__restrict__ pairL, const int32_t *__restrict__ pairR,
                                                   const T *__restrict__ pnrm, int64_t npair,
                                                   const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
                                                   int64_t n_wall, int64_t nbnd, const int32_t *__restrict__ elem_mesh,
                                                   const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
-                                                  T *__restrict__ ufbar, T *__restrict__ fvnbar) {
+                                                  T *__restrict__ ufbar, T *__restrict__ fvnbar,
+                                                  const T *__restrict__ fhatf, T *__restrict__ Gn) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Nf = S::Nf;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -334,6 +436,15 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
       uRb[v] = T(0);
     }
     rusanov_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, uLb, uRb);
+    if (GEO) {
+      T nb[D];
+      for (int j = 0; j < D; ++j) nb[j] = T(0);
+      rusanov_n_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, nb);
+      T mb = T(0);
+      for (int v = 0; v < NV; ++v) mb += Fb[v] * fhatf[(eL * NV + v) * Nf + fL];
+      for (int j = 0; j < D; ++j) Gn[(eL * (D + 1) + j) * Nf + fL] += nb[j];
+      Gn[(eL * (D + 1) + D) * Nf + fL] += mb / (mag * mag);
+    }
     if (NS) {
       const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
       for (int v = 0; v < NV; ++v) {
@@ -371,12 +482,21 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
       farfield<D>(uB, n, fl, ph.gamma, ph.gm1, ug);
     }
     rusanov_vjp<D>(uB, ug, n, ph.gamma, ph.gm1, Fb, uBb, ugb);
+    T nb[D];
+    for (int j = 0; j < D; ++j) nb[j] = T(0);
+    if (GEO) rusanov_n_vjp<D>(uB, ug, n, ph.gamma, ph.gm1, Fb, nb);
     if (wall) {
       uBb[0] += ugb[0];
       for (int j = 0; j < D; ++j) uBb[1 + j] -= ugb[1 + j];
       uBb[D + 1] += ugb[D + 1];
     } else {
-      farfield_vjp<D>(uB, n, fl, ph.gamma, ph.gm1, ugb, uBb);
+      farfield_vjp<D>(uB, n, fl, ph.gamma, ph.gm1, ugb, uBb, GEO ? nb : nullptr);
+    }
+    if (GEO) {
+      T mb = T(0);
+      for (int v = 0; v < NV; ++v) mb += Fb[v] * fhatf[(e * NV + v) * Nf + fp];
+      for (int j = 0; j < D; ++j) Gn[(e * (D + 1) + j) * Nf + fp] += nb[j];
+      Gn[(e * (D + 1) + D) * Nf + fp] += mb / (mag * mag);
     }
     for (int v = 0; v < NV; ++v) {
       ufbar[(e * NV + v) * Nf + fp] = uBb[v];
@@ -399,12 +519,16 @@ struct VjpVolTile {
 // NS volume adjoint (see the file header); writes the solution-point adjoint ubvol (may alias
 // volbar: each tile reads its vol_bar before writing), the own-flux-point adjoint ufb_own and the
 // neighbour-slot adjoint ufb_nbr
-template <int D, int P, typename T>
+// GEO: also the metric adjoints (S rows from F~_k = S_k . F and from the gradient transform,
+// 1/J from the gradient transform) into Gm, and the unit-normal adjoints of the viscous normal
+// flux and of the far-field states at own flux points into Gn
+template <int D, int P, typename T, bool GEO>
 __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
     const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, const T *volbar,
-    const T *__restrict__ fvnbar, const T *ufb_face, T *ubvol, T *ufb_own, T *__restrict__ ufb_nbr, int64_t Ne) {
+    const T *__restrict__ fvnbar, const T *ufb_face, T *ubvol, T *ufb_own, T *__restrict__ ufb_nbr,
+    T *__restrict__ Gm, T *__restrict__ Gn, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = VjpVolTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
@@ -479,6 +603,8 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       int base, stride, ik, t;
       line_of_sol<D, P>(i, k, base, stride, ik, t);
       const T cm = -ops.gm[ik], cp = ops.gp[ik];
+      T Sk[D];
+      pick_row<D>(Sm, k, Sk);
       for (int v = 0; v < NV; ++v) {
         const T *lin = lu + (el * NV + v) * Ns + base;
         T s = T(0);
@@ -486,7 +612,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
         for (int a = 0; a < P; ++a) s += ops.D[ik * P + a] * lin[a * stride];
         const T *ld = ldu + (el * NV + v) * Nf;
         s += cm * ld[(2 * k) * Nfp + t] + cp * ld[(2 * k + 1) * Nfp + t];
-        for (int j = 0; j < D; ++j) gx[j][v] += Sm[k][j] * s;
+        for (int j = 0; j < D; ++j) gx[j][v] += Sk[j] * s;
       }
     }
     for (int j = 0; j < D; ++j)
@@ -502,7 +628,8 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
   // adjoint of the viscous normal flux at own flux points (one flux point per thread)
   const int ef_idx = threadIdx.x;
   const bool actf = ef_idx < ne * Nf;
-  T gbf[D * NV], stb[NV];
+  T gbf[D * NV], stb[NV], nbv[D];
+  for (int j = 0; j < D; ++j) nbv[j] = T(0);
   int fpl = 0, elf = 0;
   if (actf) {
     elf = ef_idx / Nf;
@@ -545,11 +672,16 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
     T ubb[NV];
     for (int v = 0; v < NV; ++v) ubb[v] = T(0);
     fvis_vjp<D>(ub, g, n, flow[elem_mesh[ef]].mu, ph, heat, fb, ubb, gbf);
+    if (GEO) {  // fvn = F_vis(ub, g) . n
+      Visc<D, T> vs;
+      visc_state<D>(ub, g, flow[elem_mesh[ef]].mu, ph, heat, vs);
+      fvis_columns_dot<D>(vs, fb, nbv);
+    }
     if (code < 0) {
       if (wall)
         wall_state_vjp<D>(st, ubb, stb);
       else
-        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ubb, stb);
+        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ubb, stb, GEO ? nbv : nullptr);
     } else {
       for (int v = 0; v < NV; ++v) stb[v] = ubb[v];
     }
@@ -573,6 +705,8 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
     T gxb[D * NV];
     for (int q = 0; q < D * NV; ++q) gxb[q] = T(0);
     for (int v = 0; v < NV; ++v) ubs[v] = T(0);
+    Visc<D, T> vs0;
+    if (GEO) visc_state<D>(uv, &gx[0][0], flow[elem_mesh[e]].mu, ph, true, vs0);
 #pragma unroll 1
     for (int k = 0; k < D; ++k) {
       int base, stride, ik, t;
@@ -585,9 +719,18 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
         for (int a = 0; a < P; ++a) sd += ops.Dt[a * P + ik] * lin[a * stride];
         ftb[v] = sd;
       }
-      finv_dot_vjp<D>(uv, Sm[k], ph.gm1, ftb, ubs);
+      if (GEO) {  // F~_k = S_k . (F_inv - F_vis):  S_k_bar += F^T F~_k_bar
+        T sk[D], sv[D];
+        for (int j = 0; j < D; ++j) sk[j] = sv[j] = T(0);
+        finv_columns_dot<D>(uv, ph.gm1, ftb, sk);
+        fvis_columns_dot<D>(vs0, ftb, sv);
+        for (int j = 0; j < D; ++j) Gm[(e * NM + k * D + j) * Ns + i] += sk[j] - sv[j];
+      }
+      T Sk[D];
+      pick_row<D>(Sm, k, Sk);
+      finv_dot_vjp<D>(uv, Sk, ph.gm1, ftb, ubs);
       for (int v = 0; v < NV; ++v) ftb[v] = -ftb[v];
-      fvis_vjp<D>(uv, &gx[0][0], Sm[k], flow[elem_mesh[e]].mu, ph, true, ftb, ubs, gxb);
+      fvis_vjp<D>(uv, &gx[0][0], Sk, flow[elem_mesh[e]].mu, ph, true, ftb, ubs, gxb);
       // flux-point gradient adjoint back to this solution point (M0^T along the k-line)
       for (int j = 0; j < D; ++j)
         for (int v = 0; v < NV; ++v) {
@@ -602,6 +745,29 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
         for (int j = 0; j < D; ++j) s += Sm[k][j] * gxb[j * NV + v];
         grb[k][v] = invJ * s;
       }
+    if (GEO) {
+      // S_bar[k][j] += (1/J) sum_v grad_xi_k u_v gxb[j][v] with grad_xi u = A^T grad_x u;
+      // (1/J)_bar += sum gxb . grad_x u / (1/J)
+      T A[D][D];
+      jacobian_from_metric<D>(Sm, invJ, A);
+      T gj = T(0);
+      for (int j = 0; j < D; ++j)
+        for (int v = 0; v < NV; ++v) gj += gxb[j * NV + v] * gx[j][v];
+      Gm[(e * NM + D * D) * Ns + i] += gj / invJ;
+      for (int k = 0; k < D; ++k) {
+        T gk[NV];
+        for (int v = 0; v < NV; ++v) {
+          T s = T(0);
+          for (int j = 0; j < D; ++j) s += A[j][k] * gx[j][v];
+          gk[v] = s;
+        }
+        for (int j = 0; j < D; ++j) {
+          T s = T(0);
+          for (int v = 0; v < NV; ++v) s += gk[v] * gxb[j * NV + v];
+          Gm[(e * NM + k * D + j) * Ns + i] += invJ * s;
+        }
+      }
+    }
   }
   __syncthreads();
   T *lrb = lA;  // [E][D][NV][Ns] reference-gradient adjoint
@@ -661,19 +827,22 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       } else {
         T n[D];
         for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
-        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, dub, own);
+        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, dub, own, GEO ? nbv : nullptr);
       }
     }
     for (int v = 0; v < NV; ++v) ufb_own[(ef * NV + v) * Nf + fpl] = own[v];
+    if (GEO)
+      for (int j = 0; j < D; ++j) Gn[(ef * (D + 1) + j) * Nf + fpl] += nbv[j];
   }
 }
 
 // Euler volume adjoint: F~_bar from vol_bar, pointwise inviscid-flux adjoint
-template <int D, int P, typename T>
+template <int D, int P, typename T, bool GEO>
 __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_euler_vol(const T *__restrict__ u,
                                                                              const T *__restrict__ metric,
                                                                              OpsDev<T, P> ops_arg, PhysDev<T> ph,
-                                                                             const T *volbar, T *ubvol, int64_t Ne) {
+                                                                             const T *volbar, T *ubvol,
+                                                                             T *__restrict__ Gm, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = VjpDivTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, NV = S::NV, NM = S::NM;
@@ -704,6 +873,12 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_euler_vol(con
 #pragma unroll
       for (int a = 0; a < P; ++a) sd += ops.Dt[a * P + ik] * lin[a * stride];
       ftb[v] = sd;
+    }
+    if (GEO) {  // S_k_bar += F_inv^T F~_k_bar
+      T sk[D];
+      for (int j = 0; j < D; ++j) sk[j] = T(0);
+      finv_columns_dot<D>(uv, ph.gm1, ftb, sk);
+      for (int j = 0; j < D; ++j) Gm[(e * NM + k * D + j) * Ns + i] += sk[j];
     }
     finv_dot_vjp<D>(uv, Sk, ph.gm1, ftb, ubs);
   }
@@ -770,7 +945,16 @@ template <int D, int P, typename T>
 struct VjpEngine {
   using S = Shape<D, P>;
   static void run(const fr_solver *s, const T *u, const T *rbar, T *ubar, T *work, const AdjRK<T> &rk,
-                  hipStream_t st) {
+                  const GeoVjpArgs &geo, hipStream_t st) {
+    if (geo.Gm)
+      run_t<true>(s, u, rbar, ubar, work, rk, geo, st);
+    else
+      run_t<false>(s, u, rbar, ubar, work, rk, geo, st);
+  }
+
+  template <bool GEO>
+  static void run_t(const fr_solver *s, const T *u, const T *rbar, T *ubar, T *work, const AdjRK<T> &rk,
+                    const GeoVjpArgs &geo, hipStream_t st) {
     const OpsDev<T, P> o = make_ops<T, P>(s->ops);
     PhysDev<T> ph;
     ph.gamma = (T)s->gamma;
@@ -778,6 +962,7 @@ struct VjpEngine {
     ph.prandtl = (T)s->prandtl;
     ph.beta = (T)s->beta;
     ph.tau = (T)s->tau;
+    ph.side = ldg_side_of<T>(s->beta);
     const int64_t Ne = s->Ne, nsol = Ne * S::NV * S::Ns, nf = Ne * S::NV * S::Nf;
     T *volbar = work;            // also the solution-point adjoint (read before write per tile)
     T *fhatbar = volbar + nsol;  // also the own flux-point adjoint
@@ -787,23 +972,25 @@ struct VjpEngine {
     T *uf = (T *)s->uf;
     const T *metric = (const T *)s->metric;
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
+    T *Gm = (T *)geo.Gm, *Gn = (T *)geo.Gn;
+    const T *Rf = (const T *)geo.R, *fhf = (const T *)geo.fhat;
     using TD = VjpDivTile<D, P, T>;
-    k_vjp_div<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, u, metric, o, volbar, fhatbar, uf, Ne);
+    k_vjp_div<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, u, metric, o, volbar, fhatbar, uf, Rf, Gm, Ne);
     const int64_t nface = s->npair + s->nbnd;
     if (s->equations == 1) {
-      k_vjp_face<D, P, T, true><<<vblk(nface, 256), 256, 0, st>>>(
+      k_vjp_face<D, P, T, true, GEO><<<vblk(nface, 256), 256, 0, st>>>(
           uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, fvnbar);
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, fvnbar, fhf, Gn);
       using TV = VjpVolTile<D, P, T>;
-      k_vjp_ns_vol<D, P, T><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
+      k_vjp_ns_vol<D, P, T, GEO><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
           u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
-          volbar, fvnbar, ufbface, volbar, fhatbar, ufbnbr, Ne);
+          volbar, fvnbar, ufbface, volbar, fhatbar, ufbnbr, Gm, Gn, Ne);
       k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, fhatbar, ufbnbr, o, ubar, rk, Ne);
     } else {
-      k_vjp_face<D, P, T, false><<<vblk(nface, 256), 256, 0, st>>>(
+      k_vjp_face<D, P, T, false, GEO><<<vblk(nface, 256), 256, 0, st>>>(
           uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr);
-      k_vjp_euler_vol<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(u, metric, o, ph, volbar, volbar, Ne);
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr, fhf, Gn);
+      k_vjp_euler_vol<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(u, metric, o, ph, volbar, volbar, Gm, Ne);
       k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, nullptr, o, ubar, rk, Ne);
     }
   }
@@ -818,19 +1005,20 @@ size_t vjp_work_elems(const fr_solver *s) {
 // with z = (dR/du (u))^T r_bar, rk_ub += z and rk_kb = dt (ca rk_a + cz z) (rk_kb may be r_bar:
 // it is read by the first kernel and written by the last).
 bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, const void *rk_a,
-                void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, hipStream_t st) {
+                void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, const GeoVjpArgs &geo,
+                hipStream_t st) {
 #define FR_VCASE(DD, PP)                                                                              \
   if (s->dim == DD && s->p + 1 == PP) {                                                               \
     if (s->precision == 0) {                                                                          \
       AdjRK<double> rk{(double *)rk_a, (double *)rk_kb, (double *)(rk_a ? rk_ub : nullptr), dt,       \
                        s->elem_mesh, ca, cz};                                                         \
       VjpEngine<DD, PP, double>::run(s, (const double *)u, (const double *)rbar, (double *)ubar,      \
-                                     (double *)work, rk, st);                                         \
+                                     (double *)work, rk, geo, st);                                    \
     } else {                                                                                          \
       AdjRK<float> rk{(float *)rk_a, (float *)rk_kb, (float *)(rk_a ? rk_ub : nullptr), dt,           \
                       s->elem_mesh, (float)ca, (float)cz};                                            \
       VjpEngine<DD, PP, float>::run(s, (const float *)u, (const float *)rbar, (float *)ubar,          \
-                                    (float *)work, rk, st);                                           \
+                                    (float *)work, rk, geo, st);                                      \
     }                                                                                                 \
     return true;                                                                                      \
   }

@@ -67,6 +67,8 @@ class Solver:
                         rho_inf=_ptr(rho), vel_inf=_ptr(vel), p_inf=_ptr(pin), mu=_ptr(mu),
                         n_probe=npb, max_samples=max(int(max_samples), 1 if npb else 0),
                         probe_xyz=_ptr(pxyz), probe_mesh=_ptr(pm), forces=1 if forces else 0, reserved0=0)
+        self.n_node = int(node.shape[0])
+        self.node_xyz = node.copy()
         h = C.c_void_p()
         check(L.fr_build_operators(C.byref(md), C.byref(prm), C.byref(h)))
         self._h = h
@@ -141,17 +143,26 @@ class Solver:
         keys = ["n_elem", "nv", "ns", "nf", "n_pairs", "n_boundary", "n_wall", "n_mesh"]
         return dict(zip(keys, (int(x) for x in a)))
 
+    def _xbar_ptr(self, x_bar):
+        if x_bar is None:
+            return None
+        if not (x_bar.is_cuda and x_bar.dtype == torch.float64 and tuple(x_bar.shape) == (self.n_node, self.dim)
+                and x_bar.is_contiguous()):
+            raise ValueError(f"x_bar must be a contiguous float64 CUDA tensor of shape {(self.n_node, self.dim)}")
+        return C.c_void_p(x_bar.data_ptr())
+
     def _check_dt(self, dt):
         if not (dt.is_cuda and dt.dtype == torch.float64 and dt.numel() == self.n_mesh and dt.is_contiguous()):
             raise ValueError("dt must be a contiguous float64 CUDA tensor with one entry per mesh")
 
-    def probe_vjp(self, u: torch.Tensor, p_bar: torch.Tensor, u_bar: torch.Tensor, stream=None):
-        """u_bar += sum_a p_bar[a] dp_a/du (p_bar: float64 CUDA tensor [n_probe])."""
+    def probe_vjp(self, u: torch.Tensor, p_bar: torch.Tensor, u_bar: torch.Tensor, x_bar=None, stream=None):
+        """u_bar += sum_a p_bar[a] dp_a/du (p_bar: float64 CUDA tensor [n_probe]); with x_bar
+        (float64 [n_node, dim]) also x_bar += sum_a p_bar[a] dp_a/dX."""
         self._check_state(u, "u")
         self._check_state(u_bar, "u_bar")
         p_bar = p_bar.to(device=u.device, dtype=torch.float64).contiguous()
         check(lib().fr_probe_vjp(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(p_bar.data_ptr()),
-                                 C.c_void_p(u_bar.data_ptr()), _stream(stream)))
+                                 C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
         return u_bar
 
     def rk_step_stages(self, u: torch.Tensor, dt: torch.Tensor, stages: torch.Tensor, states=None, stream=None):
@@ -175,14 +186,16 @@ class Solver:
                                       C.c_void_p(stages.data_ptr()), _stream(stream)))
         return u
 
-    def rk_step_vjp(self, u_n: torch.Tensor, dt: torch.Tensor, u_bar: torch.Tensor, stages=None, stream=None):
-        """u_bar <- (d u_{n+1} / d u_n)^T u_bar for one RK4 step from u_n."""
+    def rk_step_vjp(self, u_n: torch.Tensor, dt: torch.Tensor, u_bar: torch.Tensor, stages=None, x_bar=None,
+                    stream=None):
+        """u_bar <- (d u_{n+1} / d u_n)^T u_bar for one RK4 step from u_n; with x_bar (float64
+        [n_node, dim]) also x_bar += (d u_{n+1} / dX)^T u_bar."""
         self._check_state(u_n, "u_n")
         self._check_state(u_bar, "u_bar")
         self._check_dt(dt)
         sp = C.c_void_p(stages.data_ptr()) if stages is not None else None
         check(lib().fr_rk_step_vjp(self._h, C.c_void_p(u_n.data_ptr()), C.c_void_p(dt.data_ptr()), sp,
-                                   C.c_void_p(u_bar.data_ptr()), _stream(stream)))
+                                   C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
         return u_bar
 
     def rhs_vjp(self, u: torch.Tensor, r_bar: torch.Tensor, u_bar: torch.Tensor, x_bar: torch.Tensor | None = None,
@@ -190,7 +203,6 @@ class Solver:
         self._check_state(u, "u")
         self._check_state(r_bar, "r_bar")
         self._check_state(u_bar, "u_bar")
-        xb = C.c_void_p(x_bar.data_ptr()) if x_bar is not None else None
         check(lib().fr_rhs_vjp(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(r_bar.data_ptr()),
-                               C.c_void_p(u_bar.data_ptr()), xb, _stream(stream)))
+                               C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
         return u_bar

@@ -44,7 +44,7 @@ def test_trajectory_gradient_matches_oracle_and_fd(gpu):
     sol = Solver(m, p, fp, equations="ns", probes=probes, max_samples=K)
     dtt = torch.tensor([dt], dtype=torch.float64, device=gpu)
     ug = u0.to(gpu).clone().requires_grad_(True)
-    P = FRTrajectory.apply(ug, sol, dtt, K, C)
+    P = FRTrajectory.apply(ug, sol, dtt, K, C, None)
     J = _objective(P)
     J.backward()
     g = ug.grad
@@ -66,8 +66,8 @@ def test_trajectory_gradient_matches_oracle_and_fd(gpu):
         v = torch.tensor(rng.normal(size=u0.shape), device=gpu) * 1e-2
         eps = 1e-4
         with torch.no_grad():
-            Jp = _objective(FRTrajectory.apply(u0.to(gpu) + eps * v, sol, dtt, K, C))
-            Jm = _objective(FRTrajectory.apply(u0.to(gpu) - eps * v, sol, dtt, K, C))
+            Jp = _objective(FRTrajectory.apply(u0.to(gpu) + eps * v, sol, dtt, K, C, None))
+            Jm = _objective(FRTrajectory.apply(u0.to(gpu) - eps * v, sol, dtt, K, C, None))
         fd = float((Jp - Jm) / (2 * eps))
         ad = float((g * v).sum())
         print(f"directional derivative: central difference {fd:.10e} adjoint {ad:.10e}")
@@ -136,7 +136,7 @@ def test_adjoint_full_size_cylinder_80x64(gpu):
     dtt = torch.tensor([1e-4], dtype=torch.float64, device=gpu)
     K, C = 200, 20
     ug = u0.clone().requires_grad_(True)
-    J = _objective(FRTrajectory.apply(ug, sol, dtt, K, C))
+    J = _objective(FRTrajectory.apply(ug, sol, dtt, K, C, None))
     J.backward()
     g = ug.grad
     rng = np.random.default_rng(50)
@@ -146,8 +146,8 @@ def test_adjoint_full_size_cylinder_80x64(gpu):
         v = v / v.norm() * u0.norm() * 1e-3
         eps = 1e-3
         with torch.no_grad():
-            Jp = _objective(FRTrajectory.apply(u0 + eps * v, sol, dtt, K, C))
-            Jm = _objective(FRTrajectory.apply(u0 - eps * v, sol, dtt, K, C))
+            Jp = _objective(FRTrajectory.apply(u0 + eps * v, sol, dtt, K, C, None))
+            Jm = _objective(FRTrajectory.apply(u0 - eps * v, sol, dtt, K, C, None))
         fd = float((Jp - Jm) / (2 * eps))
         ad = float((g * v).sum())
         worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-300))
@@ -163,7 +163,77 @@ def test_adjoint_full_size_cylinder_80x64(gpu):
         u = s.rk4_step(u, torch.tensor([1e-4], dtype=torch.float64))
     _objective(torch.stack(ps)).backward()
     ug2 = u0.clone().requires_grad_(True)
-    _objective(FRTrajectory.apply(ug2, sol, dtt, K2, C)).backward()
+    _objective(FRTrajectory.apply(ug2, sol, dtt, K2, C, None)).backward()
     err = float((ug2.grad.cpu() - uo.grad).norm() / uo.grad.norm())
     print(f"80x64 adjoint, 20 steps: gradient rel L2 vs oracle {err:.3e}")
     assert err <= 1e-9, err
+
+
+def test_trajectory_node_gradient_matches_oracle(gpu):
+    """dJ/dX (mesh nodes) of the checkpointed trajectory adjoint against reverse-mode autograd of the
+    oracle trajectory through its geometry and probe location."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+    m, p, fp, probes = _case()
+    s0 = OracleSystem(m, p, fp, equations="ns", probes=probes)
+    x = s0.solpt_coords()
+    u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (4,), 3, 2e-2))
+    u0 = u0.permute(0, 2, 1).contiguous()
+    K, C, dt = 8, 3, 2e-4
+    X = torch.tensor(m.node_xyz, dtype=torch.float64, requires_grad=True)
+    s = OracleSystem(m, p, fp, equations="ns", probes=probes, node_xyz=X)
+    u, ps = u0, []
+    for n in range(K):
+        ps.append(s.probe_pressure(u))
+        u = s.rk4_step(u, torch.tensor([dt], dtype=torch.float64))
+    _objective(torch.stack(ps)).backward()
+    gref = X.grad.detach()
+    sol = Solver(m, p, fp, equations="ns", probes=probes, max_samples=K)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    Xg = torch.tensor(m.node_xyz, dtype=torch.float64, device=gpu, requires_grad=True)
+    ug = u0.to(gpu).clone().requires_grad_(True)
+    _objective(FRTrajectory.apply(ug, sol, dtt, K, C, Xg)).backward()
+    err = float((Xg.grad.cpu() - gref).norm() / gref.norm())
+    print(f"trajectory node gradient rel L2 vs oracle {err:.3e}")
+    assert err <= 1e-8, err
+
+
+def test_adjoint_full_size_node_gradient_fd_80x64(gpu):
+    """The adjoint workload's mesh-node gradient (cylinder O-grid 80 x 64, p = 3, 200 steps,
+    checkpoints every 20) against central differences of the GPU objective on rebuilt solvers
+    along 50 seeded node directions (scaled with the local radius, so every element deforms by a
+    similar fraction)."""
+    import bench
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+    import fr_inputs as fi2
+    m, fp = bench.cylinder_workload(80, 64, p=3, q=3)
+    probes = [[0.0, 3.0]]
+    sol = Solver(m, 3, fp, equations="ns", probes=probes, max_samples=200)
+    u0 = bench.initial_state(sol, fp, m, 9).to(gpu)
+    dtt = torch.tensor([1e-4], dtype=torch.float64, device=gpu)
+    K, C = 200, 20
+    Xg = torch.tensor(m.node_xyz, dtype=torch.float64, device=gpu, requires_grad=True)
+    _objective(FRTrajectory.apply(u0.clone(), sol, dtt, K, C, Xg)).backward()
+    g = Xg.grad.cpu().numpy()
+    sol.close()
+    rng = np.random.default_rng(51)
+    r = np.linalg.norm(m.node_xyz, axis=1, keepdims=True)
+    worst = 0.0
+    for t in range(50):
+        V = rng.normal(size=m.node_xyz.shape) * r * 1e-2
+        eps = 1e-4
+        vals = []
+        for sg in (1.0, -1.0):
+            mm = fi2.MeshDesc(dim=2, q=m.q, node_xyz=m.node_xyz + sg * eps * V, elem_nodes=m.elem_nodes,
+                              face_bc=m.face_bc, periodic_vec=m.periodic_vec, mesh_elem_begin=m.mesh_elem_begin)
+            sp = Solver(mm, 3, fp, equations="ns", probes=probes, max_samples=200)
+            with torch.no_grad():
+                vals.append(float(_objective(FRTrajectory.apply(u0.clone(), sp, dtt, K, C, None))))
+            sp.close()
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        ad = float((g * V).sum())
+        worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-300))
+    print(f"80x64 node gradient: worst relative FD mismatch over 50 directions {worst:.3e}")
+    assert worst <= 1e-4, worst

@@ -93,3 +93,79 @@ def test_vjp_dot_product_against_gpu_central_differences(name, gpu):
         lhs = float((ub * v).sum())
         rhs = float((rbar * Jv).sum())
         assert abs(lhs - rhs) <= 1e-6 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+
+
+def _oracle_node_vjp(m, p, fp, eq, u0, rbar):
+    from oracle import OracleSystem
+    X = torch.tensor(m.node_xyz, dtype=torch.float64, requires_grad=True)
+    s = OracleSystem(m, p, fp, equations=eq, node_xyz=X)
+    (s.residual(u0) * rbar).sum().backward()
+    return X.grad.detach()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rhs_vjp_node_adjoint_fp64_matches_oracle(name, gpu):
+    """x_bar of fr_rhs_vjp (metric, normal and |N| adjoints mapped to the nodes) against
+    reverse-mode autograd of the oracle through its geometry; u_bar unchanged by the mode, and a
+    second call adds the same amount."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m, p, fp, eq, init, dt, probes = make_case(name)
+    s0 = OracleSystem(m, p, fp, equations=eq)
+    u0 = torch.tensor(init(s0.solpt_coords())).permute(0, 2, 1).contiguous()
+    rbar = torch.tensor(np.random.default_rng(41).normal(size=u0.shape))
+    ref = _oracle_node_vjp(m, p, fp, eq, u0, rbar)
+    uref = _oracle_vjp(s0, u0, rbar)
+    sol = Solver(m, p, fp, equations=eq)
+    ub = torch.zeros_like(u0).to(gpu)
+    xb = torch.zeros(ref.shape, dtype=torch.float64, device=gpu)
+    sol.rhs_vjp(u0.to(gpu), rbar.to(gpu), ub, x_bar=xb)
+    err = float((xb.cpu() - ref).norm() / ref.norm())
+    eu = rel_l2(ub, uref)
+    print(f"{name}: node adjoint rel L2 {err:.3e} (u_bar {eu:.3e})")
+    assert err <= 1e-10, err
+    assert eu <= 1e-10, eu
+    sol.rhs_vjp(u0.to(gpu), rbar.to(gpu), ub, x_bar=xb)
+    assert float((xb.cpu() - 2 * ref).norm() / ref.norm()) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["ns_ogrid", "ns_box3d_p2"])
+def test_rhs_vjp_node_adjoint_fp32(name, gpu):
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m, p, fp, eq, init, dt, probes = make_case(name)
+    s0 = OracleSystem(m, p, fp, equations=eq)
+    u0 = torch.tensor(init(s0.solpt_coords())).permute(0, 2, 1).contiguous()
+    rbar = torch.tensor(np.random.default_rng(42).normal(size=u0.shape))
+    ref = _oracle_node_vjp(m, p, fp, eq, u0, rbar)
+    sol = Solver(m, p, fp, equations=eq, precision="fp32")
+    ub = torch.zeros(u0.shape, dtype=torch.float32, device=gpu)
+    xb = torch.zeros(ref.shape, dtype=torch.float64, device=gpu)
+    sol.rhs_vjp(u0.float().to(gpu), rbar.float().to(gpu), ub, x_bar=xb)
+    err = float((xb.cpu() - ref).norm() / ref.norm())
+    print(f"{name}: node adjoint fp32 rel L2 {err:.3e}")
+    assert err <= 5e-3, err
+
+
+@pytest.mark.parametrize("name", ["ns_ogrid", "ns_cgrid_p4", "ns_cavity_batch"])
+def test_probe_vjp_node_adjoint_matches_oracle(name, gpu):
+    """x_bar of fr_probe_vjp: the probe is fixed in physical space, so its reference coordinates
+    follow the nodes of its element (oracle: one differentiable Newton correction)."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m, p, fp, eq, init, dt, probes = make_case(name)
+    pm = list(range(len(probes))) if m.n_mesh > 1 else None
+    s0 = OracleSystem(m, p, fp, equations=eq, probes=probes, probe_mesh=pm)
+    u0 = torch.tensor(init(s0.solpt_coords())).permute(0, 2, 1).contiguous()
+    pbar = torch.tensor(np.random.default_rng(43).normal(size=len(probes)))
+    X = torch.tensor(m.node_xyz, dtype=torch.float64, requires_grad=True)
+    s = OracleSystem(m, p, fp, equations=eq, probes=probes, probe_mesh=pm, node_xyz=X)
+    (s.probe_pressure(u0) * pbar).sum().backward()
+    ref = X.grad.detach()
+    sol = Solver(m, p, fp, equations=eq, probes=probes, probe_mesh=pm, max_samples=4)
+    ub = torch.zeros_like(u0).to(gpu)
+    xb = torch.zeros(ref.shape, dtype=torch.float64, device=gpu)
+    sol.probe_vjp(u0.to(gpu), pbar.to(gpu), ub, x_bar=xb)
+    err = float((xb.cpu() - ref).norm() / ref.norm())
+    print(f"{name}: probe node adjoint rel L2 {err:.3e}")
+    assert err <= 1e-10, err

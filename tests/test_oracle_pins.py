@@ -362,3 +362,125 @@ def test_oracle_gradient_matches_central_differences(eq):
         fd = ((s.residual(u0 + eps * v) - s.residual(u0 - eps * v)) * r).sum() / (2 * eps)
         ad = (u.grad * v).sum()
         assert abs(float(fd - ad)) <= 1e-6 * abs(float(ad)), (float(fd), float(ad))
+
+
+# ----------------------------------------------------------------------------- mesh-node gradient
+def _node_case(kind):
+    if kind == "euler_periodic":
+        m = fi.periodic_box(2, 3, q=2, curv=0.2, seed=3)
+        fp = fi.freestream_params(2, 0.3, None, aoa_deg=20.0)
+        return m, 2, fp, "euler"
+    if kind == "ns_ogrid":
+        m = fi.o_grid(8, 3, q=2, r1=4.0, stretch=1.3, seed=4)
+        fp = fi.freestream_params(2, 0.3, 100.0, aoa_deg=10.0)
+        return m, 2, fp, "ns"
+    m = fi.periodic_box(3, 2, q=2, curv=0.15, seed=5, bc="farfield")
+    fp = fi.freestream_params(3, 0.3, 100.0, aoa_deg=15.0)
+    return m, 2, fp, "ns"
+
+
+def _node_grad(m, p, fp, eq, u0, r, probes=None):
+    X = torch.tensor(m.node_xyz, dtype=torch.float64, requires_grad=True)
+    s = OracleSystem(m, p, fp, equations=eq, node_xyz=X, probes=probes)
+    val = (s.residual(u0) * r).sum()
+    val.backward()
+    return s, X.grad.clone(), float(val.detach())
+
+
+def _noisy_state(s, fp, seed):
+    u0 = state_at(s, fi.freestream_state, fp=fp)
+    rng = np.random.default_rng(seed)
+    return u0 * (1.0 + torch.tensor(rng.uniform(-0.02, 0.02, u0.shape))), rng
+
+
+@pytest.mark.parametrize("kind", ["euler_periodic", "ns_ogrid", "ns_box3d_farfield"])
+def test_node_gradient_translation_and_scaling_invariants(kind):
+    """The residual does not depend on where the mesh sits (sum of node adjoints = 0), and it is
+    homogeneous in the node coordinates: the inviscid and penalty parts scale as 1/lambda and the
+    mu-proportional viscous part as 1/lambda^2 under X -> lambda X, so by Euler's theorem
+    sum_n X_n . X_bar_n = -r.R(mu = 0) - 2 r.(R(mu) - R(mu = 0))."""
+    m, p, fp, eq = _node_case(kind)
+    s0 = OracleSystem(m, p, fp, equations=eq)
+    u0, rng = _noisy_state(s0, fp, 12)
+    r = torch.tensor(rng.normal(size=u0.shape))
+    s, g, _ = _node_grad(m, p, fp, eq, u0, r)
+    scale = float(g.abs().max())
+    assert float(g.sum(dim=0).abs().max()) <= 1e-11 * scale * g.shape[0] ** 0.5
+    lhs = float((torch.tensor(m.node_xyz) * g).sum())
+    R = s0.residual(u0)
+    if eq == "euler":
+        rhs = -float((r * R).sum())
+    else:
+        fp0 = fi.freestream_params(fp.dim, 0.3, None, aoa_deg=0.0)
+        fp0.rho_inf, fp0.vel_inf, fp0.p_inf = fp.rho_inf, fp.vel_inf, fp.p_inf
+        fp0.mu = np.zeros_like(np.asarray(fp.mu, float))
+        R0 = OracleSystem(m, p, fp0, equations="ns").residual(u0)
+        rhs = -float((r * R0).sum()) - 2.0 * float((r * (R - R0)).sum())
+    assert abs(lhs - rhs) <= 1e-9 * max(abs(rhs), float((r * R).abs().sum())), (lhs, rhs)
+
+
+def test_node_gradient_zero_at_free_stream_on_curved_farfield_mesh():
+    """A uniform state is preserved on every conforming curved mesh of degree q <= p with far-field
+    boundaries, R(X) = 0 for all such X, so its node gradient vanishes.  (On a periodic box a
+    single boundary node moved without its periodic image breaks conformity, so that mesh does
+    not qualify.)"""
+    m = fi.o_grid(8, 3, q=2, r1=4.0, stretch=1.3, seed=4, wall="farfield")
+    fp = fi.freestream_params(2, 0.3, 100.0, aoa_deg=10.0)
+    p = 2
+    s0 = OracleSystem(m, p, fp, equations="ns")
+    u0 = state_at(s0, fi.freestream_state, fp=fp)
+    r = torch.tensor(np.random.default_rng(3).normal(size=u0.shape))
+    _, g, _ = _node_grad(m, p, fp, "ns", u0, r)
+    assert float(g.abs().max()) <= 1e-10 * float(u0.abs().max())
+
+
+@pytest.mark.parametrize("kind", ["euler_periodic", "ns_ogrid", "ns_box3d_farfield"])
+def test_node_gradient_matches_central_differences(kind):
+    """<X_bar, V> against central differences of r . R(X + e V) along seeded node directions
+    (metrics recomputed from the perturbed nodes, face pairing kept)."""
+    m, p, fp, eq = _node_case(kind)
+    s0 = OracleSystem(m, p, fp, equations=eq)
+    u0, rng = _noisy_state(s0, fp, 13)
+    r = torch.tensor(rng.normal(size=u0.shape))
+    _, g, _ = _node_grad(m, p, fp, eq, u0, r)
+    h = float(np.ptp(m.node_xyz, axis=0).max()) / 50.0
+    for _ in range(2):
+        V = rng.normal(size=m.node_xyz.shape) * h
+        eps = 1e-6
+        vals = []
+        for sg in (1.0, -1.0):
+            s0.set_nodes(torch.tensor(m.node_xyz + sg * eps * V))
+            vals.append(float((s0.residual(u0) * r).sum()))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        ad = float((g * torch.tensor(V)).sum())
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-8), (fd, ad)
+
+
+def test_probe_node_gradient_matches_relocated_probe():
+    """The probe pressure's node gradient (one differentiable Newton correction) against central
+    differences in which the probe is located afresh (Newton from scratch) on each perturbed mesh."""
+    m = fi.o_grid(8, 3, q=2, r1=4.0, stretch=1.3, seed=4)
+    fp = fi.freestream_params(2, 0.3, 100.0, aoa_deg=10.0)
+    probe = np.array([[0.3, 1.1]])
+    s0 = OracleSystem(m, 2, fp, equations="ns", probes=probe)
+    x = s0.solpt_coords()
+    rng = np.random.default_rng(21)
+    u0 = state_at(s0, fi.freestream_state, fp=fp)
+    u0 = u0 + 0.05 * torch.tensor(np.sin(3 * x[..., 0] + 2 * x[..., 1]))[:, None, :] * u0.abs().mean(dim=(0, 2))[None, :, None]
+    X = torch.tensor(m.node_xyz, dtype=torch.float64, requires_grad=True)
+    s = OracleSystem(m, 2, fp, equations="ns", node_xyz=X, probes=probe)
+    s.probe_pressure(u0).sum().backward()
+    g = X.grad
+    assert float(g.abs().max()) > 0
+    h = 0.02
+    for _ in range(3):
+        V = rng.normal(size=m.node_xyz.shape) * h
+        eps = 1e-6
+        vals = []
+        for sg in (1.0, -1.0):
+            mm = fi.MeshDesc(dim=2, q=m.q, node_xyz=m.node_xyz + sg * eps * V, elem_nodes=m.elem_nodes,
+                             face_bc=m.face_bc, periodic_vec=m.periodic_vec, mesh_elem_begin=m.mesh_elem_begin)
+            vals.append(float(OracleSystem(mm, 2, fp, equations="ns", probes=probe).probe_pressure(u0).sum()))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        ad = float((g * torch.tensor(V)).sum())
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-6), (fd, ad)
