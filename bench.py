@@ -196,7 +196,8 @@ def cpu_baseline(budget_s: float = 20.0):
 
 
 # ------------------------------------------------------------------------------------ main
-def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None, seed=5, profile=False):
+def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None, seed=5, profile=False,
+                autotune=True):
     import torch
     from paper_2312_14167_amd import Solver
     t0 = time.perf_counter()
@@ -206,11 +207,14 @@ def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None
     u = initial_state(sol, fp, mesh, seed).to(device="cuda", dtype=sol.dtype)
     # stable explicit dt: the trailing-edge cells of the C-grid are ~7e-4 chords long
     dt = torch.full((mesh.n_mesh,), 5e-7 if mesh.dim == 3 else 1e-5, dtype=torch.float64, device="cuda")
+    tiles = sol.autotune(u, dt, reps=3) if autotune else None
+    if tiles:
+        log("  autotuned tiles: " + ", ".join(f"{k} E={v['elements_per_workgroup']}" for k, v in tiles.items()))
     t = time_steps(sol, u, dt, steps, warmup)
     info = solver_info(sol)
     dof = info[0] * info[1] * info[2]
     out = {"sec": t, "gdofs": dof * 4 * steps / t / 1e9, "ms_per_step": 1e3 * t / steps, "info": info,
-           "finite": bool(torch.isfinite(u).all())}
+           "finite": bool(torch.isfinite(u).all()), "tiles": tiles}
     if profile:
         out["kernels"] = kernel_profile(sol, u, dt, max(2, min(steps, 10)))
     st = sol.probe_oaspl(p_ref=2e-5 * fp.p_inf[0] / 101325.0)
@@ -325,6 +329,7 @@ def sequential_cavities(bm, bfp, counts, steps, precision="fp32"):
                      max_samples=steps + 4, forces=True)
         u = initial_state(sol, fpk, mk, 5).to(device="cuda", dtype=sol.dtype)
         dt = torch.full((1,), 1e-5, dtype=torch.float64, device="cuda")
+        sol.autotune(u, dt, reps=2)
         total += time_steps(sol, u, dt, steps, 2)
         info = solver_info(sol)
         dof += info[0] * info[1] * info[2]
@@ -421,13 +426,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": avg_ms},
         "kernels": per_kernel,
+        "tiles": r64.get("tiles"),
     }
     if not args.no_variants:
         log("FP32 (FP64 accumulators)")
         r32 = run_variant(mesh, fp, "fp32", K, W, probes=probe)
         log(f"  {r32['gdofs']:.2f} GDoF-stage/s")
         result["variants"] = {"fp32": {"value": r32["gdofs"], "ms_per_step": r32["ms_per_step"],
-                                       "speedup_vs_fp64": r32["gdofs"] / r64["gdofs"]}}
+                                       "speedup_vs_fp64": r32["gdofs"] / r64["gdofs"], "tiles": r32.get("tiles")}}
         del mesh
         log("batched poll: 16 cavities, FP32, one launch per kernel over all meshes")
         bm, bfp, bprobes, counts = cavity_batch()
@@ -436,10 +442,16 @@ def main():
         log("16 sequential FP32 solves of the same meshes")
         rs = sequential_cavities(bm, bfp, counts, K)
         log(f"  {rs['gdofs']:.2f} GDoF-stage/s")
+        log("16 sequential FP64 solves of the same meshes")
+        rs64 = sequential_cavities(bm, bfp, counts, K, precision="fp64")
+        log(f"  {rs64['gdofs']:.2f} GDoF-stage/s")
         result["variants"]["batched_16_cavities_fp32"] = {
             "value": rb["gdofs"], "ms_per_step": rb["ms_per_step"], "quads": counts, "total_quads": bm.n_elem,
+            "tiles": rb.get("tiles"),
             "sequential_fp32_value": rs["gdofs"], "sequential_fp32_ms_per_step": rs["ms_per_step"],
-            "speedup_vs_sequential_fp32": rs["ms_per_step"] / rb["ms_per_step"]}
+            "speedup_vs_sequential_fp32": rs["ms_per_step"] / rb["ms_per_step"],
+            "sequential_fp64_value": rs64["gdofs"], "sequential_fp64_ms_per_step": rs64["ms_per_step"],
+            "speedup_vs_sequential_fp64": rs64["ms_per_step"] / rb["ms_per_step"]}
         log("adjoint / forward time (cylinder 80 x 64, p=3, 200 steps)")
         ra = adjoint_ratio()
         log(f"  forward {ra['forward_s']:.3f}s backward {ra['backward_s']:.3f}s ratio {ra['adjoint_over_forward']:.2f}; "

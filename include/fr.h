@@ -197,6 +197,17 @@ fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_s
 fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, void *u_bar,
                          double *x_bar, void *stream);
 
+/* Tile-shape autotuner.  For each volume kernel of the solver's equations (Navier-Stokes: the
+ * volume kernel and the lifting + RK kernel; Euler: the volume + RK kernel) it times the candidate
+ * tile sizes (elements per workgroup: the default, its half and its quarter) with `reps` RK4 steps
+ * each on a device copy of u (u is not modified), keeps the fastest, and drops the captured step
+ * graphs so that the next fr_rk_step re-captures them.  Synchronises `stream`; allocates and frees
+ * one state-sized scratch copy.  tiles[3] (host, nullable): chosen elements per workgroup for
+ * kinds {NS volume, NS lifting + RK, Euler volume + RK}; ms[3][3] (host, nullable): measured ms
+ * per RK4 step of each candidate (0 where not tried).  FR_ERR_ARG for reps < 1. */
+fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *tiles, double *ms,
+                      void *stream);
+
 /* Release everything the handle owns (NULL is a no-op). */
 void fr_destroy(fr_solver *s);
 

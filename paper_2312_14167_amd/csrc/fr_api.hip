@@ -548,6 +548,75 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
   return FR_OK;
 }
 
+fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *tiles, double *ms,
+                      void *stream) {
+  if (!s || !u || !dt) return fail(FR_ERR_ARG, "NULL argument");
+  if (reps < 1) return fail(FR_ERR_ARG, "reps must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  void *tmp = nullptr;
+  try {
+    Dispatch d = dispatch_of(s);
+    const size_t nb = (size_t)s->Ne * s->NV * s->Ns * s->tsize;
+    HIP_OK(hipMalloc(&tmp, nb));
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    const int kinds_ns[2] = {0, 1}, kinds_eu[1] = {2};
+    const int *kinds = s->equations == FR_NAVIER_STOKES ? kinds_ns : kinds_eu;
+    const int nk = s->equations == FR_NAVIER_STOKES ? 2 : 1;
+    double times[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int c = 0; c < 3; ++c) times[k][c] = 0.0;
+    const int prof = s->profiling;
+    s->profiling = 0;
+    for (int q = 0; q < nk; ++q) {
+      const int kind = kinds[q];
+      int E[3];
+      d.tile_cands(kind, E);
+      double best = 1e300;
+      int best_c = 0;
+      for (int c = 0; c < 3; ++c) {
+        if (c > 0 && (E[c] == E[c - 1] || (c == 2 && E[2] == E[0]))) continue;
+        s->tune[kind] = c;
+        HIP_OK(hipMemcpyAsync(tmp, u, nb, hipMemcpyDeviceToDevice, st));
+        d.step(s, tmp, dt, false, true, st);  // warm-up (first launch of this variant)
+        HIP_OK(hipEventRecord(a, st));
+        for (int r = 0; r < reps; ++r) d.step(s, tmp, dt, false, r == 0, st);
+        HIP_OK(hipEventRecord(b, st));
+        HIP_OK(hipEventSynchronize(b));
+        float t = 0.0f;
+        HIP_OK(hipEventElapsedTime(&t, a, b));
+        times[kind][c] = (double)t / reps;
+        if (times[kind][c] < best) {
+          best = times[kind][c];
+          best_c = c;
+        }
+      }
+      s->tune[kind] = best_c;
+    }
+    s->profiling = prof;
+    free_graphs(s);  // captured steps must use the chosen tiles
+    if (tiles)
+      for (int k = 0; k < 3; ++k) {
+        int E[3];
+        d.tile_cands(k, E);
+        tiles[k] = E[s->tune[k]];
+      }
+    if (ms)
+      for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 3; ++c) ms[k * 3 + c] = times[k][c];
+    HIP_OK(hipEventDestroy(a));
+    HIP_OK(hipEventDestroy(b));
+    HIP_OK(hipFree(tmp));
+  } catch (const FrError &e) {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (tmp) (void)hipFree(tmp);
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
 fr_status fr_solver_info(const fr_solver *s, int64_t info[8]) {
   if (!s || !info) return fail(FR_ERR_ARG, "NULL argument");
   info[0] = s->Ne;

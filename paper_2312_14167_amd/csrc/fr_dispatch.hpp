@@ -18,6 +18,9 @@ struct Dispatch {
   void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
                          const double *, hipStream_t);
   void (*zero)(const fr_solver *, void *, hipStream_t);
+  // elements per workgroup of the autotuner candidates of volume kernel `kind`
+  // (0: NS volume, 1: NS lifting + RK, 2: Euler volume + RK)
+  void (*tile_cands)(int kind, int *E);
 };
 bool get_dispatch(int dim, int p, int precision, Dispatch &out);
 void launch_fill(double *p, int64_t n, double v, hipStream_t st);

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fr_device.hpp"
 #include "fr_dispatch.hpp"
@@ -122,34 +123,41 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
   }
 }
 
-// tile sizes of the LDS-staged volume kernels
-template <int D, int P, typename T>
+// tile sizes (elements per workgroup E) of the LDS-staged volume kernels: EE = 0 gives the
+// default; the autotuner also tries the default's halves and quarters (TileCands)
+template <int D, int P, typename T, int EE = 0>
 struct GradTile {
   using S = Shape<D, P>;
   // per element: the state [NV][Ns], kept to the flux-point viscous phase, then one region that
   // holds u^ - u_f [NV][Nf], the physical gradient [D][NV][Ns] and the transformed flux
-  // [D][NV][Ns] in turn.  E is chosen so that four workgroups fit in 160 KB of LDS.
+  // [D][NV][Ns] in turn.  The default E fits four workgroups in 160 KB of LDS.
   static constexpr int LU = S::NV * S::Ns;
   static constexpr int LG = cmax(S::NV * S::Nf, D * S::NV * S::Ns);
   static constexpr int LE = LU + LG;
-  static constexpr int E = cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
+  static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
 };
 
-template <int D, int P, typename T>
+template <int D, int P, typename T, int EE = 0>
 struct DivTile {
   using S = Shape<D, P>;
   static constexpr int LE = S::NV * cmax(S::Nf, S::Ns);
-  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int E = EE > 0 ? EE : tile_elems<S::Ns>(LE, sizeof(T));
   static constexpr int BS = round64(E * S::Ns);
 };
 
-template <int D, int P, typename T>
+template <int D, int P, typename T, int EE = 0>
 struct EulerTile {
   using S = Shape<D, P>;
   static constexpr int LE = D * S::NV * S::Ns + S::NV * S::Nf;
-  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int E = EE > 0 ? EE : tile_elems<S::Ns>(LE, sizeof(T));
   static constexpr int BS = round64(E * S::Ns);
+};
+
+// autotuner candidates: the default E, its half and its quarter
+template <int E0>
+struct TileCands {
+  static constexpr int c0 = E0, c1 = cmax(1, E0 / 2), c2 = cmax(1, E0 / 4);
 };
 
 // NS volume kernel.  Per element tile:
@@ -160,14 +168,14 @@ struct EulerTile {
 //   state); F~_k = S_k . (F_inv - F_vis) at solution points;
 //   vol = sum_k D~_k F~_k with D~ = D - (interior part of the correction), i.e.
 //   vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}).
-template <int D, int P, typename T>
-__global__ __launch_bounds__((GradTile<D, P, T>::BS), 4) void k_ns_grad(
+template <int D, int P, typename T, int EE>
+__global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
     const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, T *__restrict__ fvn,
     T *__restrict__ fhat, T *__restrict__ vol, int64_t Ne) {
   using S = Shape<D, P>;
-  using TL = GradTile<D, P, T>;
+  using TL = GradTile<D, P, T, EE>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM, NFACE = 2 * D;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
@@ -489,13 +497,13 @@ __device__ __forceinline__ void tile_interp(const T *lw, int ne, const OpsDev<T,
 }
 
 // NS: R = -(1/J)(vol + Lift F^), RK update, u_f of the new stage state
-template <int D, int P, typename T>
-__global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_div_rk(const T *__restrict__ vol, const T *__restrict__ fhat,
+template <int D, int P, typename T, int EE>
+__global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *__restrict__ vol, const T *__restrict__ fhat,
                                                                 const T *__restrict__ metric,
                                                                 const int32_t *__restrict__ elem_mesh,
                                                                 OpsDev<T, P> ops_arg, RKArgs<T> rk, int64_t Ne) {
   using S = Shape<D, P>;
-  using TL = DivTile<D, P, T>;
+  using TL = DivTile<D, P, T, EE>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
@@ -535,13 +543,13 @@ __global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_div_rk(const T *__re
 
 // Euler: F~ at solution points, volume divergence with interior correction, lifting of the
 // common flux, RK update and u_f of the new stage state, in one kernel
-template <int D, int P, typename T>
-__global__ __launch_bounds__((EulerTile<D, P, T>::BS)) void k_euler_vol_rk(
+template <int D, int P, typename T, int EE>
+__global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
     const T *u,  // may alias rk.ustage: every thread reads its own point before writing it
     const T *__restrict__ fhat, const T *__restrict__ metric,
     const int32_t *__restrict__ elem_mesh, OpsDev<T, P> ops_arg, PhysDev<T> ph, RKArgs<T> rk, int64_t Ne) {
   using S = Shape<D, P>;
-  using TL = EulerTile<D, P, T>;
+  using TL = EulerTile<D, P, T, EE>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
@@ -816,6 +824,17 @@ struct ProfScope {
   }
 };
 
+// launch the candidate tile chosen by the autotuner (index 0: default, 1: half, 2: quarter)
+template <class C, class F>
+static inline void pick_tile(int which, F &&go) {
+  if (which == 1)
+    go(std::integral_constant<int, C::c1>{});
+  else if (which == 2)
+    go(std::integral_constant<int, C::c2>{});
+  else
+    go(std::integral_constant<int, C::c0>{});
+}
+
 template <int D, int P, typename T>
 struct Engine {
   using S = Shape<D, P>;
@@ -852,12 +871,17 @@ struct Engine {
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
     if (s->equations == 1) {
       T *fvn = (T *)s->fvn, *vol = (T *)s->vol;
-      using TL = GradTile<D, P, T>;
       {
         ProfScope ps(s, 2, st);
-        k_ns_grad<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, uf, s->nbr, (const T *)s->fnrm,
-                                                                   (const T *)s->bnd_nrm, s->n_wall, metric,
-                                                                   s->elem_mesh, fl, o, ph, fvn, fhat, vol, s->Ne);
+        auto go = [&](auto tag) {
+          constexpr int EE = decltype(tag)::value;
+          using TL = GradTile<D, P, T, EE>;
+          k_ns_grad<D, P, T, EE><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(
+              u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o,
+              ph, fvn, fhat, vol, s->Ne);
+        };
+        using C = TileCands<GradTile<D, P, T>::E>;
+        pick_tile<C>(s->tune[0], go);
       }
       if (force_sample && s->forces && s->n_wall > 0) {
         ProfScope ps(s, 7, st);
@@ -870,9 +894,14 @@ struct Engine {
             uf, fvn, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
             s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
       }
-      using TD = DivTile<D, P, T>;
       ProfScope ps(s, 4, st);
-      k_div_rk<D, P, T><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk, s->Ne);
+      auto go = [&](auto tag) {
+        constexpr int EE = decltype(tag)::value;
+        using TD = DivTile<D, P, T, EE>;
+        k_div_rk<D, P, T, EE><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk, s->Ne);
+      };
+      using C = TileCands<DivTile<D, P, T>::E>;
+      pick_tile<C>(s->tune[1], go);
     } else {
       {
         ProfScope ps(s, 3, st);
@@ -880,10 +909,15 @@ struct Engine {
             uf, nullptr, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
             s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
       }
-      using TE = EulerTile<D, P, T>;
       ProfScope ps(s, 5, st);
-      k_euler_vol_rk<D, P, T><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh, o, ph, rk,
-                                                                      s->Ne);
+      auto go = [&](auto tag) {
+        constexpr int EE = decltype(tag)::value;
+        using TE = EulerTile<D, P, T, EE>;
+        k_euler_vol_rk<D, P, T, EE><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh, o, ph,
+                                                                            rk, s->Ne);
+      };
+      using C = TileCands<EulerTile<D, P, T>::E>;
+      pick_tile<C>(s->tune[2], go);
     }
   }
 
@@ -963,6 +997,18 @@ Dispatch make_dispatch() {
     const int64_t per = (int64_t)S::NV * S::Ns, n = s->Ne * per;
     k_rk_adj_combine<T><<<nblk(n, 256), 256, 0, st>>>((T *)a, (T *)z, (T *)kb, (T *)ub, (T *)zz, ca, cz, dt,
                                                        s->elem_mesh, per, n);
+  };
+  d.tile_cands = [](int kind, int *E) {
+    if (kind == 0) {
+      using C = TileCands<GradTile<D, P, T>::E>;
+      E[0] = C::c0; E[1] = C::c1; E[2] = C::c2;
+    } else if (kind == 1) {
+      using C = TileCands<DivTile<D, P, T>::E>;
+      E[0] = C::c0; E[1] = C::c1; E[2] = C::c2;
+    } else {
+      using C = TileCands<EulerTile<D, P, T>::E>;
+      E[0] = C::c0; E[1] = C::c1; E[2] = C::c2;
+    }
   };
   d.zero = [](const fr_solver *s, void *p, hipStream_t st) {
     using S = Shape<D, P>;

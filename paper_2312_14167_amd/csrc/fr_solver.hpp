@@ -112,6 +112,8 @@ struct fr_solver {
   void *graph_u[4] = {nullptr, nullptr, nullptr, nullptr};
   const double *graph_dt[4] = {nullptr, nullptr, nullptr, nullptr};
   int use_graphs = 1;
+  // autotuner choice per volume kernel (0: default tile, 1: half, 2: quarter)
+  int tune[3] = {0, 0, 0};
 
   // per-kernel event timing (FR_K_* ids)
   int profiling = 0;

@@ -137,6 +137,20 @@ class Solver:
         check(lib().fr_probe_series(self._h, out.ctypes.data_as(C.c_void_p), int(cap), C.byref(n), _stream(stream)))
         return out[:self.n_probe, :min(int(n.value), cap)]
 
+    def autotune(self, u: torch.Tensor, dt: torch.Tensor, reps: int = 3, stream=None) -> dict:
+        """Time the candidate tile sizes of the volume kernels on this mesh (u is not modified) and
+        keep the fastest; returns the chosen elements per workgroup and the measured ms per step."""
+        self._check_state(u, "u")
+        self._check_dt(dt)
+        tiles = np.zeros(3, dtype=np.int32)
+        ms = np.zeros(9)
+        check(lib().fr_autotune(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), int(reps),
+                                tiles.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), _stream(stream)))
+        names = ["ns_volume", "ns_lift_rk", "euler_volume_rk"]
+        kinds = [0, 1] if self.equations == "ns" else [2]
+        return {names[k]: {"elements_per_workgroup": int(tiles[k]),
+                           "ms_per_step": [float(x) for x in ms[3 * k:3 * k + 3]]} for k in kinds}
+
     def info(self) -> dict:
         a = np.zeros(8, dtype=np.int64)
         check(lib().fr_solver_info(self._h, a.ctypes.data_as(C.c_void_p)))

@@ -150,3 +150,21 @@ def test_ragged_tiles_and_single_element(gpu):
         sol = Solver(m, p, fp, equations="ns")
         R = sol.rhs(u0.to(gpu))
         assert rel_l2(R, s.residual(u0)) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["ns_ogrid", "euler_vortex", "ns_cgrid_p4"])
+def test_autotuned_tiles_give_the_same_step(name, gpu):
+    """Every candidate tile size of the autotuner computes the same RK4 step (the tile only
+    regroups elements into workgroups), and the tuner leaves u untouched and re-captures graphs."""
+    s, sol, u0, dt = _solver(name)
+    dtt = torch.tensor(dt, dtype=torch.float64, device=gpu)
+    ug = u0.to(gpu)
+    ref = ug.clone()
+    sol.rk_step(ref, dtt, 2)
+    keep = ug.clone()
+    choice = sol.autotune(ug, dtt, reps=1)
+    assert torch.equal(ug, keep)
+    print(f"{name}: autotuned {choice}")
+    u = ug.clone()
+    sol.rk_step(u, dtt, 2)
+    assert rel_l2(u, ref) <= 1e-14
