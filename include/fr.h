@@ -182,20 +182,22 @@ fr_status fr_profile_read(fr_solver *s, double *total_ms, int64_t *launches, voi
 fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u_bar, double *x_bar, void *stream);
 
 /* n_steps classical RK4 steps of u (device state, in place, no sampling) that also store, for
- * every step n, the base state u_n in states[n][n_elem][nv][Ns] (skipped when states is NULL) and
+ * every step n, the base state u_n in states[n][n_elem][nv][Ns] (skipped when states is NULL),
  * the three intermediate stage states y2 = u_n + dt/2 k1, y3 = u_n + dt/2 k2, y4 = u_n + dt k3 in
- * stages[n][3][n_elem][nv][Ns] (device, state dtype), for use by fr_rk_step_vjp.  states must not
- * alias u.  FR_ERR_ARG for n_steps < 1 or NULL u / dt / stages. */
+ * stages[n][3][n_elem][nv][Ns], and (skipped when residuals is NULL) the four stage residuals
+ * k1..k4 in residuals[n][4][n_elem][nv][Ns] (device, state dtype), for use by fr_rk_step_vjp.
+ * states and residuals must not alias u.  FR_ERR_ARG for n_steps < 1 or NULL u / dt / stages. */
 fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_steps, void *states, void *stages,
-                            void *stream);
+                            void *residuals, void *stream);
 
 /* Adjoint of one RK4 step u_n -> u_{n+1}: on entry u_bar holds dJ/du_{n+1}, on return dJ/du_n
  * (= (du_{n+1}/du_n)^T u_bar).  stages: the step's stage states from fr_rk_step_stages, or NULL
  * to recompute them from u_n.  dt: device FP64 [n_mesh].  x_bar: NULL, or device FP64
  * [n_node][dim] += (du_{n+1}/dX)^T u_bar (entry value of u_bar) through the residuals of the
- * four stages.  Allocates its work area on first use. */
-fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, void *u_bar,
-                         double *x_bar, void *stream);
+ * four stages; residuals: the step's stage residuals from fr_rk_step_stages (used with x_bar),
+ * or NULL to evaluate them.  Allocates its work area on first use. */
+fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, const void *residuals,
+                         void *u_bar, double *x_bar, void *stream);
 
 /* Tile-shape autotuner.  For each volume kernel of the solver's equations (Navier-Stokes: the
  * volume kernel and the lifting + RK kernel; Euler: the volume + RK kernel) it times the candidate

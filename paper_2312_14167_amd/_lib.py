@@ -64,8 +64,8 @@ def lib() -> C.CDLL:
     L.fr_profile_enable.argtypes = [vp, i32]
     L.fr_profile_read.argtypes = [vp, vp, vp, vp]
     L.fr_probe_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
-    L.fr_rk_step_stages.argtypes = [vp, vp, vp, i32, vp, vp, vp]
-    L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.fr_rk_step_stages.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.fr_autotune.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.fr_destroy.argtypes = [vp]
     L.fr_destroy.restype = None

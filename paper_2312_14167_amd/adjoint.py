@@ -50,12 +50,15 @@ class FRTrajectory(torch.autograd.Function):
             xb = torch.zeros((sol.n_node, sol.dim), dtype=torch.float64, device=dev)
         states = torch.empty((C,) + sol.shape, dtype=sol.dtype, device=dev)      # reused by every segment
         stages = torch.empty((C, 3) + sol.shape, dtype=sol.dtype, device=dev)
+        res = torch.empty((C, 4) + sol.shape, dtype=sol.dtype, device=dev) if xb is not None else None
         for s0 in reversed(range(0, K, C)):
             s1 = min(s0 + C, K)
             u = ctx.ckpts[s0].clone()
-            sol.rk_step_stages(u, dt, stages[:s1 - s0], states=states[:s1 - s0])
+            sol.rk_step_stages(u, dt, stages[:s1 - s0], states=states[:s1 - s0],
+                               residuals=None if res is None else res[:s1 - s0])
             for n in reversed(range(s0, s1)):
-                sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0], x_bar=xb)
+                sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0], x_bar=xb,
+                                residuals=None if res is None else res[n - s0])
                 sol.probe_vjp(states[n - s0], p_bar[n], ub, x_bar=xb)
         return ub, None, None, None, None, xb
 

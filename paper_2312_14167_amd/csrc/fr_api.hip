@@ -456,8 +456,8 @@ fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar
     if (x_bar) {
       ensure_geo(s);
       zero_geo(s, st);
-      dispatch_of(s).rhs_two_sided(s, u, s->geo_R, st);  // forward residual and common flux at u
-      geo = GeoVjpArgs{s->geo_Gm, s->geo_Gn, s->geo_R, s->fhat};
+      dispatch_of(s).rhs(s, u, s->geo_R, st);  // forward residual at u (adjoint of 1/J)
+      geo = GeoVjpArgs{s->geo_Gm, s->geo_Gn, s->geo_R};
     }
     if (!launch_vjp(s, u, r_bar, u_bar, s->vjp_work, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, geo, st))
       throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
@@ -482,13 +482,13 @@ fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u
 }
 
 fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_steps, void *states, void *stages,
-                            void *stream) {
+                            void *residuals, void *stream) {
   if (!s || !u || !dt || !stages) return fail(FR_ERR_ARG, "NULL argument");
   if (n_steps < 1) return fail(FR_ERR_ARG, "n_steps must be >= 1");
-  if (states == u) return fail(FR_ERR_ARG, "states must not alias u");
+  if (states == u || residuals == u) return fail(FR_ERR_ARG, "states / residuals must not alias u");
   try {
     Dispatch d = dispatch_of(s);
-    d.step_record(s, u, dt, n_steps, states, stages, (hipStream_t)stream);
+    d.step_record(s, u, dt, n_steps, states, stages, residuals, (hipStream_t)stream);
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
@@ -496,25 +496,27 @@ fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_s
   return FR_OK;
 }
 
-fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, void *u_bar,
-                         double *x_bar, void *stream) {
+fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, const void *residuals,
+                         void *u_bar, double *x_bar, void *stream) {
   if (!s || !u_n || !dt || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
   if (u_bar == u_n) return fail(FR_ERR_ARG, "u_bar must not alias u_n");
   hipStream_t st = (hipStream_t)stream;
   try {
     Dispatch d = dispatch_of(s);
     const size_t nb = (size_t)s->Ne * s->NV * s->Ns * s->tsize;
-    if (!s->adj_work) s->adj_work = (char *)dalloc(s, nb * 7);  // A, KB, Z, temp state, 3 stages
+    if (!s->adj_work) s->adj_work = (char *)dalloc(s, nb * 11);  // A, KB, Z, temp state, 3 stages, 4 residuals
     if (!s->vjp_work) {
       s->vjp_bytes = vjp_work_elems(s) * s->tsize;
       s->vjp_work = dalloc(s, s->vjp_bytes);
     }
-    char *A = s->adj_work, *KB = A + nb, *Z = KB + nb, *TMP = Z + nb, *STG = TMP + nb;
+    char *A = s->adj_work, *KB = A + nb, *Z = KB + nb, *TMP = Z + nb, *STG = TMP + nb, *RES = STG + 3 * nb;
     const char *Y = (const char *)stages;
-    if (!Y) {  // recompute the stage states from u_n on a copy
+    const char *Rs = (const char *)residuals;
+    if (!Y) {  // recompute the stage states (and, for x_bar, the stage residuals) from u_n on a copy
       HIP_OK(hipMemcpyAsync(TMP, u_n, nb, hipMemcpyDeviceToDevice, st));
-      d.step_record(s, TMP, dt, 1, nullptr, STG, st);
+      d.step_record(s, TMP, dt, 1, nullptr, STG, x_bar ? RES : nullptr, st);
       Y = STG;
+      if (x_bar) Rs = RES;
     }
     // u_{n+1} = u_n + dt/6 (k1 + 2 k2 + 2 k3 + k4); k_{s} = R(y_s), y1 = u_n, y2 = u_n + dt/2 k1,
     // y3 = u_n + dt/2 k2, y4 = u_n + dt k3.  Reverse, with a = u_bar on entry:
@@ -533,8 +535,9 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
     for (int k = 3; k >= 0; --k) {
       GeoVjpArgs geo;
       if (x_bar) {
-        d.rhs_two_sided(s, ys[k], s->geo_R, st);
-        geo = GeoVjpArgs{s->geo_Gm, s->geo_Gn, s->geo_R, s->fhat};
+        const void *Rk = Rs ? (const void *)(Rs + (size_t)k * nb) : s->geo_R;
+        if (!Rs) d.rhs(s, ys[k], s->geo_R, st);  // residual of stage k (adjoint of 1/J)
+        geo = GeoVjpArgs{s->geo_Gm, s->geo_Gn, Rk};
       }
       if (!launch_vjp(s, ys[k], KB, Z, s->vjp_work, A, KB, u_bar, k > 0 ? cA[k - 1] : 0.0, k > 0 ? cZ[k - 1] : 0.0,
                       dt, geo, st))

@@ -11,9 +11,8 @@ namespace frmi {
 // per (dim, p, precision) function table of the forward engine
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
-  void (*rhs_two_sided)(const fr_solver *, const void *, void *, hipStream_t);
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
-  void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, hipStream_t);
+  void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, void *, hipStream_t);
   void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, double *, hipStream_t);
   void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
                          const double *, hipStream_t);
@@ -30,10 +29,10 @@ void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_
 // adjoint engine (fr_vjp.hip)
 size_t vjp_work_elems(const fr_solver *s);
 // geometric adjoint arrays of one residual VJP: metric and normal adjoints accumulate (+=) into
-// Gm / Gn; R and fhat are the forward residual and common flux of the linearisation state
+// Gm / Gn; R is the forward residual at the linearisation state
 struct GeoVjpArgs {
   void *Gm = nullptr, *Gn = nullptr;
-  const void *R = nullptr, *fhat = nullptr;
+  const void *R = nullptr;
 };
 bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar, void *work, const void *rk_a,
                 void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, const GeoVjpArgs &geo,

@@ -4,8 +4,8 @@
 // Forward chain (Eq. (1) in transformed form, degree-q Lagrange map on GLL nodes):
 //   A[j][k] = dx_j/dxi_k = sum_n X_{n,j} dphi_n/dxi_k;  S = adj(A);  1/J = 1/det(A)
 //   flux point of face f (coordinate k_f, side s_f):  N = s_f S_f[k_f, :],  |N|,  n = N / |N|
-// Interior face pairs use the L side's normal on both sides, so the R side's normal adjoint is
-// folded into the L point's (its normal is -n_L).  Per element, one workgroup forms A_bar at
+// Interior face pairs use the L side's normal and |N| on both sides, so the R side's adjoints
+// are folded into the L point's (its normal is -n_L).  Per element, one workgroup forms A_bar at
 // every solution and owning flux point, then dphi^T A_bar at every element node; a second kernel
 // sums each node's contributions over its elements in a fixed order (no atomics).
 #include <hip/hip_runtime.h>
@@ -114,13 +114,14 @@ __global__ __launch_bounds__(256) void k_geo_nodes(const T *__restrict__ Gm, con
         const double mag = sqrt(nrm);
         double nb[D], dot = 0.0;
         for (int j = 0; j < D; ++j) nb[j] = (double)Gn[(e * (D + 1) + j) * Nf + pt];
-        if (code >= 0) {  // the R partner used -n_L
+        double mb = (double)Gn[(e * (D + 1) + D) * Nf + pt];
+        if (code >= 0) {  // the R partner used -n_L and |N_L|
           const int32_t c2 = code & (NBR_R_BIT - 1);
           const int64_t e2 = c2 / Nf;
           const int f2 = c2 % Nf;
           for (int j = 0; j < D; ++j) nb[j] -= (double)Gn[(e2 * (D + 1) + j) * Nf + f2];
+          mb += (double)Gn[(e2 * (D + 1) + D) * Nf + f2];
         }
-        const double mb = (double)Gn[(e * (D + 1) + D) * Nf + pt];
         for (int j = 0; j < D; ++j) dot += nb[j] * N[j] / mag;
         double Sb[D][D];
         for (int k = 0; k < D; ++k)

@@ -448,6 +448,7 @@ struct RKArgs {
   T *uf_next;        // flux-point values of the new stage state, or nullptr
   T *ustage_copy;    // optional second copy of the new stage state (adjoint recording)
   T *u0_copy;        // optional copy of the base state (adjoint recording, first stage)
+  T *r_copy;         // optional copy of this stage's residual (adjoint recording)
 };
 
 // shared epilogue: R at (el, i) for all variables -> rhs output or RK update; the new stage
@@ -464,6 +465,7 @@ __device__ __forceinline__ void rk_epilogue(const T *R, int64_t e, int i, const 
   const T dt = (T)rk.dt[elem_mesh[e]];
   for (int v = 0; v < NV; ++v) {
     const int64_t o = (e * NV + v) * Ns + i;
+    if (rk.r_copy) rk.r_copy[o] = R[v];
     const T a = rk.first ? T(0) : rk.acc[o];
     const T u0 = rk.u0[o];
     if (rk.u0_copy) rk.u0_copy[o] = u0;
@@ -858,13 +860,9 @@ struct Engine {
 
   // one residual evaluation of `u` whose flux-point values are already in s->uf; the epilogue
   // `rk` decides what is written
-  // two_sided: store the viscous normal flux at every flux point and form the common flux in the
-  // face kernel whatever beta is (the mesh-node adjoint reads both)
-  static void stage(const fr_solver *s, const T *u, const RKArgs<T> &rk, hipStream_t st, bool force_sample,
-                    bool two_sided = false) {
+  static void stage(const fr_solver *s, const T *u, const RKArgs<T> &rk, hipStream_t st, bool force_sample) {
     const OpsDev<T, P> o = ops(s);
-    PhysDev<T> ph = phys(s);
-    if (two_sided) ph.side = 0;
+    const PhysDev<T> ph = phys(s);
     const int64_t nface = s->npair + s->nbnd;
     T *uf = (T *)s->uf, *fhat = (T *)s->fhat;
     const T *metric = (const T *)s->metric;
@@ -921,11 +919,11 @@ struct Engine {
     }
   }
 
-  static void rhs(const fr_solver *s, const T *u, T *r, hipStream_t st, bool two_sided = false) {
+  static void rhs(const fr_solver *s, const T *u, T *r, hipStream_t st) {
     interp(s, u, (T *)s->uf, st);
     RKArgs<T> rk{};
     rk.r_out = r;
-    stage(s, u, rk, st, false, two_sided);
+    stage(s, u, rk, st, false);
   }
 
   static void probe(const fr_solver *s, const T *u, hipStream_t st) {
@@ -937,7 +935,7 @@ struct Engine {
   // one classical RK4 step of u in place; `fresh`: s->uf does not hold u_f of u yet (first step
   // of a call); later steps reuse the flux-point values written by the previous last stage
   static void step(const fr_solver *s, T *u, const double *dt, bool sample, bool fresh, hipStream_t st,
-                   T *record = nullptr, T *record_u0 = nullptr) {
+                   T *record = nullptr, T *record_u0 = nullptr, T *record_r = nullptr) {
     static const double cA[4] = {0.5, 0.5, 1.0, 0.0};
     static const double cB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     if (sample) probe(s, u, st);
@@ -955,6 +953,7 @@ struct Engine {
       rk.uf_next = (T *)s->uf;
       rk.ustage_copy = (record && k < 3) ? record + (int64_t)k * s->Ne * S::NV * S::Ns : nullptr;
       rk.u0_copy = k == 0 ? record_u0 : nullptr;
+      rk.r_copy = record_r ? record_r + (int64_t)k * s->Ne * S::NV * S::Ns : nullptr;
       const T *ust = k == 0 ? u : (const T *)s->ustage;
       stage(s, ust, rk, st, sample && k == 0);
     }
@@ -970,20 +969,19 @@ Dispatch make_dispatch() {
   d.rhs = [](const fr_solver *s, const void *u, void *r, hipStream_t st) {
     Engine<D, P, T>::rhs(s, (const T *)u, (T *)r, st);
   };
-  d.rhs_two_sided = [](const fr_solver *s, const void *u, void *r, hipStream_t st) {
-    Engine<D, P, T>::rhs(s, (const T *)u, (T *)r, st, true);
-  };
   d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
     Engine<D, P, T>::step(s, (T *)u, dt, sample, fresh, st);
   };
-  // n steps recording each step's base state (states, optional) and its three stage states;
+  // n steps recording each step's base state (states, optional), its three stage states and
+  // (residuals, optional) the residuals of its four stages;
   // flux-point values carry over between the steps of one call, as in fr_rk_step
   d.step_record = [](const fr_solver *s, void *u, const double *dt, int n, void *states, void *stages,
-                     hipStream_t st) {
+                     void *residuals, hipStream_t st) {
     const int64_t nb = s->Ne * Shape<D, P>::NV * Shape<D, P>::Ns;
     for (int k = 0; k < n; ++k)
       Engine<D, P, T>::step(s, (T *)u, dt, false, k == 0, st, (T *)stages + 3 * nb * k,
-                            states ? (T *)states + nb * k : nullptr);
+                            states ? (T *)states + nb * k : nullptr,
+                            residuals ? (T *)residuals + 4 * nb * k : nullptr);
   };
   d.probe_vjp = [](const fr_solver *s, const void *u, const double *pbar, void *ub, double *xbar, hipStream_t st) {
     if (s->n_probe > 0)

@@ -407,8 +407,8 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
 }
 
 // adjoint of the common-flux kernel: u_f_bar of both sides and (NS) the viscous-normal-flux adjoints
-// GEO: also the adjoints of the unit normal (Rusanov, far-field ghost) and of |N| (from the
-// forward common flux fhatf) at the owning point (L side / boundary point), into Gn
+// GEO: also the adjoints of the unit normal (Rusanov, far-field ghost) and the inviscid and
+// penalty part of the adjoint of |N| at the owning point (L side / boundary point), into Gn
 template <int D, int P, typename T, bool NS, bool GEO>
 __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, const T *__restrict__ fhatbar,
                                                   const int32_t *__restrict__ pairL, const int32_t *__restrict__ pairR,
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
                                                   int64_t n_wall, int64_t nbnd, const int32_t *__restrict__ elem_mesh,
                                                   const FlowDev<T> *__restrict__ flow, PhysDev<T> ph,
                                                   T *__restrict__ ufbar, T *__restrict__ fvnbar,
-                                                  const T *__restrict__ fhatf, T *__restrict__ Gn) {
+                                                  T *__restrict__ Gn) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Nf = S::Nf;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -437,13 +437,16 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
     }
     rusanov_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, uLb, uRb);
     if (GEO) {
-      T nb[D];
+      // |N|_bar = sum (F^_bar_L - F^_bar_R) . F with F = Rusanov + penalty - viscous part; the
+      // viscous part is added by the volume adjoint, which recomputes each side's fvn
+      T nb[D], Fr[NV];
       for (int j = 0; j < D; ++j) nb[j] = T(0);
       rusanov_n_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, nb);
+      rusanov<D>(uL, uR, n, ph.gamma, ph.gm1, Fr);
       T mb = T(0);
-      for (int v = 0; v < NV; ++v) mb += Fb[v] * fhatf[(eL * NV + v) * Nf + fL];
+      for (int v = 0; v < NV; ++v) mb += Fb[v] * (Fr[v] + (NS ? ph.tau * (uL[v] - uR[v]) : T(0)));
       for (int j = 0; j < D; ++j) Gn[(eL * (D + 1) + j) * Nf + fL] += nb[j];
-      Gn[(eL * (D + 1) + D) * Nf + fL] += mb / (mag * mag);
+      Gn[(eL * (D + 1) + D) * Nf + fL] += mb / mag;
     }
     if (NS) {
       const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
@@ -493,10 +496,12 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
       farfield_vjp<D>(uB, n, fl, ph.gamma, ph.gm1, ugb, uBb, GEO ? nb : nullptr);
     }
     if (GEO) {
+      T Fr[NV];
+      rusanov<D>(uB, ug, n, ph.gamma, ph.gm1, Fr);
       T mb = T(0);
-      for (int v = 0; v < NV; ++v) mb += Fb[v] * fhatf[(e * NV + v) * Nf + fp];
+      for (int v = 0; v < NV; ++v) mb += Fb[v] * Fr[v];
       for (int j = 0; j < D; ++j) Gn[(e * (D + 1) + j) * Nf + fp] += nb[j];
-      Gn[(e * (D + 1) + D) * Nf + fp] += mb / (mag * mag);
+      Gn[(e * (D + 1) + D) * Nf + fp] += mb / mag;
     }
     for (int v = 0; v < NV; ++v) {
       ufbar[(e * NV + v) * Nf + fp] = uBb[v];
@@ -676,6 +681,13 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       Visc<D, T> vs;
       visc_state<D>(ub, g, flow[elem_mesh[ef]].mu, ph, heat, vs);
       fvis_columns_dot<D>(vs, fb, nbv);
+      // the common flux is F^ . |N| and enters with this side's fvn_bar: |N|_bar += fvn_bar . fvn / |N|
+      // (stored at this point; the node mapping folds an R point's share into its L partner)
+      T fv[NV];
+      fvis_dot<D>(vs, n, fv);
+      T mb = T(0);
+      for (int v = 0; v < NV; ++v) mb += fb[v] * fv[v];
+      Gn[(ef * (D + 1) + D) * Nf + fpl] += mb / fnrm[(ef * (D + 1) + D) * Nf + fpl];
     }
     if (code < 0) {
       if (wall)
@@ -973,14 +985,14 @@ struct VjpEngine {
     const T *metric = (const T *)s->metric;
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
     T *Gm = (T *)geo.Gm, *Gn = (T *)geo.Gn;
-    const T *Rf = (const T *)geo.R, *fhf = (const T *)geo.fhat;
+    const T *Rf = (const T *)geo.R;
     using TD = VjpDivTile<D, P, T>;
     k_vjp_div<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, u, metric, o, volbar, fhatbar, uf, Rf, Gm, Ne);
     const int64_t nface = s->npair + s->nbnd;
     if (s->equations == 1) {
       k_vjp_face<D, P, T, true, GEO><<<vblk(nface, 256), 256, 0, st>>>(
           uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, fvnbar, fhf, Gn);
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, fvnbar, Gn);
       using TV = VjpVolTile<D, P, T>;
       k_vjp_ns_vol<D, P, T, GEO><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
           u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
@@ -989,7 +1001,7 @@ struct VjpEngine {
     } else {
       k_vjp_face<D, P, T, false, GEO><<<vblk(nface, 256), 256, 0, st>>>(
           uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr, fhf, Gn);
+          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr, Gn);
       k_vjp_euler_vol<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(u, metric, o, ph, volbar, volbar, Gm, Ne);
       k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, nullptr, o, ubar, rk, Ne);
     }

@@ -179,10 +179,12 @@ class Solver:
                                  C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
         return u_bar
 
-    def rk_step_stages(self, u: torch.Tensor, dt: torch.Tensor, stages: torch.Tensor, states=None, stream=None):
+    def rk_step_stages(self, u: torch.Tensor, dt: torch.Tensor, stages: torch.Tensor, states=None, residuals=None,
+                       stream=None):
         """RK4 steps of u in place, recording each step's stage states y2, y3, y4 into stages
         ([3, *shape] for one step, [n, 3, *shape] for n steps) and, if given, each step's base
-        state into states ([n, *shape])."""
+        state into states ([n, *shape]) and its four stage residuals into residuals ([n, 4, *shape]
+        or [4, *shape])."""
         self._check_state(u, "u")
         self._check_dt(dt)
         one = tuple(stages.shape) == (3,) + self.shape
@@ -190,25 +192,30 @@ class Solver:
         if not (stages.is_cuda and stages.dtype == self.dtype and stages.is_contiguous()
                 and (one or tuple(stages.shape) == (n, 3) + self.shape)):
             raise ValueError("stages must be a contiguous CUDA tensor of shape (3,) + state shape or (n, 3) + state shape")
-        sp = None
-        if states is not None:
-            if not (states.is_cuda and states.dtype == self.dtype and states.is_contiguous()
-                    and tuple(states.shape) == (n,) + self.shape):
-                raise ValueError("states must be a contiguous CUDA tensor of shape (n,) + state shape")
-            sp = C.c_void_p(states.data_ptr())
+
+        def opt(t, shape, name):
+            if t is None:
+                return None
+            if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and t.numel() == int(np.prod(shape))):
+                raise ValueError(f"{name} must be a contiguous CUDA tensor with the elements of {shape}")
+            return C.c_void_p(t.data_ptr())
+        sp = opt(states, (n,) + self.shape, "states")
+        rp = opt(residuals, (n, 4) + self.shape, "residuals")
         check(lib().fr_rk_step_stages(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), n, sp,
-                                      C.c_void_p(stages.data_ptr()), _stream(stream)))
+                                      C.c_void_p(stages.data_ptr()), rp, _stream(stream)))
         return u
 
     def rk_step_vjp(self, u_n: torch.Tensor, dt: torch.Tensor, u_bar: torch.Tensor, stages=None, x_bar=None,
-                    stream=None):
+                    residuals=None, stream=None):
         """u_bar <- (d u_{n+1} / d u_n)^T u_bar for one RK4 step from u_n; with x_bar (float64
-        [n_node, dim]) also x_bar += (d u_{n+1} / dX)^T u_bar."""
+        [n_node, dim]) also x_bar += (d u_{n+1} / dX)^T u_bar, using the step's recorded stage
+        residuals ([4, *shape]) when given."""
         self._check_state(u_n, "u_n")
         self._check_state(u_bar, "u_bar")
         self._check_dt(dt)
         sp = C.c_void_p(stages.data_ptr()) if stages is not None else None
-        check(lib().fr_rk_step_vjp(self._h, C.c_void_p(u_n.data_ptr()), C.c_void_p(dt.data_ptr()), sp,
+        rp = C.c_void_p(residuals.data_ptr()) if residuals is not None else None
+        check(lib().fr_rk_step_vjp(self._h, C.c_void_p(u_n.data_ptr()), C.c_void_p(dt.data_ptr()), sp, rp,
                                    C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
         return u_bar
 

@@ -94,6 +94,20 @@ def test_rk_step_vjp_recompute_equals_recorded_stages(gpu):
     b2 = a.clone()
     sol.rk_step_vjp(u0, dtt, b2, None)
     assert torch.equal(b1, b2)
+    # node adjoint: recorded stage residuals, recomputed ones, and residuals evaluated afresh
+    res = torch.empty((4,) + sol.shape, dtype=torch.float64, device=gpu)
+    st2 = torch.empty_like(st)
+    sol.rk_step_stages(u0.clone(), dtt, st2, residuals=res)
+    assert torch.equal(st2, st)
+    xbs = []
+    for stages, residuals in [(st2, res), (None, None), (st2, None)]:
+        b = a.clone()
+        xb = torch.zeros((sol.n_node, 2), dtype=torch.float64, device=gpu)
+        sol.rk_step_vjp(u0, dtt, b, stages, x_bar=xb, residuals=residuals)
+        assert torch.equal(b, b1)
+        xbs.append(xb)
+    assert torch.equal(xbs[0], xbs[1])
+    assert float((xbs[2] - xbs[0]).norm() / xbs[0].norm()) <= 1e-13
 
 
 def test_multi_step_recording_equals_single_steps(gpu):
