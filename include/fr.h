@@ -199,6 +199,15 @@ fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_s
 fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, const void *residuals,
                          void *u_bar, double *x_bar, void *stream);
 
+/* Deferred mesh-node adjoint for reverse sweeps over many steps (the node mapping is linear, so
+ * it can run once): after fr_geo_adjoint_begin, fr_rk_step_vjp calls with a non-NULL x_bar add
+ * their metric and normal adjoints to the handle's accumulators without touching x_bar (their
+ * probe terms, through fr_probe_vjp, still go to x_bar directly); fr_geo_adjoint_end maps the
+ * accumulated adjoints to the nodes, x_bar (device FP64 [n_node][dim]) +=, and ends the mode.
+ * fr_rhs_vjp with x_bar is refused (FR_ERR_ARG) while the mode is on. */
+fr_status fr_geo_adjoint_begin(fr_solver *s, void *stream);
+fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream);
+
 /* Tile-shape autotuner.  For each volume kernel of the solver's equations (Navier-Stokes: the
  * volume kernel and the lifting + RK kernel; Euler: the volume + RK kernel) it times the candidate
  * tile sizes (elements per workgroup: the default, its half and its quarter) with `reps` RK4 steps

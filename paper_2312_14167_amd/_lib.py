@@ -67,6 +67,8 @@ def lib() -> C.CDLL:
     L.fr_rk_step_stages.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.fr_autotune.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.fr_geo_adjoint_begin.argtypes = [vp, vp]
+    L.fr_geo_adjoint_end.argtypes = [vp, vp, vp]
     L.fr_destroy.argtypes = [vp]
     L.fr_destroy.restype = None
     L.fr_last_error.argtypes = []
@@ -74,7 +76,7 @@ def lib() -> C.CDLL:
     for name in ("fr_build_operators", "fr_state_shape", "fr_solpt_coords", "fr_rhs", "fr_rk_step",
                  "fr_probe_oaspl", "fr_probe_series", "fr_reset_accumulators", "fr_rhs_vjp", "fr_solver_info",
                  "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp",
-                 "fr_autotune"):
+                 "fr_autotune", "fr_geo_adjoint_begin", "fr_geo_adjoint_end"):
         getattr(L, name).restype = i32
     _lib = L
     return L

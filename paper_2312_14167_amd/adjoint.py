@@ -51,6 +51,8 @@ class FRTrajectory(torch.autograd.Function):
         states = torch.empty((C,) + sol.shape, dtype=sol.dtype, device=dev)      # reused by every segment
         stages = torch.empty((C, 3) + sol.shape, dtype=sol.dtype, device=dev)
         res = torch.empty((C, 4) + sol.shape, dtype=sol.dtype, device=dev) if xb is not None else None
+        if xb is not None:
+            sol.geo_adjoint_begin()   # metric / normal adjoints of all steps mapped to the nodes once
         for s0 in reversed(range(0, K, C)):
             s1 = min(s0 + C, K)
             u = ctx.ckpts[s0].clone()
@@ -60,6 +62,8 @@ class FRTrajectory(torch.autograd.Function):
                 sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0], x_bar=xb,
                                 residuals=None if res is None else res[n - s0])
                 sol.probe_vjp(states[n - s0], p_bar[n], ub, x_bar=xb)
+        if xb is not None:
+            sol.geo_adjoint_end(xb)
         return ub, None, None, None, None, xb
 
 

@@ -454,6 +454,7 @@ fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar
     }
     GeoVjpArgs geo;
     if (x_bar) {
+      if (s->geo_deferred) throw FrError(FR_ERR_ARG, "fr_rhs_vjp with x_bar inside a deferred node adjoint");
       ensure_geo(s);
       zero_geo(s, st);
       dispatch_of(s).rhs(s, u, s->geo_R, st);  // forward residual at u (adjoint of 1/J)
@@ -527,7 +528,7 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
     const double cZ[4] = {0.5, 0.5, 1.0, 0.0};
     if (x_bar) {
       ensure_geo(s);
-      zero_geo(s, st);
+      if (!s->geo_deferred) zero_geo(s, st);
     }
     d.rk_adj_combine(s, A, nullptr, KB, u_bar, Z, cA[3], 0.0, dt, st);  // A = a, KB = dt/6 a, Z = 0
     // each stage's VJP ends in the RK epilogue: u_bar += z_s, KB = k_{s-1}_bar; with x_bar the
@@ -543,7 +544,35 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
                       dt, geo, st))
         throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
     }
-    if (x_bar && !launch_geo_nodes(s, x_bar, st)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported geometry degree");
+    if (x_bar && !s->geo_deferred && !launch_geo_nodes(s, x_bar, st))
+      throw FrError(FR_ERR_UNSUPPORTED, "unsupported geometry degree");
+    HIP_OK(hipGetLastError());
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_geo_adjoint_begin(fr_solver *s, void *stream) {
+  if (!s) return fail(FR_ERR_ARG, "NULL solver");
+  try {
+    ensure_geo(s);
+    zero_geo(s, (hipStream_t)stream);
+    s->geo_deferred = 1;
+    HIP_OK(hipGetLastError());
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream) {
+  if (!s || !x_bar) return fail(FR_ERR_ARG, "NULL argument");
+  if (!s->geo_deferred) return fail(FR_ERR_ARG, "fr_geo_adjoint_begin was not called");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    s->geo_deferred = 0;
+    if (!launch_geo_nodes(s, x_bar, st)) throw FrError(FR_ERR_UNSUPPORTED, "unsupported geometry degree");
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());

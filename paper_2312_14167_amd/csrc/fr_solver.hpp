@@ -137,6 +137,7 @@ struct fr_solver {
   void *geo_Gm = nullptr;         // [Ne][dim*dim+1][Ns] adjoint of S rows and 1/J (state precision)
   void *geo_Gn = nullptr;         // [Ne][dim+1][Nf] adjoint of the unit normal and |N| at own flux points
   void *geo_R = nullptr;          // [Ne][nv][Ns] forward residual at the linearisation state
+  int geo_deferred = 0;           // between fr_geo_adjoint_begin / _end: accumulate, map once
   double *probe_dw = nullptr;     // [n_probe][dim][Ns] d weights / d xi
   double *probe_dxi = nullptr;    // [n_probe][nn][dim][dim] d xi_k / d X_{n,j}
   int64_t *probe_nodes = nullptr; // [n_probe][nn]

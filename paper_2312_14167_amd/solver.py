@@ -219,6 +219,15 @@ class Solver:
                                    C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
         return u_bar
 
+    def geo_adjoint_begin(self, stream=None):
+        """Start a deferred mesh-node adjoint (see fr_geo_adjoint_begin)."""
+        check(lib().fr_geo_adjoint_begin(self._h, _stream(stream)))
+
+    def geo_adjoint_end(self, x_bar: torch.Tensor, stream=None):
+        """x_bar += the node mapping of the metric / normal adjoints accumulated since begin."""
+        check(lib().fr_geo_adjoint_end(self._h, self._xbar_ptr(x_bar), _stream(stream)))
+        return x_bar
+
     def rhs_vjp(self, u: torch.Tensor, r_bar: torch.Tensor, u_bar: torch.Tensor, x_bar: torch.Tensor | None = None,
                 stream=None):
         self._check_state(u, "u")
