@@ -219,6 +219,30 @@ fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream);
 fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *tiles, double *ms,
                       void *stream);
 
+/* Host statistics of FP64 probe pressure series (no solver, no device; plain host arrays).
+ *
+ * fr_stats_prms_cumulative: the vectors of Eqs. (10)-(12): prms[k] (k < n) is the RMS of the
+ * first k+1 samples about their own mean (the cumulative time average); prms[n-1] is the p_RMS
+ * of Eq. (9).  FR_ERR_ARG for NULL or n < 1.
+ *
+ * fr_stats_observer_oaspl: several observer points per observer (the spanwise probes of one
+ * observer location): series[a][n] for probes a < n_probe, group[a] in [0, n_group) the observer
+ * of probe a.  Per observer g: prms[g] = mean over its probes of each probe's p_RMS (Eq. (9)),
+ * oaspl[g] = 20 log10(prms[g] / p_ref).  FR_ERR_ARG for bad sizes, a group without probes or
+ * p_ref <= 0.
+ *
+ * fr_stats_psd_welch: Welch's method of averaged periodograms for the pressure perturbation:
+ * n_windows segments of even length L = 2 floor(n / (n_windows + 1)) with 50% overlap, each
+ * demeaned and multiplied by the periodic Hann window; one-sided density
+ * psd[f] = c_f sum over segments |DFT|^2 / (n_windows fs sum w^2) (c_f = 2 except at 0 and fs/2),
+ * freq[f] = f fs / L for f = 0..L/2, fs = 1 / sample_dt.  *n_freq = L/2 + 1; FR_ERR_ARG when cap
+ * is smaller, n_windows < 1, sample_dt <= 0 or the series is too short. */
+fr_status fr_stats_prms_cumulative(const double *series, int64_t n, double *prms);
+fr_status fr_stats_observer_oaspl(const double *series, int32_t n_probe, int64_t n, const int32_t *group,
+                                  int32_t n_group, double p_ref, double *prms, double *oaspl);
+fr_status fr_stats_psd_welch(const double *series, int64_t n, int32_t n_windows, double sample_dt, double *freq,
+                             double *psd, int64_t cap, int64_t *n_freq);
+
 /* Release everything the handle owns (NULL is a no-op). */
 void fr_destroy(fr_solver *s);
 

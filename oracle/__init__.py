@@ -14,7 +14,8 @@ What it computes and where the paper fixes it:
   subsection; the paper defers details to earlier work), read as: Gauss-Legendre
   solution and flux points, the g_DG correction function, Rusanov inviscid and
   LDG viscous common fluxes, adiabatic no-slip walls, Riemann-invariant far field;
-* drag coefficient Eq. (8); OASPL, RMS and cumulative mean, Eqs. (9)-(12);
+* drag coefficient Eq. (8); OASPL, RMS and cumulative mean, Eqs. (9)-(12); the spanwise
+  observer average and the Welch spectra of the case sections (``spectra.py``);
 * classical RK4 time stepping with a given dt (the paper's own integrator is a
   second-order optimal scheme whose coefficients it does not print).
 
@@ -24,3 +25,4 @@ from .basis import (  # noqa: F401
     gauss_legendre, lagrange_eval, lagrange_deriv, correction_deriv, gll_nodes, TensorOps,
 )
 from .fr import OracleSystem, oaspl_from_series, cumulative_prms  # noqa: F401
+from .spectra import observer_oaspl, welch_psd  # noqa: F401

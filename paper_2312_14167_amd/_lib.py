@@ -69,6 +69,9 @@ def lib() -> C.CDLL:
     L.fr_autotune.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.fr_geo_adjoint_begin.argtypes = [vp, vp]
     L.fr_geo_adjoint_end.argtypes = [vp, vp, vp]
+    L.fr_stats_prms_cumulative.argtypes = [vp, i64, vp]
+    L.fr_stats_observer_oaspl.argtypes = [vp, i32, i64, vp, i32, dbl, vp, vp]
+    L.fr_stats_psd_welch.argtypes = [vp, i64, i32, dbl, vp, vp, i64, C.POINTER(i64)]
     L.fr_destroy.argtypes = [vp]
     L.fr_destroy.restype = None
     L.fr_last_error.argtypes = []
@@ -76,7 +79,8 @@ def lib() -> C.CDLL:
     for name in ("fr_build_operators", "fr_state_shape", "fr_solpt_coords", "fr_rhs", "fr_rk_step",
                  "fr_probe_oaspl", "fr_probe_series", "fr_reset_accumulators", "fr_rhs_vjp", "fr_solver_info",
                  "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp",
-                 "fr_autotune", "fr_geo_adjoint_begin", "fr_geo_adjoint_end"):
+                 "fr_autotune", "fr_geo_adjoint_begin", "fr_geo_adjoint_end", "fr_stats_prms_cumulative",
+                 "fr_stats_observer_oaspl", "fr_stats_psd_welch"):
         getattr(L, name).restype = i32
     _lib = L
     return L

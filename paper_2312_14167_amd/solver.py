@@ -151,6 +151,43 @@ class Solver:
         return {names[k]: {"elements_per_workgroup": int(tiles[k]),
                            "ms_per_step": [float(x) for x in ms[3 * k:3 * k + 3]]} for k in kinds}
 
+    def probe_statistics(self, p_ref: float, groups=None, n_windows: int = 6, sample_dt: float | None = None,
+                         cap: int | None = None) -> dict:
+        """Host statistics of the recorded probe series (library host code): the cumulative p_RMS
+        vector of every probe (Eqs. (10)-(12)), the OASPL of each observer whose probes are
+        grouped by ``groups`` (spanwise average of p_RMS; default: one observer per probe) and,
+        with ``sample_dt`` (time between samples), the Welch PSD of every probe."""
+        series = np.ascontiguousarray(self.probe_series(cap or 1 << 20))
+        npb, n = series.shape
+        if n == 0:
+            raise ValueError("no samples recorded")
+        L = lib()
+        cum = np.zeros((npb, n))
+        for a in range(npb):
+            check(L.fr_stats_prms_cumulative(series[a].ctypes.data_as(C.c_void_p), n,
+                                             cum[a].ctypes.data_as(C.c_void_p)))
+        grp = np.ascontiguousarray(np.arange(npb) if groups is None else np.asarray(groups), dtype=np.int32)
+        ng = int(grp.max()) + 1
+        prms = np.zeros(ng)
+        oaspl = np.zeros(ng)
+        check(L.fr_stats_observer_oaspl(series.ctypes.data_as(C.c_void_p), npb, n, grp.ctypes.data_as(C.c_void_p),
+                                        ng, float(p_ref), prms.ctypes.data_as(C.c_void_p),
+                                        oaspl.ctypes.data_as(C.c_void_p)))
+        out = {"prms_cumulative": cum, "observer_prms": prms, "observer_oaspl": oaspl}
+        if sample_dt is not None:
+            nf = C.c_int64()
+            spec = []
+            for a in range(npb):
+                f = np.zeros(n)
+                P = np.zeros(n)
+                check(L.fr_stats_psd_welch(series[a].ctypes.data_as(C.c_void_p), n, int(n_windows), float(sample_dt),
+                                           f.ctypes.data_as(C.c_void_p), P.ctypes.data_as(C.c_void_p), n,
+                                           C.byref(nf)))
+                spec.append(P[:nf.value])
+            out["freq"] = f[:nf.value]
+            out["psd"] = np.stack(spec)
+        return out
+
     def info(self) -> dict:
         a = np.zeros(8, dtype=np.int64)
         check(lib().fr_solver_info(self._h, a.ctypes.data_as(C.c_void_p)))

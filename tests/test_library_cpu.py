@@ -107,3 +107,59 @@ def test_host_validation_errors_without_gpu():
     st, msg, _ = _build(m)
     assert st == lb.FR_ERR_ARG
     L.fr_destroy(None)
+
+
+# ----------------------------------------------------------------------------- host statistics
+def _dp(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def test_host_statistics_match_the_oracle():
+    """fr_stats_* (plain host code of the library) against the oracle's definitions on seeded
+    series shaped like probe pressure records (p_inf ~ 17.9 plus small fluctuations)."""
+    from oracle import cumulative_prms, observer_oaspl, welch_psd
+    L = _lib().lib()
+    rng = np.random.default_rng(12)
+    n = 2500
+    t = np.arange(n) * 0.02
+    S = np.stack([17.857 + 1e-3 * np.sin(2.1 * t + a) + 2e-4 * rng.normal(size=n) for a in range(6)])
+    S = np.ascontiguousarray(S)
+    # cumulative RMS vectors
+    out = np.zeros(n)
+    assert L.fr_stats_prms_cumulative(_dp(S[2]), n, _dp(out)) == 0
+    ref = cumulative_prms(S[2])
+    np.testing.assert_allclose(out, ref, rtol=1e-9, atol=0)
+    # spanwise observers: probes 0-2 and 3-5
+    grp = np.array([0, 0, 0, 1, 1, 1], dtype=np.int32)
+    prms = np.zeros(2)
+    db = np.zeros(2)
+    assert L.fr_stats_observer_oaspl(_dp(S), 6, n, _dp(grp), 2, 2e-5, _dp(prms), _dp(db)) == 0
+    rp, rd = observer_oaspl(S, grp, 2, 2e-5)
+    np.testing.assert_allclose(prms, rp, rtol=1e-9)
+    np.testing.assert_allclose(db, rd, rtol=0, atol=1e-9)
+    # Welch PSD
+    cap = 2000
+    f = np.zeros(cap)
+    P = np.zeros(cap)
+    nf = C.c_int64()
+    assert L.fr_stats_psd_welch(_dp(S[4]), n, 6, 0.02, _dp(f), _dp(P), cap, C.byref(nf)) == 0
+    fr, Pr = welch_psd(S[4], 6, 0.02)
+    assert nf.value == len(fr)
+    np.testing.assert_allclose(f[:nf.value], fr, rtol=1e-13)
+    np.testing.assert_allclose(P[:nf.value], Pr, rtol=1e-8, atol=1e-10 * Pr.max())
+
+
+def test_host_statistics_argument_errors():
+    L = _lib().lib()
+    x = np.ones(10)
+    out = np.zeros(10)
+    nf = C.c_int64()
+    assert L.fr_stats_prms_cumulative(None, 10, _dp(out)) == -1
+    assert L.fr_stats_prms_cumulative(_dp(x), 0, _dp(out)) == -1
+    assert L.fr_stats_psd_welch(_dp(x), 5, 6, 0.1, _dp(out), _dp(out), 10, C.byref(nf)) == -1  # too short
+    y = np.ones(100)
+    assert L.fr_stats_psd_welch(_dp(y), 100, 3, 0.1, _dp(out), _dp(out), 10, C.byref(nf)) == -1  # cap < L/2+1
+    assert nf.value == 26
+    grp = np.array([0, 2], dtype=np.int32)
+    two = np.ones((2, 10))
+    assert L.fr_stats_observer_oaspl(_dp(two), 2, 10, _dp(grp), 2, 1.0, _dp(out), _dp(out)) == -1

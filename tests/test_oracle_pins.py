@@ -484,3 +484,43 @@ def test_probe_node_gradient_matches_relocated_probe():
         fd = (vals[0] - vals[1]) / (2 * eps)
         ad = float((g * torch.tensor(V)).sum())
         assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-6), (fd, ad)
+
+
+# ----------------------------------------------------------------------------- observer statistics
+def test_welch_psd_matches_scipy_and_tone_closed_form():
+    """The oracle's Welch PSD equals scipy.signal.welch with the same segmentation (a textbook
+    routine); a tone at an exact bin integrates to A^2/2 (periodic Hann window, density scaling)
+    and peaks at its frequency; white noise integrates to its variance."""
+    import scipy.signal
+    from oracle import welch_psd
+    rng = np.random.default_rng(4)
+    n, nw, dt = 3001, 6, 0.05
+    x = 17.0 + rng.normal(size=n) * 0.3
+    f, P = welch_psd(x, nw, dt)
+    L = 2 * (n // (nw + 1))
+    fr, Pr = scipy.signal.welch(x[:L * (nw + 1) // 2], fs=1 / dt, window="hann", nperseg=L, noverlap=L // 2,
+                                detrend="constant", scaling="density")
+    np.testing.assert_allclose(f, fr, rtol=1e-14)
+    np.testing.assert_allclose(P, Pr, rtol=1e-11, atol=0)
+    df = f[1] - f[0]
+    assert abs(P.sum() * df - x.var()) <= 0.1 * x.var()
+    A, b = 0.7, 23
+    t = np.arange(L * (nw + 1) // 2)
+    tone = A * np.sin(2 * np.pi * b * t / L)
+    f2, P2 = welch_psd(tone, nw, dt)
+    assert int(np.argmax(P2)) == b
+    assert abs(P2.sum() * (f2[1] - f2[0]) - A * A / 2) <= 1e-12
+
+
+def test_observer_average_of_rms():
+    """Spanwise observer: the averaged p_RMS of identical probes is that probe's p_RMS; probes of
+    an observer are averaged in RMS (not in mean square)."""
+    from oracle import cumulative_prms, observer_oaspl
+    rng = np.random.default_rng(9)
+    s1 = rng.normal(size=200)
+    s2 = 3.0 * rng.normal(size=200)
+    avg, db = observer_oaspl(np.stack([s1, s1, s2, s1]), np.array([0, 0, 1, 1]), 2, 1e-3)
+    r1, r2 = cumulative_prms(s1)[-1], cumulative_prms(s2)[-1]
+    assert abs(avg[0] - r1) <= 1e-15 * r1
+    assert abs(avg[1] - 0.5 * (r1 + r2)) <= 1e-14 * r2
+    assert abs(db[0] - 20 * np.log10(r1 / 1e-3)) <= 1e-12
