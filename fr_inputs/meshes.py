@@ -468,21 +468,25 @@ def c_grid_naca(n_wake: int = 40, n_foil: int = 120, n_normal: int = 80, n_span:
 
 def concat_meshes(meshes) -> MeshDesc:
     """Concatenate independent meshes of equal dim and q into one description with
-    disjoint element ranges (the batched form advances them together)."""
+    disjoint element ranges (the batched form advances them together).  Faces are only ever
+    paired within one mesh, so the meshes may overlap in space; periodic meshes must share
+    their translation vectors (e.g. the same span)."""
     d, q = meshes[0].dim, meshes[0].q
+    pv = np.asarray(meshes[0].periodic_vec, float).reshape(-1, d)
     xs, ens, fbs, begins = [], [], [], [0]
     off = 0
     for m in meshes:
         if m.dim != d or m.q != q:
             raise ValueError("meshes must share dim and geometry degree")
-        if len(m.periodic_vec):
-            raise ValueError("concatenated meshes may not be periodic (translations would cross meshes)")
+        mv = np.asarray(m.periodic_vec, float).reshape(-1, d)
+        if mv.shape != pv.shape or not np.allclose(mv, pv, rtol=0, atol=1e-12):
+            raise ValueError("concatenated meshes must share their periodic translations")
         xs.append(m.node_xyz)
         ens.append(m.elem_nodes + off)
         fbs.append(m.face_bc)
         off += m.node_xyz.shape[0]
         begins.append(begins[-1] + m.n_elem)
     return MeshDesc(dim=d, q=q, node_xyz=np.concatenate(xs), elem_nodes=np.concatenate(ens),
-                    face_bc=np.concatenate(fbs), periodic_vec=np.zeros((0, d)),
+                    face_bc=np.concatenate(fbs), periodic_vec=pv.copy(),
                     mesh_elem_begin=np.array(begins, dtype=np.int64),
                     info={"kind": "batch", "parts": [m.info for m in meshes]})

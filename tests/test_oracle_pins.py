@@ -320,20 +320,28 @@ def test_unmatched_face_and_inverted_element_raise():
         OracleSystem(m, 2, fi.vortex_params(), equations="euler", probes=[[50.0, 0.0]])
 
 
-def test_batched_meshes_equal_separate_solves():
+@pytest.mark.parametrize("kind", ["cavities", "periodic_cgrids"])
+def test_batched_meshes_equal_separate_solves(kind):
     """Concatenated independent meshes (a poll's designs) evolve exactly as separate solves, even
-    when their geometries overlap in space (faces never pair across meshes)."""
-    ms = [fi.cavity(a, h=0.5, q=2, upstream=2.0, top=3.0, outflow=3.0, top_buffer=1.0, out_buffer=1.0)
-          for a in (1.5, 2.5)]
-    fps = [fi.freestream_params(2, 0.15, 1500.0), fi.freestream_params(2, 0.2, 1000.0, aoa_deg=5.0)]
+    when their geometries overlap in space (faces never pair across meshes), also for spanwise
+    periodic meshes sharing their period."""
+    if kind == "cavities":
+        ms = [fi.cavity(a, h=0.5, q=2, upstream=2.0, top=3.0, outflow=3.0, top_buffer=1.0, out_buffer=1.0)
+              for a in (1.5, 2.5)]
+        fps = [fi.freestream_params(2, 0.15, 1500.0), fi.freestream_params(2, 0.2, 1000.0, aoa_deg=5.0)]
+    else:
+        g = dict(n_wake=2, n_foil=6, n_normal=2, n_span=2, q=2, r_out=4.0, x_out=6.0, h_wall=0.05)
+        ms = [fi.c_grid_naca(camber=c, thickness=t, **g) for c, t in ((0.0, 0.12), (0.03, 0.09))]
+        fps = [fi.freestream_params(3, 0.2, 23000.0, aoa_deg=a) for a in (2.0, 5.0)]
     batch = fi.concat_meshes(ms)
     fpb = fi.FlowParams(dim=2, rho_inf=np.concatenate([f.rho_inf for f in fps]),
                         vel_inf=np.concatenate([f.vel_inf for f in fps]),
                         p_inf=np.concatenate([f.p_inf for f in fps]), mu=np.concatenate([f.mu for f in fps]))
-    sb = OracleSystem(batch, 3, fpb, equations="ns")
+    pdeg = 3 if kind == "cavities" else 2
+    sb = OracleSystem(batch, pdeg, fpb, equations="ns")
     parts = []
     for m, f in zip(ms, fps):
-        s = OracleSystem(m, 3, f, equations="ns")
+        s = OracleSystem(m, pdeg, f, equations="ns")
         u = state_at(s, fi.freestream_state, fp=f)
         u = u * (1.0 + torch.tensor(fi.noise_like(u.shape, 4, 0.01)))
         parts.append((s, u))
