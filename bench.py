@@ -25,6 +25,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FR RK-stage GDoF/s (p=4 hex, FP64 vs FP32 vs batched); adjoint/fwd time"
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "naca_cgrid_p4_fp64_traffic.json")
+KERNEL_SOURCES = ["fr_kernels.hip", "fr_device.hpp", "fr_solver.hpp"]
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the sources of the forward kernels (the counters of profiles/ go stale when
+    these change)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_14167_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
+    or None when there is none or the kernels changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_digest() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    return k["read_bytes"] + k["write_bytes"]
 KNAMES = ["interp", "common_sol", "ns_grad", "face_flux", "div_rk", "euler_vol_rk", "probe", "wall_force"]
 
 
@@ -423,7 +451,7 @@ def main():
                                 f"wall-force sampling"),
                    "dof": info[0] * info[1] * info[2], "stages_per_step": 4},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": avg_ms},
         "kernels": per_kernel,
         "tiles": r64.get("tiles"),
