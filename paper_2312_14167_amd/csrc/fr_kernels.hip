@@ -188,29 +188,35 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][D][NV][Ns] gradient / F~
   tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
   const int side = ph.side;
-  // list of faces whose viscous normal flux is consumed (boundary faces, and interior faces on
-  // the flux side); every flux point of a face shares its partner face and its side
+  // faces of the tile ordered with those whose viscous normal flux is consumed first (boundary
+  // faces, and interior faces on the flux side; every flux point of a face shares its partner
+  // face and its side), s_nface of them; the flux-point phases walk this order, so that the
+  // waves doing flux-side work (neighbour gather, Rusanov) are not split with the others
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     int cnt = 0;
-    for (int b = 0; b < ne * NFACE; b += 64) {
-      const int fi = b + lane;
-      bool need = false;
-      if (fi < ne * NFACE) {
-        const int32_t code = nbr[(e0 + fi / NFACE) * Nf + (fi % NFACE) * Nfp];
-        need = code < 0 || side == 0 || (((code & NBR_R_BIT) != 0) == (side > 0));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int b = 0; b < ne * NFACE; b += 64) {
+        const int fi = b + lane;
+        bool need = false;
+        if (fi < ne * NFACE) {
+          const int32_t code = nbr[(e0 + fi / NFACE) * Nf + (fi % NFACE) * Nfp];
+          need = code < 0 || side == 0 || (((code & NBR_R_BIT) != 0) == (side > 0));
+        }
+        const bool take = fi < ne * NFACE && (pass == 0 ? need : !need);
+        const unsigned long long m = __ballot(take);
+        if (take) s_face[cnt + __popcll(m & ((1ull << lane) - 1ull))] = fi;
+        cnt += __popcll(m);
       }
-      const unsigned long long m = __ballot(need);
-      if (need) s_face[cnt + __popcll(m & ((1ull << lane) - 1ull))] = fi;
-      cnt += __popcll(m);
+      if (pass == 0 && lane == 0) s_nface = cnt;
     }
-    if (lane == 0) s_nface = cnt;
   }
   __syncthreads();
   const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;     // LDG common solution: weights of u_L, u_R
   const T wlf = T(0.5) - ph.beta, wrf = T(0.5) + ph.beta;   // LDG common viscous flux: weights of F_L, F_R
   for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
-    const int el = idx / Nf, fp = idx % Nf;
+    const int fc0 = s_face[idx / Nfp];
+    const int el = fc0 / NFACE, fp = (fc0 % NFACE) * Nfp + idx % Nfp;
     const int64_t e = e0 + el;
     int base, stride, fs;
     line_of_fpt<D, P>(fp, base, stride, fs);
