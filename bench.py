@@ -376,7 +376,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 192,000 hexes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["adjoint", "drift", "batched"],
+    ap.add_argument("--only", choices=["adjoint", "drift", "batched", "fp32"],
                     help="run one secondary measurement alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -401,6 +401,11 @@ def main():
     if args.only:
         if args.only == "adjoint":
             r = adjoint_ratio()
+        elif args.only == "fp32":
+            mesh, fp, aoa = naca_workload(scale=args.scale)
+            r = run_variant(mesh, fp, "fp32", K, W, probes=mesh.info["probe"][None, :], profile=True)
+            r = {"gdofs": r["gdofs"], "ms_per_step": r["ms_per_step"], "tiles": r["tiles"],
+                 "kernels": {k: v[0] / v[1] for k, v in r["kernels"].items()}}
         elif args.only == "drift":
             r = cylinder_precision_drift()
         else:
