@@ -129,10 +129,12 @@ template <int D, int P, typename T, int EE = 0>
 struct GradTile {
   using S = Shape<D, P>;
   // per element: the state [NV][Ns], kept to the flux-point viscous phase, then one region that
-  // holds u^ - u_f [NV][Nf], the physical gradient [D][NV][Ns] and the transformed flux
-  // [D][NV][Ns] in turn.  The default E fits four workgroups in 160 KB of LDS.
+  // holds u^ - u_f [NV][Nf] (with the tile's neighbour codes [Nf] behind all elements' u^ - u_f),
+  // the physical gradient [D][NV][Ns] and the transformed flux [D][NV][Ns] in turn.  The default
+  // E fits four workgroups in 160 KB of LDS.
   static constexpr int LU = S::NV * S::Ns;
-  static constexpr int LG = cmax(S::NV * S::Nf, D * S::NV * S::Ns);
+  static constexpr int LC = (S::Nf * (int)sizeof(int32_t) + (int)sizeof(T) - 1) / (int)sizeof(T);
+  static constexpr int LG = cmax(S::NV * S::Nf + LC, D * S::NV * S::Ns);
   static constexpr int LE = LU + LG;
   static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
@@ -181,35 +183,48 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   __shared__ OpsDev<T, P> ops;
   __shared__ int s_face[E * NFACE];
   __shared__ int s_nface;
+  __shared__ int s_mesh[E];  // mesh of each element (free-stream data)
   stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  // tile bases are uniform; per-thread offsets inside the tile are 32-bit
+  const int32_t *nbr_t = nbr + e0 * Nf;
+  const T *fnrm_t = fnrm + e0 * (D + 1) * Nf, *metric_t = metric + e0 * NM * Ns;
+  T *fvn_t = fvn + e0 * NV * Nf, *fhat_t = fhat + e0 * NV * Nf, *vol_t = vol + e0 * NV * Ns;
   T *lu = lds;                // [E][NV][Ns]
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][D][NV][Ns] gradient / F~
+  int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
+  // the state, the neighbour codes and the mesh indices arrive together, so the first flux-point
+  // phase starts its neighbour gathers without another round trip to memory
   tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
+  for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) lcode[idx] = nbr_t[(uint32_t)idx];
+  if (threadIdx.x < ne) s_mesh[threadIdx.x] = elem_mesh[e0 + threadIdx.x];
+  __syncthreads();
   const int side = ph.side;
-  // faces of the tile ordered with those whose viscous normal flux is consumed first (boundary
-  // faces, and interior faces on the flux side; every flux point of a face shares its partner
-  // face and its side), s_nface of them; the flux-point phases walk this order, so that the
-  // waves doing flux-side work (neighbour gather, Rusanov) are not split with the others
+  // faces of the tile ordered with those whose viscous normal flux is consumed (boundary faces,
+  // and interior faces on the flux side; every flux point of a face shares its partner face and
+  // its side) at the front, s_nface of them, the others behind; the flux-point phases walk this
+  // order, so that the waves doing flux-side work (neighbour gather, Rusanov) are not split with
+  // the others
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    int cnt = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int b = 0; b < ne * NFACE; b += 64) {
-        const int fi = b + lane;
-        bool need = false;
-        if (fi < ne * NFACE) {
-          const int32_t code = nbr[(e0 + fi / NFACE) * Nf + (fi % NFACE) * Nfp];
-          need = code < 0 || side == 0 || (((code & NBR_R_BIT) != 0) == (side > 0));
-        }
-        const bool take = fi < ne * NFACE && (pass == 0 ? need : !need);
-        const unsigned long long m = __ballot(take);
-        if (take) s_face[cnt + __popcll(m & ((1ull << lane) - 1ull))] = fi;
-        cnt += __popcll(m);
+    int cnt = 0, rest = 0;
+    for (int b = 0; b < ne * NFACE; b += 64) {
+      const int fi = b + lane;
+      const bool in = fi < ne * NFACE;
+      bool need = false;
+      if (in) {
+        const int32_t code = lcode[(fi / NFACE) * Nf + (fi % NFACE) * Nfp];
+        need = code < 0 || side == 0 || (((code & NBR_R_BIT) != 0) == (side > 0));
       }
-      if (pass == 0 && lane == 0) s_nface = cnt;
+      const unsigned long long below = (1ull << lane) - 1ull;
+      const unsigned long long m = __ballot(in && need), mo = __ballot(in && !need);
+      if (in && need) s_face[cnt + __popcll(m & below)] = fi;
+      if (in && !need) s_face[ne * NFACE - 1 - rest - __popcll(mo & below)] = fi;
+      cnt += __popcll(m);
+      rest += __popcll(mo);
     }
+    if (lane == 0) s_nface = cnt;
   }
   __syncthreads();
   const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;     // LDG common solution: weights of u_L, u_R
@@ -217,7 +232,6 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
     const int fc0 = s_face[idx / Nfp];
     const int el = fc0 / NFACE, fp = (fc0 % NFACE) * Nfp + idx % Nfp;
-    const int64_t e = e0 + el;
     int base, stride, fs;
     line_of_fpt<D, P>(fp, base, stride, fs);
     const T *lv = fs ? ops.lp : ops.lm;
@@ -229,7 +243,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
       for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
       uo[v] = s;
     }
-    const int32_t code = nbr[e * Nf + fp];
+    const int32_t code = lcode[el * Nf + fp];
     if (code >= 0) {
       const int32_t c = code & (NBR_R_BIT - 1);
       const int64_t e2 = c / Nf;
@@ -245,15 +259,16 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
         // flux side of a one-sided pair: inviscid common flux along n_L plus the penalty, x |N|,
         // into this point's fhat; the flux-point phase adds the viscous part
         T n[D], F[NV];
-        for (int j = 0; j < D; ++j) n[j] = fnrm[(e * (D + 1) + j) * Nf + fp];
-        const T mag = fnrm[(e * (D + 1) + D) * Nf + fp];
+        for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((el * (D + 1) + j) * Nf + fp)];
+        const T mag = fnrm_t[(uint32_t)((el * (D + 1) + D) * Nf + fp)];
+        T *fo = fhat_t + (uint32_t)(el * NV * Nf + fp);
         if (isR) {
           for (int j = 0; j < D; ++j) n[j] = -n[j];  // n_L
           rusanov<D>(un, uo, n, ph.gamma, ph.gm1, F);
-          for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = (F[v] + ph.tau * (un[v] - uo[v])) * mag;
+          for (int v = 0; v < NV; ++v) fo[v * Nf] = (F[v] + ph.tau * (un[v] - uo[v])) * mag;
         } else {
           rusanov<D>(uo, un, n, ph.gamma, ph.gm1, F);
-          for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
+          for (int v = 0; v < NV; ++v) fo[v * Nf] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
         }
       }
     } else {
@@ -264,7 +279,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
       if (wall) {
         wall_state<D>(uo, uh);
       } else {
-        farfield<D>(uo, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, uh);
+        farfield<D>(uo, n, flow[s_mesh[el]], ph.gamma, ph.gm1, uh);
       }
       if (side != 0) {
         // boundary flux, inviscid part: Rusanov against the ghost (wall reflection / far-field state)
@@ -278,7 +293,8 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
         }
         rusanov<D>(uo, ug, n, ph.gamma, ph.gm1, F);
         const T mag = bnrm[b * (D + 1) + D];
-        for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = F[v] * mag;
+        T *fo = fhat_t + (uint32_t)(el * NV * Nf + fp);
+        for (int v = 0; v < NV; ++v) fo[v * Nf] = F[v] * mag;
       }
     }
     for (int v = 0; v < NV; ++v) lw[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
@@ -286,14 +302,13 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   __syncthreads();
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
-  const int64_t e = e0 + el;
   // corrected physical gradient at the own solution point
   T gx[D][NV];
   if (act) {
     T Sm[D][D];
     for (int k = 0; k < D; ++k)
-      for (int j = 0; j < D; ++j) Sm[k][j] = metric[(e * NM + k * D + j) * Ns + i];
-    const T invJ = metric[(e * NM + D * D) * Ns + i];
+      for (int j = 0; j < D; ++j) Sm[k][j] = metric_t[(uint32_t)((el * NM + k * D + j) * Ns + i)];
+    const T invJ = metric_t[(uint32_t)((el * NM + D * D) * Ns + i)];
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) gx[j][v] = T(0);
 #pragma unroll 1
@@ -335,7 +350,6 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   for (int idx = threadIdx.x; idx < nfc * Nfp; idx += blockDim.x) {
     const int fc = s_face[idx / Nfp];
     const int elf = fc / NFACE, fp = (fc % NFACE) * Nfp + idx % Nfp;
-    const int64_t ef = e0 + elf;
     int base, stride, fs;
     line_of_fpt<D, P>(fp, base, stride, fs);
     const T *lv = fs ? ops.lp : ops.lm;
@@ -347,9 +361,9 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
       for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
       uo[v] = s;
     }
-    for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * (D + 1) + j) * Nf + fp];
-    const int32_t code = nbr[ef * Nf + fp];
-    const int mi = elem_mesh[ef];
+    for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((elf * (D + 1) + j) * Nf + fp)];
+    const int32_t code = nbr_t[(uint32_t)(elf * Nf + fp)];
+    const FlowDev<T> &fl = flow[s_mesh[elf]];
     bool heat = true, wall = false;
     if (code < 0) {
       wall = (-(int64_t)code - 1) < n_wall;
@@ -357,7 +371,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
         wall_state<D>(uo, st);
         heat = false;
       } else {
-        farfield<D>(uo, n, flow[mi], ph.gamma, ph.gm1, st);
+        farfield<D>(uo, n, fl, ph.gamma, ph.gm1, st);
       }
     } else {
       for (int v = 0; v < NV; ++v) st[v] = uo[v];
@@ -371,13 +385,13 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
       return s;
     };
     T fv[NV];
-    fvis_normal_stream<D>(st, gdir, n, flow[mi].mu, ph, heat, fv);
+    fvis_normal_stream<D>(st, gdir, n, fl.mu, ph, heat, fv);
     if (side == 0 || code < 0)
-      for (int v = 0; v < NV; ++v) fvn[(ef * NV + v) * Nf + fp] = fv[v];
+      for (int v = 0; v < NV; ++v) fvn_t[(uint32_t)((elf * NV + v) * Nf + fp)] = fv[v];
     if (side == 0) continue;
     // complete the common flux started in the first phase (same workgroup, ordered by the barriers)
-    const T mag = fnrm[(ef * (D + 1) + D) * Nf + fp];
-    T *fo = fhat + ef * NV * Nf + fp;
+    const T mag = fnrm_t[(uint32_t)((elf * (D + 1) + D) * Nf + fp)];
+    T *fo = fhat_t + (uint32_t)(elf * NV * Nf + fp);
     if (code < 0) {
       for (int v = 0; v < NV; ++v) fo[v * Nf] = fo[v * Nf] - fv[v] * mag;
     } else {
@@ -407,10 +421,10 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) g[j * NV + v] = lw[((el * D + j) * NV + v) * Ns + i];
     Visc<D, T> vs;
-    visc_state<D>(uv, g, flow[elem_mesh[e]].mu, ph, true, vs);
+    visc_state<D>(uv, g, flow[s_mesh[el]].mu, ph, true, vs);
     for (int k = 0; k < D; ++k) {
       T Sk[D], fi[NV], fv[NV];
-      for (int j = 0; j < D; ++j) Sk[j] = metric[(e * NM + k * D + j) * Ns + i];  // second read: L2
+      for (int j = 0; j < D; ++j) Sk[j] = metric_t[(uint32_t)((el * NM + k * D + j) * Ns + i)];  // second read
       finv_dot<D>(uv, Sk, ph.gm1, fi);
       fvis_dot<D>(vs, Sk, fv);
       for (int v = 0; v < NV; ++v) ft[k][v] = fi[v] - fv[v];
@@ -437,7 +451,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
         accv[v] += ds;
       }
     }
-    for (int v = 0; v < NV; ++v) vol[(e * NV + v) * Ns + i] = accv[v];
+    for (int v = 0; v < NV; ++v) vol_t[(uint32_t)((el * NV + v) * Ns + i)] = accv[v];
   }
 }
 
