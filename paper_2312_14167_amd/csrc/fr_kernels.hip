@@ -364,6 +364,13 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
     for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((elf * (D + 1) + j) * Nf + fp)];
     const int32_t code = nbr_t[(uint32_t)(elf * Nf + fp)];
     const FlowDev<T> &fl = flow[s_mesh[elf]];
+    // the common-flux partial of the first phase and |N| are requested with the other loads
+    T *fo = fhat_t + (uint32_t)(elf * NV * Nf + fp);
+    T fprev[NV], mag = T(0);
+    if (side != 0) {
+      mag = fnrm_t[(uint32_t)((elf * (D + 1) + D) * Nf + fp)];
+      for (int v = 0; v < NV; ++v) fprev[v] = fo[v * Nf];
+    }
     bool heat = true, wall = false;
     if (code < 0) {
       wall = (-(int64_t)code - 1) < n_wall;
@@ -390,22 +397,20 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
       for (int v = 0; v < NV; ++v) fvn_t[(uint32_t)((elf * NV + v) * Nf + fp)] = fv[v];
     if (side == 0) continue;
     // complete the common flux started in the first phase (same workgroup, ordered by the barriers)
-    const T mag = fnrm_t[(uint32_t)((elf * (D + 1) + D) * Nf + fp)];
-    T *fo = fhat_t + (uint32_t)(elf * NV * Nf + fp);
     if (code < 0) {
-      for (int v = 0; v < NV; ++v) fo[v * Nf] = fo[v * Nf] - fv[v] * mag;
+      for (int v = 0; v < NV; ++v) fo[v * Nf] = fprev[v] - fv[v] * mag;
     } else {
       const int32_t c = code & (NBR_R_BIT - 1);
       T *fq = fhat + (int64_t)(c / Nf) * NV * Nf + c % Nf;
       if (code & NBR_R_BIT) {  // F^ . n_L = ... + (1/2 + b) fvn_R
         for (int v = 0; v < NV; ++v) {
-          const T t = fo[v * Nf] + wrf * fv[v] * mag;
+          const T t = fprev[v] + wrf * fv[v] * mag;
           fo[v * Nf] = -t;
           fq[v * Nf] = t;
         }
       } else {                 // F^ . n_L = ... - (1/2 - b) fvn_L
         for (int v = 0; v < NV; ++v) {
-          const T t = fo[v * Nf] - wlf * fv[v] * mag;
+          const T t = fprev[v] - wlf * fv[v] * mag;
           fo[v * Nf] = t;
           fq[v * Nf] = -t;
         }
