@@ -226,6 +226,30 @@ __device__ __forceinline__ void stage_ops(OpsDev<T, P> &dst, const OpsDev<T, P> 
   for (int k = threadIdx.x; k < n; k += blockDim.x) d[k] = s[k];
 }
 
+// contiguous tile copy global -> LDS of n <= NMAX elements by a BS-thread block, split in two so
+// that a kernel requests all of its start-up loads before the first wait: load() issues every
+// element load of this thread, store() puts them into LDS (one memory round trip per tile instead
+// of one per loop iteration)
+template <int NMAX, int BS, typename T>
+struct TileLoad {
+  static constexpr int K = (NMAX + BS - 1) / BS;
+  T r[K];
+  __device__ __forceinline__ void load(const T *__restrict__ src, int n) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int idx = (int)threadIdx.x + k * BS;
+      if (idx < n) r[k] = src[(uint32_t)idx];
+    }
+  }
+  __device__ __forceinline__ void store(T *__restrict__ dst, int n) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int idx = (int)threadIdx.x + k * BS;
+      if (idx < n) dst[idx] = r[k];
+    }
+  }
+};
+
 // contiguous tile copy global -> LDS, 16-byte vector accesses when both sides allow it
 template <typename T>
 __device__ __forceinline__ void tile_load(T *__restrict__ dst, const T *__restrict__ src, int n) {

@@ -184,7 +184,6 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   __shared__ int s_face[E * NFACE];
   __shared__ int s_nface;
   __shared__ int s_mesh[E];  // mesh of each element (free-stream data)
-  stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
   // tile bases are uniform; per-thread offsets inside the tile are 32-bit
@@ -194,11 +193,19 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   T *lu = lds;                // [E][NV][Ns]
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][D][NV][Ns] gradient / F~
   int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
-  // the state, the neighbour codes and the mesh indices arrive together, so the first flux-point
-  // phase starts its neighbour gathers without another round trip to memory
-  tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
-  for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) lcode[idx] = nbr_t[(uint32_t)idx];
-  if (threadIdx.x < ne) s_mesh[threadIdx.x] = elem_mesh[e0 + threadIdx.x];
+  // the state, the neighbour codes and the mesh indices arrive in one round trip, so the first
+  // flux-point phase starts its neighbour gathers without another one
+  {
+    TileLoad<E * NV * Ns, TL::BS, T> tu;
+    TileLoad<E * Nf, TL::BS, int32_t> tc;
+    tu.load(u + e0 * NV * Ns, ne * NV * Ns);
+    tc.load(nbr_t, ne * Nf);
+    const int mesh = (int)threadIdx.x < ne ? elem_mesh[e0 + threadIdx.x] : 0;
+    stage_ops(ops, ops_arg);
+    tu.store(lu, ne * NV * Ns);
+    tc.store(lcode, ne * Nf);
+    if ((int)threadIdx.x < ne) s_mesh[threadIdx.x] = mesh;
+  }
   __syncthreads();
   const int side = ph.side;
   // faces of the tile ordered with those whose viscous normal flux is consumed (boundary faces,
@@ -476,23 +483,46 @@ struct RKArgs {
   T *r_copy;         // optional copy of this stage's residual (adjoint recording)
 };
 
+// what the RK epilogue reads at (e, i): requested with the kernel's other loads so that their
+// latency is shared
+template <typename T, int NV>
+struct RKIn {
+  T u0[NV], acc[NV];
+  int mesh;
+};
+
+template <int D, int P, typename T>
+__device__ __forceinline__ void rk_prefetch(int64_t e, int i, const RKArgs<T> &rk,
+                                            const int32_t *__restrict__ elem_mesh, RKIn<T, Shape<D, P>::NV> &in) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns;
+  in.mesh = 0;
+  if (rk.r_out) return;
+  in.mesh = elem_mesh[e];
+  for (int v = 0; v < NV; ++v) {
+    const int64_t o = (e * NV + v) * Ns + i;
+    in.u0[v] = rk.u0[o];
+    in.acc[v] = rk.first ? T(0) : rk.acc[o];
+  }
+}
+
 // shared epilogue: R at (el, i) for all variables -> rhs output or RK update; the new stage
-// state goes to LDS `lw` ([E][NV][Ns]) when uf_next is requested
+// state goes to `w` (for the flux-point values of the next stage)
 template <int D, int P, typename T>
 __device__ __forceinline__ void rk_epilogue(const T *R, int64_t e, int i, const RKArgs<T> &rk,
-                                            const int32_t *__restrict__ elem_mesh, T *w) {
+                                            const RKIn<T, Shape<D, P>::NV> &in, T *w) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Ns = S::Ns;
   if (rk.r_out) {
     for (int v = 0; v < NV; ++v) rk.r_out[(e * NV + v) * Ns + i] = R[v];
     return;
   }
-  const T dt = (T)rk.dt[elem_mesh[e]];
+  const T dt = (T)rk.dt[in.mesh];
   for (int v = 0; v < NV; ++v) {
     const int64_t o = (e * NV + v) * Ns + i;
     if (rk.r_copy) rk.r_copy[o] = R[v];
-    const T a = rk.first ? T(0) : rk.acc[o];
-    const T u0 = rk.u0[o];
+    const T a = in.acc[v];
+    const T u0 = in.u0[v];
     if (rk.u0_copy) rk.u0_copy[o] = u0;
     if (!rk.last) {
       rk.acc[o] = a + rk.cB * dt * R[v];
@@ -534,19 +564,26 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
-  stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  tile_load(lds, fhat + e0 * NV * Nf, ne * NV * Nf);
-  __syncthreads();
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
   const int64_t e = e0 + el;
+  // the common-flux tile, this point's volume term, 1/J and the RK inputs in one round trip
+  TileLoad<E * NV * Nf, TL::BS, T> tf;
+  tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
+  T R[NV], invJ = T(0);
+  RKIn<T, NV> in;
+  if (act) {
+    invJ = metric[(e * NM + D * D) * Ns + i];
+    for (int v = 0; v < NV; ++v) R[v] = vol[(e * NV + v) * Ns + i];
+    rk_prefetch<D, P>(e, i, rk, elem_mesh, in);
+  }
+  stage_ops(ops, ops_arg);
+  tf.store(lds, ne * NV * Nf);
+  __syncthreads();
   T w[NV];
   if (act) {
-    const T invJ = metric[(e * NM + D * D) * Ns + i];
-    T R[NV];
-    for (int v = 0; v < NV; ++v) R[v] = vol[(e * NV + v) * Ns + i];
     for (int k = 0; k < D; ++k) {
       int base, stride, ik, t;
       line_of_sol<D, P>(i, k, base, stride, ik, t);
@@ -557,7 +594,7 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
       }
     }
     for (int v = 0; v < NV; ++v) R[v] = -invJ * R[v];
-    rk_epilogue<D, P>(R, e, i, rk, elem_mesh, w);
+    rk_epilogue<D, P>(R, e, i, rk, in, w);
   }
   if (rk.uf_next) {
     __syncthreads();
@@ -580,26 +617,33 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
-  stage_ops(ops, ops_arg);
   T *lF = lds;                  // [E][D][NV][Ns]
   T *lf = lds + E * D * NV * Ns;  // [E][NV][Nf]
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  tile_load(lf, fhat + e0 * NV * Nf, ne * NV * Nf);
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
   const int64_t e = e0 + el;
-  T invJ = T(0);
+  // the common-flux tile, this point's state and metric terms and the RK inputs in one round trip
+  TileLoad<E * NV * Nf, TL::BS, T> tf;
+  tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
+  T invJ = T(0), uv[NV], Sm[D][D];
+  RKIn<T, NV> in;
   if (act) {
-    T uv[NV], Sm[D];
     for (int v = 0; v < NV; ++v) uv[v] = u[(e * NV + v) * Ns + i];
+    for (int k = 0; k < D; ++k)
+      for (int j = 0; j < D; ++j) Sm[k][j] = metric[(e * NM + k * D + j) * Ns + i];
+    invJ = metric[(e * NM + D * D) * Ns + i];
+    rk_prefetch<D, P>(e, i, rk, elem_mesh, in);
+  }
+  stage_ops(ops, ops_arg);
+  tf.store(lf, ne * NV * Nf);
+  if (act) {
     for (int k = 0; k < D; ++k) {
-      for (int j = 0; j < D; ++j) Sm[j] = metric[(e * NM + k * D + j) * Ns + i];
       T fi[NV];
-      finv_dot<D>(uv, Sm, ph.gm1, fi);
+      finv_dot<D>(uv, Sm[k], ph.gm1, fi);
       for (int v = 0; v < NV; ++v) lF[((el * D + k) * NV + v) * Ns + i] = fi[v];
     }
-    invJ = metric[(e * NM + D * D) * Ns + i];
   }
   __syncthreads();
   T w[NV];
@@ -620,7 +664,7 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
       }
       R[v] = -invJ * accv;
     }
-    rk_epilogue<D, P>(R, e, i, rk, elem_mesh, w);
+    rk_epilogue<D, P>(R, e, i, rk, in, w);
   }
   if (rk.uf_next) {
     __syncthreads();
