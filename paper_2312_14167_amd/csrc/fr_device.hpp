@@ -146,7 +146,7 @@ __device__ __forceinline__ void fvis_normal_stream(const T *st, const G &gdir, c
 #pragma unroll 1
   for (int d = 0; d < D; ++d) {
     T gd[NV];
-    for (int v = 0; v < NV; ++v) gd[v] = gdir(d, v);
+    gdir(d, gd);
     T sv = T(0), tn = T(0);
     for (int m = 0; m < D; ++m) {
       const T dvdm = (gd[1 + m] - vel[m] * gd[0]) * ir;  // d_d v_m

@@ -318,7 +318,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
     const T invJ = metric_t[(uint32_t)((el * NM + D * D) * Ns + i)];
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) gx[j][v] = T(0);
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < D; ++k) {
       int base, stride, ik, t;
       line_of_sol<D, P>(i, k, base, stride, ik, t);
@@ -343,9 +343,11 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
       for (int v = 0; v < NV; ++v) gx[j][v] *= invJ;
   }
   __syncthreads();
+  // gradient point-major, [E][Ns][D][NV]: the flux-point interpolation reads the D*NV values of
+  // one line point at constant offsets from one address
   if (act)
     for (int j = 0; j < D; ++j)
-      for (int v = 0; v < NV; ++v) lw[((el * D + j) * NV + v) * Ns + i] = gx[j][v];
+      for (int v = 0; v < NV; ++v) lw[(el * Ns + i) * (D * NV) + j * NV + v] = gx[j][v];
   __syncthreads();
   // Flux points of the listed faces: viscous normal flux fvn = F_vis(u_f, M0 grad_x u) . n_out.
   // Two-sided LDG: stored for the face kernel.  One-sided LDG: this point's side alone supplies
@@ -390,13 +392,14 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
     } else {
       for (int v = 0; v < NV; ++v) st[v] = uo[v];
     }
-    const T *lge = lw + elf * D * NV * Ns + base;
-    auto gdir = [&](int d, int v) {
-      const T *lin = lge + (d * NV + v) * Ns;
-      T s = T(0);
+    const T *lge = lw + (elf * Ns + base) * (D * NV);
+    auto gdir = [&](int d, T *gd) {
+      for (int v = 0; v < NV; ++v) gd[v] = T(0);
 #pragma unroll
-      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-      return s;
+      for (int a = 0; a < P; ++a) {
+        const T *row = lge + a * stride * (D * NV) + d * NV;
+        for (int v = 0; v < NV; ++v) gd[v] += lv[a] * row[v];
+      }
     };
     T fv[NV];
     fvis_normal_stream<D>(st, gdir, n, fl.mu, ph, heat, fv);
@@ -430,8 +433,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   if (act) {
     T uv[NV], g[D * NV];
     for (int v = 0; v < NV; ++v) uv[v] = lu[(el * NV + v) * Ns + i];
-    for (int j = 0; j < D; ++j)
-      for (int v = 0; v < NV; ++v) g[j * NV + v] = lw[((el * D + j) * NV + v) * Ns + i];
+    for (int c = 0; c < D * NV; ++c) g[c] = lw[(el * Ns + i) * (D * NV) + c];
     Visc<D, T> vs;
     visc_state<D>(uv, g, flow[s_mesh[el]].mu, ph, true, vs);
     for (int k = 0; k < D; ++k) {
@@ -450,7 +452,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   if (act) {
     T accv[NV];
     for (int v = 0; v < NV; ++v) accv[v] = T(0);
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < D; ++k) {
       int base, stride, ik, t;
       line_of_sol<D, P>(i, k, base, stride, ik, t);
