@@ -268,6 +268,12 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->series = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * s->cap * sizeof(double));
     s->sums = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * 2 * sizeof(double));
     s->force_acc = (double *)dalloc(s, (size_t)n_mesh * s->dim * sizeof(double));
+    {
+      int64_t mx = 0;
+      for (int k = 0; k < n_mesh; ++k) mx = std::max(mx, c.wall_mesh_begin[k + 1] - c.wall_mesh_begin[k]);
+      s->wall_nchunk = (int)std::max<int64_t>(1, (mx + WALL_CHUNK - 1) / WALL_CHUNK);
+      s->wall_partial = (double *)dalloc(s, (size_t)n_mesh * s->wall_nchunk * s->dim * sizeof(double));
+    }
     s->count = (unsigned long long *)dalloc(s, sizeof(unsigned long long));
     s->nonfinite = (int *)dalloc(s, sizeof(int));
     HIP_OK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));

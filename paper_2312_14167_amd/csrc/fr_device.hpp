@@ -173,19 +173,25 @@ __device__ __forceinline__ void fvis_normal_stream(const T *st, const G &gdir, c
 
 template <int D, typename T>
 __device__ __forceinline__ void rusanov(const T *uL, const T *uR, const T *n, T gamma, T gm1, T *F) {
-  constexpr int NV = D + 2;
-  T fL[NV], fR[NV];
-  finv_dot<D>(uL, n, gm1, fL);
-  finv_dot<D>(uR, n, gm1, fR);
-  T rL, vL[D], pL, rR, vR[D], pR;
-  primitives<D>(uL, gm1, rL, vL, pL);
-  primitives<D>(uR, gm1, rR, vR, pR);
-  T vnL = T(0), vnR = T(0);
-  for (int j = 0; j < D; ++j) { vnL += vL[j] * n[j]; vnR += vR[j] * n[j]; }
-  const T aL = fabs(vnL) + sqrt(gamma * pL / rL);
-  const T aR = fabs(vnR) + sqrt(gamma * pR / rR);
+  // primitives once per side; the sound speed reuses the reciprocal density
+  const T irL = T(1) / uL[0], irR = T(1) / uR[0];
+  T vnL = T(0), vnR = T(0), keL = T(0), keR = T(0);
+  for (int j = 0; j < D; ++j) {
+    const T vl = uL[1 + j] * irL, vr = uR[1 + j] * irR;
+    keL += vl * uL[1 + j];
+    keR += vr * uR[1 + j];
+    vnL += vl * n[j];
+    vnR += vr * n[j];
+  }
+  const T pL = gm1 * (uL[D + 1] - T(0.5) * keL), pR = gm1 * (uR[D + 1] - T(0.5) * keR);
+  const T aL = fabs(vnL) + sqrt(gamma * pL * irL);
+  const T aR = fabs(vnR) + sqrt(gamma * pR * irR);
   const T lam = aL >= aR ? aL : aR;
-  for (int v = 0; v < NV; ++v) F[v] = T(0.5) * (fL[v] + fR[v]) - T(0.5) * lam * (uR[v] - uL[v]);
+  F[0] = T(0.5) * (uL[0] * vnL + uR[0] * vnR) - T(0.5) * lam * (uR[0] - uL[0]);
+  for (int i = 0; i < D; ++i)
+    F[1 + i] = T(0.5) * ((uL[1 + i] * vnL + pL * n[i]) + (uR[1 + i] * vnR + pR * n[i])) -
+               T(0.5) * lam * (uR[1 + i] - uL[1 + i]);
+  F[D + 1] = T(0.5) * ((uL[D + 1] + pL) * vnL + (uR[D + 1] + pR) * vnR) - T(0.5) * lam * (uR[D + 1] - uL[D + 1]);
 }
 
 // Riemann-invariant far-field state

@@ -719,40 +719,51 @@ __global__ __launch_bounds__(256) void k_probe(const T *__restrict__ u, const in
 }
 
 // wall force per mesh (FP64): sum over wall flux points of w |N| (p n - tau n), tau n being the
-// momentum part of the wall viscous normal flux; one workgroup per mesh, fixed reduction order
+// momentum part of the wall viscous normal flux.  Workgroup (chunk c, mesh m) sums the chunk's
+// WALL_CHUNK points in a fixed tree into partial[m][c]; k_wall_force_sum adds the chunks of a mesh
+// in order (deterministic, no atomics).
 template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void k_wall_force(const T *__restrict__ uf, const T *__restrict__ fvn,
-                                                    const int32_t *__restrict__ bnd, const T *__restrict__ bnrm,
-                                                    const double *__restrict__ bw,
-                                                    const int64_t *__restrict__ wall_begin, PhysDev<T> ph,
-                                                    double *force_acc) {
+__global__ __launch_bounds__(WALL_CHUNK) void k_wall_force(const T *__restrict__ uf, const T *__restrict__ fvn,
+                                                           const int32_t *__restrict__ bnd,
+                                                           const T *__restrict__ bnrm, const double *__restrict__ bw,
+                                                           const int64_t *__restrict__ wall_begin, PhysDev<T> ph,
+                                                           int nchunk, double *__restrict__ partial) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Nf = S::Nf;
-  __shared__ double red[256][D];
-  const int m = blockIdx.x;
+  __shared__ double red[WALL_CHUNK][D];
+  const int m = blockIdx.y, c = blockIdx.x;
+  const int64_t b = wall_begin[m] + (int64_t)c * WALL_CHUNK + threadIdx.x;
   double f[D];
   for (int j = 0; j < D; ++j) f[j] = 0.0;
-  for (int64_t b = wall_begin[m] + threadIdx.x; b < wall_begin[m + 1]; b += blockDim.x) {
-    const int32_t c = bnd[b];
-    const int64_t e = c / Nf;
-    const int fp = c % Nf;
+  if (b < wall_begin[m + 1]) {
+    const int32_t code = bnd[b];
+    const int64_t e = code / Nf;
+    const int fp = code % Nf;
     T uB[NV];
     for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
     T rho, vel[D], p;
     primitives<D>(uB, ph.gm1, rho, vel, p);
     const double wm = bw[b] * (double)bnrm[b * (D + 1) + D];
     for (int j = 0; j < D; ++j)
-      f[j] += wm * ((double)p * (double)bnrm[b * (D + 1) + j] - (double)fvn[(e * NV + 1 + j) * Nf + fp]);
+      f[j] = wm * ((double)p * (double)bnrm[b * (D + 1) + j] - (double)fvn[(e * NV + 1 + j) * Nf + fp]);
   }
   for (int j = 0; j < D; ++j) red[threadIdx.x][j] = f[j];
   __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+  for (int st = WALL_CHUNK / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
       for (int j = 0; j < D; ++j) red[threadIdx.x][j] += red[threadIdx.x + st][j];
     __syncthreads();
   }
-  if (threadIdx.x == 0)
-    for (int j = 0; j < D; ++j) force_acc[m * D + j] += red[0][j];
+  if (threadIdx.x < D) partial[((int64_t)m * nchunk + c) * D + threadIdx.x] = red[0][threadIdx.x];
+}
+
+template <int D>
+__global__ void k_wall_force_sum(const double *__restrict__ partial, int nchunk, double *force_acc) {
+  const int m = blockIdx.x, j = threadIdx.x;
+  if (j >= D) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[((int64_t)m * nchunk + c) * D + j];
+  force_acc[m * D + j] += s;
 }
 
 // adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du (one workgroup, probes in order)
@@ -954,8 +965,10 @@ struct Engine {
       }
       if (force_sample && s->forces && s->n_wall > 0) {
         ProfScope ps(s, 7, st);
-        k_wall_force<D, P, T><<<s->n_mesh, 256, 0, st>>>(uf, fvn, s->bnd, (const T *)s->bnd_nrm, s->bnd_w,
-                                                          s->wall_mesh_begin, ph, s->force_acc);
+        k_wall_force<D, P, T><<<dim3((unsigned)s->wall_nchunk, (unsigned)s->n_mesh), WALL_CHUNK, 0, st>>>(
+            uf, fvn, s->bnd, (const T *)s->bnd_nrm, s->bnd_w, s->wall_mesh_begin, ph, s->wall_nchunk,
+            s->wall_partial);
+        k_wall_force_sum<D><<<s->n_mesh, 64, 0, st>>>(s->wall_partial, s->wall_nchunk, s->force_acc);
       }
       if (ph.side == 0) {  // one-sided LDG: the common flux was formed inside k_ns_grad
         ProfScope ps(s, 3, st);

@@ -10,6 +10,8 @@
 
 namespace frmi {
 
+constexpr int WALL_CHUNK = 256;  // wall flux points per workgroup of the wall-force sum
+
 // per-mesh free stream and viscosity in the state precision
 template <typename T>
 struct FlowDev {
@@ -102,6 +104,8 @@ struct fr_solver {
   double *series = nullptr;       // [n_probe][cap]
   double *sums = nullptr;         // [n_probe][2]
   double *force_acc = nullptr;    // [n_mesh][dim]
+  int wall_nchunk = 0;            // wall-force partial sums per mesh (chunks of WALL_CHUNK points)
+  double *wall_partial = nullptr; // [n_mesh][wall_nchunk][dim]
   unsigned long long *count = nullptr;  // samples taken
   int *nonfinite = nullptr;
 
