@@ -368,23 +368,33 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
   __shared__ __attribute__((aligned(16))) T lw[E * TL::LE];
   __shared__ __attribute__((aligned(16))) T lu[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
-  stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  const int64_t e = e0 + el;
+  // the state tile and this point's operands in one round trip
+  TileLoad<E * NV * Ns, TL::BS, T> tu;
+  tu.load(u + e0 * NV * Ns, ne * NV * Ns);
+  T invJ = T(0), rb[NV], rf[NV], gprev = T(0);
   if (el < ne) {
-    const int64_t e = e0 + el;
-    const T invJ = metric[(e * NM + D * D) * Ns + i];
+    invJ = metric[(e * NM + D * D) * Ns + i];
+    for (int v = 0; v < NV; ++v) {
+      rb[v] = rbar[(e * NV + v) * Ns + i];
+      if (GEO) rf[v] = Rf[(e * NV + v) * Ns + i];
+    }
+    if (GEO) gprev = Gm[(e * NM + D * D) * Ns + i];
+  }
+  stage_ops(ops, ops_arg);
+  tu.store(lu, ne * NV * Ns);
+  if (el < ne) {
     T gj = T(0);
     for (int v = 0; v < NV; ++v) {
-      const T rb = rbar[(e * NV + v) * Ns + i];
-      const T w = -invJ * rb;
+      const T w = -invJ * rb[v];
       lw[(el * NV + v) * Ns + i] = w;
       volbar[(e * NV + v) * Ns + i] = w;
-      if (GEO) gj += rb * Rf[(e * NV + v) * Ns + i];
+      if (GEO) gj += rb[v] * rf[v];
     }
-    if (GEO) Gm[(e * NM + D * D) * Ns + i] += gj / invJ;
+    if (GEO) Gm[(e * NM + D * D) * Ns + i] = gprev + gj / invJ;
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) {
@@ -539,7 +549,6 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
-  stage_ops(ops, ops_arg);
   T *lA = lds;
   T *luf = lds + E * TL::LA;             // [E][NV][Nf]
   T *lvb = luf + E * NV * Nf;            // [E][NV][Ns]
@@ -548,8 +557,15 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
   T *ldu = lA + E * NV * Ns;             // [E][NV][Nf]
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  tile_load(lu, u + e0 * NV * Ns, ne * NV * Ns);
-  tile_load(lvb, volbar + e0 * NV * Ns, ne * NV * Ns);
+  {
+    // both tiles in one round trip
+    TileLoad<E * NV * Ns, TL::BS, T> tu, tv;
+    tu.load(u + e0 * NV * Ns, ne * NV * Ns);
+    tv.load(volbar + e0 * NV * Ns, ne * NV * Ns);
+    stage_ops(ops, ops_arg);
+    tu.store(lu, ne * NV * Ns);
+    tv.store(lvb, ne * NV * Ns);
+  }
   __syncthreads();
   const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
   // own u_f, LDG common solution, u^ - u_f (forward recompute)
@@ -860,19 +876,22 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_euler_vol(con
   constexpr int E = TL::E, Ns = S::Ns, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lvb[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
-  stage_ops(ops, ops_arg);
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
-  tile_load(lvb, volbar + e0 * NV * Ns, ne * NV * Ns);
-  __syncthreads();
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
-  if (el >= ne) return;
   const int64_t e = e0 + el;
+  // the adjoint tile and this point's state in one round trip
+  TileLoad<E * NV * Ns, TL::BS, T> tv;
+  tv.load(volbar + e0 * NV * Ns, ne * NV * Ns);
   T uv[NV], ubs[NV];
   for (int v = 0; v < NV; ++v) {
-    uv[v] = u[(e * NV + v) * Ns + i];
+    uv[v] = el < ne ? u[(e * NV + v) * Ns + i] : T(0);
     ubs[v] = T(0);
   }
+  stage_ops(ops, ops_arg);
+  tv.store(lvb, ne * NV * Ns);
+  __syncthreads();
+  if (el >= ne) return;
   for (int k = 0; k < D; ++k) {
     T Sk[D];
     for (int j = 0; j < D; ++j) Sk[j] = metric[(e * NM + k * D + j) * Ns + i];
