@@ -281,8 +281,4 @@ __device__ __forceinline__ void wall_state(const T *uB, T *uw) {
   uw[D + 1] = uB[D + 1] - T(0.5) * ke / uB[0];
 }
 
-// element flux-point neighbour code: >= 0 -> partner (element * Nf + flux point), bit 30 set when
-// this element is the R side of the pair; < 0 -> boundary point -(code + 1)
-constexpr int32_t NBR_R_BIT = 1 << 30;
-
 }  // namespace frmi

@@ -457,11 +457,10 @@ Connectivity build_connectivity(const MeshIn &m, const Ops1D &o, const Geometry 
   // element-side view of the same connectivity
   c.nbr.assign((size_t)Ne * Nf, INT32_MIN);
   c.fnrm.assign((size_t)Ne * (d + 1) * Nf, 0.0);
-  const int32_t RBIT = 1 << 30;
   for (size_t q = 0; q < c.pairL.size(); ++q) {
     const int32_t L = c.pairL[q], R = c.pairR[q];
     c.nbr[L] = R;
-    c.nbr[R] = L | RBIT;
+    c.nbr[R] = L | NBR_R_BIT;
     const int64_t eL = L / Nf, eR = R / Nf;
     const int fL = L % Nf, fR = R % Nf;
     for (int j = 0; j <= d; ++j) {

@@ -8,6 +8,10 @@
 
 namespace frmi {
 
+// element flux-point neighbour code: >= 0 -> partner (element * Nf + flux point), bit 30 set when
+// this element is the R side of the pair; < 0 -> boundary point -(code + 1)
+constexpr int32_t NBR_R_BIT = 1 << 30;
+
 // Thrown by host construction; mapped to an fr_status at the ABI.
 struct FrError : std::runtime_error {
   int code;
