@@ -152,6 +152,36 @@ def test_ragged_tiles_and_single_element(gpu):
         assert rel_l2(R, s.residual(u0)) <= 1e-11
 
 
+@pytest.mark.parametrize("shape", [(3, 1, 1), (1, 3, 1), (3, 3, 1)])
+def test_ragged_tiles_3d_p4_channel(shape, gpu):
+    """3-D p = 4 (the headline element type) with odd element counts, so the last workgroup of the
+    NS volume kernel (2 elements per tile in FP64) and of the lifting + RK kernel is partial; walls
+    at the y bounds exercise the boundary flux points and the chunked wall-force sum.  Residual and
+    one RK4 step with force sampling against the oracle."""
+    import fr_inputs as fi
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m = fi.periodic_box(3, shape, q=2, curv=0.1, bc="channel", seed=5)
+    fp = fi.freestream_params(3, 0.3, 100.0, aoa_deg=20.0)
+    s = OracleSystem(m, 4, fp, equations="ns")
+    x = s.solpt_coords()
+    u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (5,), 7, 0.01)).permute(0, 2, 1)
+    u0 = u0.contiguous()
+    sol = Solver(m, 4, fp, equations="ns", forces=True, probes=[[0.1, 0.2, 0.3]], max_samples=4)
+    R = sol.rhs(u0.to(gpu))
+    assert rel_l2(R, s.residual(u0)) <= 1e-11
+    dt = np.array([1e-3])
+    u = u0.to(gpu).clone()
+    sol.reset_accumulators()
+    sol.rk_step(u, torch.tensor(dt, dtype=torch.float64, device=gpu), 1, sample_every=1)
+    uref, P, F = s.run(u0, torch.tensor(dt), 1, sample_every=1)
+    torch.cuda.synchronize()
+    assert rel_l2(u, uref) <= 1e-12
+    st = sol.probe_oaspl(p_ref=2e-5)
+    Fm = F.numpy().mean(axis=0)
+    np.testing.assert_allclose(st["mean_force"], Fm, rtol=0, atol=1e-10 * max(float(np.abs(Fm).max()), 1e-3))
+
+
 @pytest.mark.parametrize("name", ["ns_ogrid", "euler_vortex", "ns_cgrid_p4"])
 def test_autotuned_tiles_give_the_same_step(name, gpu):
     """Every candidate tile size of the autotuner computes the same RK4 step (the tile only
