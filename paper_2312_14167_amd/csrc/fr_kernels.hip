@@ -193,41 +193,49 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   T *lu = lds;                // [E][NV][Ns]
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][D][NV][Ns] gradient / F~
   int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
+  const int side = ph.side;
   // the state, the neighbour codes and the mesh indices arrive in one round trip, so the first
-  // flux-point phase starts its neighbour gathers without another one
+  // flux-point phase starts its neighbour gathers without another one; wave 0 also requests the
+  // code of every face of the tile (its first flux point) for the face list below
+  constexpr int KF = (E * NFACE + 63) / 64;  // faces per lane of wave 0
+  int32_t fcode[KF];
   {
     TileLoad<E * NV * Ns, TL::BS, T> tu;
     TileLoad<E * Nf, TL::BS, int32_t> tc;
     tu.load(u + e0 * NV * Ns, ne * NV * Ns);
     tc.load(nbr_t, ne * Nf);
+    if (threadIdx.x < 64) {
+#pragma unroll
+      for (int k = 0; k < KF; ++k) {
+        const int fi = k * 64 + (int)threadIdx.x;
+        fcode[k] = fi < ne * NFACE ? nbr_t[(uint32_t)((fi / NFACE) * Nf + (fi % NFACE) * Nfp)] : 0;
+      }
+    }
     const int mesh = (int)threadIdx.x < ne ? elem_mesh[e0 + threadIdx.x] : 0;
     stage_ops(ops, ops_arg);
     tu.store(lu, ne * NV * Ns);
     tc.store(lcode, ne * Nf);
     if ((int)threadIdx.x < ne) s_mesh[threadIdx.x] = mesh;
   }
-  __syncthreads();
-  const int side = ph.side;
   // faces of the tile ordered with those whose viscous normal flux is consumed (boundary faces,
   // and interior faces on the flux side; every flux point of a face shares its partner face and
   // its side) at the front, s_nface of them, the others behind; the flux-point phases walk this
   // order, so that the waves doing flux-side work (neighbour gather, Rusanov) are not split with
-  // the others
+  // the others.  Built by wave 0 before the first barrier.
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
+    const unsigned long long below = (1ull << lane) - 1ull;
     int cnt = 0, rest = 0;
-    for (int b = 0; b < ne * NFACE; b += 64) {
-      const int fi = b + lane;
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+      const int fi = k * 64 + lane;
       const bool in = fi < ne * NFACE;
-      bool need = false;
-      if (in) {
-        const int32_t code = lcode[(fi / NFACE) * Nf + (fi % NFACE) * Nfp];
-        need = code < 0 || side == 0 || (((code & NBR_R_BIT) != 0) == (side > 0));
-      }
-      const unsigned long long below = (1ull << lane) - 1ull;
-      const unsigned long long m = __ballot(in && need), mo = __ballot(in && !need);
-      if (in && need) s_face[cnt + __popcll(m & below)] = fi;
-      if (in && !need) s_face[ne * NFACE - 1 - rest - __popcll(mo & below)] = fi;
+      const int32_t code = fcode[k];
+      const bool need = in && (code < 0 || side == 0 || (((code & NBR_R_BIT) != 0) == (side > 0)));
+      const bool other = in && !need;
+      const unsigned long long m = __ballot(need), mo = __ballot(other);
+      if (need) s_face[cnt + __popcll(m & below)] = fi;
+      if (other) s_face[ne * NFACE - 1 - rest - __popcll(mo & below)] = fi;
       cnt += __popcll(m);
       rest += __popcll(mo);
     }
