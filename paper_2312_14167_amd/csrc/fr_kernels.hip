@@ -33,27 +33,6 @@
 namespace frmi {
 
 // ------------------------------------------------------------------------------------ kernels
-// u_f = M0 u for every (element, flux point)
-template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void k_interp(const T *__restrict__ u, T *__restrict__ uf, OpsDev<T, P> ops,
-                                                int64_t Ne) {
-  using S = Shape<D, P>;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= Ne * S::Nf) return;
-  const int64_t e = gid / S::Nf;
-  const int fp = (int)(gid % S::Nf);
-  int base, stride, side;
-  line_of_fpt<D, P>(fp, base, stride, side);
-  const T *lv = side ? ops.lp : ops.lm;
-  for (int v = 0; v < S::NV; ++v) {
-    const T *ue = u + (e * S::NV + v) * S::Ns + base;
-    T s = T(0);
-#pragma unroll
-    for (int a = 0; a < P; ++a) s += lv[a] * ue[a * stride];
-    uf[(e * S::NV + v) * S::Nf + fp] = s;
-  }
-}
-
 // common normal flux x |N| at every flux point.  Inviscid: Rusanov with the neighbour state or
 // the boundary ghost.  NS: minus the LDG viscous flux assembled from the per-side viscous normal
 // fluxes fvn (each side's F_vis(u, grad u) . n_out, boundary points already in boundary form).
@@ -563,6 +542,26 @@ __device__ __forceinline__ void tile_interp(const T *lw, int ne, const OpsDev<T,
   }
 }
 
+// u_f = M0 u, E elements per workgroup: the state tile is staged in LDS (contiguous loads, one
+// round trip) and every flux-point value is written once, contiguously
+template <int D, int P, typename T>
+__global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_interp(const T *__restrict__ u, T *__restrict__ uf,
+                                                                   OpsDev<T, P> ops_arg, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = DivTile<D, P, T>;
+  constexpr int E = TL::E, NV = S::NV, Ns = S::Ns, Nf = S::Nf;
+  __shared__ __attribute__((aligned(16))) T lu[E * NV * Ns];
+  __shared__ OpsDev<T, P> ops;
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  TileLoad<E * NV * Ns, TL::BS, T> tu;
+  tu.load(u + e0 * NV * Ns, ne * NV * Ns);
+  stage_ops(ops, ops_arg);
+  tu.store(lu, ne * NV * Ns);
+  __syncthreads();
+  tile_interp<D, P>(lu, ne, ops, uf + e0 * NV * Nf);
+}
+
 // NS: R = -(1/J)(vol + Lift F^), RK update, u_f of the new stage state
 template <int D, int P, typename T, int EE>
 __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *__restrict__ vol, const T *__restrict__ fhat,
@@ -945,7 +944,8 @@ struct Engine {
 
   static void interp(const fr_solver *s, const T *u, T *uf, hipStream_t st) {
     ProfScope ps(s, 0, st);
-    k_interp<D, P, T><<<nblk(s->Ne * S::Nf, 256), 256, 0, st>>>(u, uf, ops(s), s->Ne);
+    using TL = DivTile<D, P, T>;
+    k_interp<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, uf, ops(s), s->Ne);
   }
 
   // one residual evaluation of `u` whose flux-point values are already in s->uf; the epilogue
