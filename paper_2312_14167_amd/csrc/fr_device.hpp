@@ -256,21 +256,6 @@ struct TileLoad {
   }
 };
 
-// contiguous tile copy global -> LDS, 16-byte vector accesses when both sides allow it
-template <typename T>
-__device__ __forceinline__ void tile_load(T *__restrict__ dst, const T *__restrict__ src, int n) {
-  constexpr int W = 16 / sizeof(T);
-  if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
-    const int nv = n / W;
-    const float4 *s4 = reinterpret_cast<const float4 *>(src);
-    float4 *d4 = reinterpret_cast<float4 *>(dst);
-    for (int idx = threadIdx.x; idx < nv; idx += blockDim.x) d4[idx] = s4[idx];
-    for (int idx = nv * W + threadIdx.x; idx < n; idx += blockDim.x) dst[idx] = src[idx];
-  } else {
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) dst[idx] = src[idx];
-  }
-}
-
 // no-slip wall state: zero velocity, same density and internal energy
 template <int D, typename T>
 __device__ __forceinline__ void wall_state(const T *uB, T *uw) {

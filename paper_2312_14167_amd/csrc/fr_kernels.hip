@@ -109,8 +109,8 @@ struct GradTile {
   using S = Shape<D, P>;
   // per element: the state [NV][Ns], kept to the flux-point viscous phase, then one region that
   // holds u^ - u_f [NV][Nf] (with the tile's neighbour codes [Nf] behind all elements' u^ - u_f),
-  // the physical gradient [D][NV][Ns] and the transformed flux [D][NV][Ns] in turn.  The default
-  // E fits four workgroups in 160 KB of LDS.
+  // the physical gradient point-major [Ns][D][NV] and the transformed flux [D][NV][Ns] in turn.
+  // The default E fits four workgroups in 160 KB of LDS.
   static constexpr int LU = S::NV * S::Ns;
   static constexpr int LC = (S::Nf * (int)sizeof(int32_t) + (int)sizeof(T) - 1) / (int)sizeof(T);
   static constexpr int LG = cmax(S::NV * S::Nf + LC, D * S::NV * S::Ns);
@@ -170,7 +170,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
   const T *fnrm_t = fnrm + e0 * (D + 1) * Nf, *metric_t = metric + e0 * NM * Ns;
   T *fvn_t = fvn + e0 * NV * Nf, *fhat_t = fhat + e0 * NV * Nf, *vol_t = vol + e0 * NV * Ns;
   T *lu = lds;                // [E][NV][Ns]
-  T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][D][NV][Ns] gradient / F~
+  T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][Ns][D][NV] gradient; [E][D][NV][Ns] F~
   int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
   const int side = ph.side;
   // the state, the neighbour codes and the mesh indices arrive in one round trip, so the first
