@@ -389,8 +389,8 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "reps": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build runs one process on one MI355X "
-              f"(got --gpus {args.gpus}); multi-GPU sharding is described, not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the path runs as one process on one "
+              f"MI355X; sharding across GPUs is not run.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -163,3 +163,15 @@ def test_host_statistics_argument_errors():
     grp = np.array([0, 2], dtype=np.int32)
     two = np.ones((2, 10))
     assert L.fr_stats_observer_oaspl(_dp(two), 2, 10, _dp(grp), 2, 1.0, _dp(out), _dp(out)) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asking for more exits non-zero with a message that says so
+    (before touching a GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=300, cwd=root)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr or "1 GPU" in r.stderr, r.stderr
