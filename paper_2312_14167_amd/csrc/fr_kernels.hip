@@ -684,45 +684,44 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   }
 }
 
-// probe pressure samples (FP64): one workgroup handles every probe in a fixed order
+// probe pressure samples (FP64): one workgroup per probe, the weighted sum over the element's
+// solution points reduced in a fixed tree; the sample counter is advanced afterwards by
+// k_probe_count, so every workgroup of a sample reads the same index
+constexpr int PROBE_BS = 128;  // >= Ns for p <= 4
 template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void k_probe(const T *__restrict__ u, const int64_t *__restrict__ pelem,
-                                               const double *__restrict__ pw, const double *__restrict__ pinf,
-                                               int n_probe, double gm1, double *series, int cap, double *sums,
-                                               unsigned long long *count, int *nonfinite) {
+__global__ __launch_bounds__(PROBE_BS) void k_probe(const T *__restrict__ u, const int64_t *__restrict__ pelem,
+                                                    const double *__restrict__ pw, const double *__restrict__ pinf,
+                                                    double gm1, double *series, int cap, double *sums,
+                                                    const unsigned long long *__restrict__ count, int *nonfinite) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Ns = S::Ns;
-  __shared__ double red[256];
-  __shared__ double uval[NV];
-  const unsigned long long n = *count;
-  for (int a = 0; a < n_probe; ++a) {
-    const int64_t e = pelem[a];
-    for (int v = 0; v < NV; ++v) {
-      double s = 0.0;
-      for (int i = threadIdx.x; i < Ns; i += blockDim.x)
-        s += pw[(int64_t)a * Ns + i] * (double)u[(e * NV + v) * Ns + i];
-      red[threadIdx.x] = s;
-      __syncthreads();
-      for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) uval[v] = red[0];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      double ke = 0.0;
-      for (int j = 0; j < D; ++j) ke += uval[1 + j] * uval[1 + j];
-      const double p = gm1 * (uval[D + 1] - 0.5 * ke / uval[0]);
-      if (n < (unsigned long long)cap) series[(int64_t)a * cap + (int64_t)n] = p;
-      const double dp = p - pinf[a];
-      sums[2 * a] += dp;
-      sums[2 * a + 1] += dp * dp;
-      if (!isfinite(p)) *nonfinite = 1;
-    }
+  static_assert(Ns <= PROBE_BS, "one solution point per thread");
+  __shared__ double red[NV][PROBE_BS];
+  const int a = blockIdx.x, i = threadIdx.x;
+  const int64_t e = pelem[a];
+  const double w = i < Ns ? pw[(int64_t)a * Ns + i] : 0.0;
+  for (int v = 0; v < NV; ++v) red[v][i] = i < Ns ? w * (double)u[(e * NV + v) * Ns + i] : 0.0;
+  __syncthreads();
+  for (int st = PROBE_BS / 2; st > 0; st >>= 1) {
+    if (i < st)
+      for (int v = 0; v < NV; ++v) red[v][i] += red[v][i + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *count = n + 1;
+  if (i == 0) {
+    const unsigned long long n = *count;
+    double ke = 0.0;
+    for (int j = 0; j < D; ++j) ke += red[1 + j][0] * red[1 + j][0];
+    const double p = gm1 * (red[D + 1][0] - 0.5 * ke / red[0][0]);
+    if (n < (unsigned long long)cap) series[(int64_t)a * cap + (int64_t)n] = p;
+    const double dp = p - pinf[a];
+    sums[2 * a] += dp;
+    sums[2 * a + 1] += dp * dp;
+    if (!isfinite(p)) *nonfinite = 1;
+  }
+}
+
+__global__ void k_probe_count(unsigned long long *count) {
+  if (threadIdx.x == 0) *count += 1;
 }
 
 // wall force per mesh (FP64): sum over wall flux points of w |N| (p n - tau n), tau n being the
@@ -1020,8 +1019,11 @@ struct Engine {
 
   static void probe(const fr_solver *s, const T *u, hipStream_t st) {
     ProfScope ps(s, 6, st);
-    k_probe<D, P, T><<<1, 256, 0, st>>>(u, s->probe_elem, s->probe_w, s->probe_pinf, s->n_probe, s->gamma - 1.0,
-                                        s->series, s->cap, s->sums, s->count, s->nonfinite);
+    if (s->n_probe > 0)
+      k_probe<D, P, T><<<(unsigned)s->n_probe, PROBE_BS, 0, st>>>(u, s->probe_elem, s->probe_w, s->probe_pinf,
+                                                                   s->gamma - 1.0, s->series, s->cap, s->sums,
+                                                                   s->count, s->nonfinite);
+    k_probe_count<<<1, 64, 0, st>>>(s->count);
   }
 
   // one classical RK4 step of u in place; `fresh`: s->uf does not hold u_f of u yet (first step
