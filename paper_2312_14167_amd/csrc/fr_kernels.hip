@@ -763,13 +763,24 @@ __global__ __launch_bounds__(WALL_CHUNK) void k_wall_force(const T *__restrict__
   if (threadIdx.x < D) partial[((int64_t)m * nchunk + c) * D + threadIdx.x] = red[0][threadIdx.x];
 }
 
+// lane l of the 64 sums chunks l, l + 64, ... in order, then a fixed tree over the lanes
 template <int D>
-__global__ void k_wall_force_sum(const double *__restrict__ partial, int nchunk, double *force_acc) {
-  const int m = blockIdx.x, j = threadIdx.x;
-  if (j >= D) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += partial[((int64_t)m * nchunk + c) * D + j];
-  force_acc[m * D + j] += s;
+__global__ __launch_bounds__(64) void k_wall_force_sum(const double *__restrict__ partial, int nchunk,
+                                                       double *force_acc) {
+  __shared__ double red[64][D];
+  const int m = blockIdx.x, l = threadIdx.x;
+  double s[D];
+  for (int j = 0; j < D; ++j) s[j] = 0.0;
+  for (int c = l; c < nchunk; c += 64)
+    for (int j = 0; j < D; ++j) s[j] += partial[((int64_t)m * nchunk + c) * D + j];
+  for (int j = 0; j < D; ++j) red[l][j] = s[j];
+  __syncthreads();
+  for (int st = 32; st > 0; st >>= 1) {
+    if (l < st)
+      for (int j = 0; j < D; ++j) red[l][j] += red[l + st][j];
+    __syncthreads();
+  }
+  if (l < D) force_acc[m * D + l] += red[0][l];
 }
 
 // adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du (one workgroup, probes in order)
