@@ -152,12 +152,14 @@ def test_ragged_tiles_and_single_element(gpu):
         assert rel_l2(R, s.residual(u0)) <= 1e-11
 
 
-@pytest.mark.parametrize("shape", [(3, 1, 1), (1, 3, 1), (3, 3, 1)])
-def test_ragged_tiles_3d_p4_channel(shape, gpu):
+@pytest.mark.parametrize("shape,probes", [((3, 1, 1), True), ((1, 3, 1), True), ((3, 3, 1), True),
+                                          ((3, 3, 1), False)])
+def test_ragged_tiles_3d_p4_channel(shape, probes, gpu):
     """3-D p = 4 (the headline element type) with odd element counts, so the last workgroup of the
     NS volume kernel (2 elements per tile in FP64) and of the lifting + RK kernel is partial; walls
     at the y bounds exercise the boundary flux points and the chunked wall-force sum.  Residual and
-    one RK4 step with force sampling against the oracle."""
+    one RK4 step with force sampling against the oracle; without probes the sample count (which
+    divides the force sum) still advances."""
     import fr_inputs as fi
     from oracle import OracleSystem
     from paper_2312_14167_amd import Solver
@@ -167,7 +169,8 @@ def test_ragged_tiles_3d_p4_channel(shape, gpu):
     x = s.solpt_coords()
     u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (5,), 7, 0.01)).permute(0, 2, 1)
     u0 = u0.contiguous()
-    sol = Solver(m, 4, fp, equations="ns", forces=True, probes=[[0.1, 0.2, 0.3]], max_samples=4)
+    sol = Solver(m, 4, fp, equations="ns", forces=True, probes=[[0.1, 0.2, 0.3]] if probes else None,
+                 max_samples=4)
     R = sol.rhs(u0.to(gpu))
     assert rel_l2(R, s.residual(u0)) <= 1e-11
     dt = np.array([1e-3])
@@ -178,6 +181,7 @@ def test_ragged_tiles_3d_p4_channel(shape, gpu):
     torch.cuda.synchronize()
     assert rel_l2(u, uref) <= 1e-12
     st = sol.probe_oaspl(p_ref=2e-5)
+    assert st["n_samples"] == 1
     Fm = F.numpy().mean(axis=0)
     np.testing.assert_allclose(st["mean_force"], Fm, rtol=0, atol=1e-10 * max(float(np.abs(Fm).max()), 1e-3))
 
