@@ -230,12 +230,18 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
     line_of_fpt<D, P>(fp, base, stride, fs);
     const T *lv = fs ? ops.lp : ops.lm;
     T uo[NV], uh[NV];
-    for (int v = 0; v < NV; ++v) {
-      const T *lin = lu + (el * NV + v) * Ns + base;
-      T s = T(0);
+    {
+      // every line value is requested before the first product (the reads overlap)
+      T val[NV][P];
+      for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-      uo[v] = s;
+        for (int a = 0; a < P; ++a) val[v][a] = lu[(el * NV + v) * Ns + base + a * stride];
+      for (int v = 0; v < NV; ++v) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) s += lv[a] * val[v][a];
+        uo[v] = s;
+      }
     }
     const int32_t code = lcode[el * Nf + fp];
     if (code >= 0) {
@@ -350,12 +356,17 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
     line_of_fpt<D, P>(fp, base, stride, fs);
     const T *lv = fs ? ops.lp : ops.lm;
     T uo[NV], st[NV], n[D];
-    for (int v = 0; v < NV; ++v) {
-      const T *lin = lu + (elf * NV + v) * Ns + base;
-      T s = T(0);
+    {
+      T val[NV][P];  // every line value requested before the first product
+      for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-      uo[v] = s;
+        for (int a = 0; a < P; ++a) val[v][a] = lu[(elf * NV + v) * Ns + base + a * stride];
+      for (int v = 0; v < NV; ++v) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) s += lv[a] * val[v][a];
+        uo[v] = s;
+      }
     }
     for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((elf * (D + 1) + j) * Nf + fp)];
     const int32_t code = nbr_t[(uint32_t)(elf * Nf + fp)];
