@@ -117,6 +117,8 @@ struct GradTile {
   static constexpr int LE = LU + LG;
   static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
+  // register budget (launch bound, waves per SIMD): 4 (128 VGPRs) in FP64, 6 (80 VGPRs) in FP32
+  static constexpr int MIN_WAVES = sizeof(T) == 4 ? 6 : 4;
 };
 
 template <int D, int P, typename T, int EE = 0>
@@ -150,7 +152,7 @@ struct TileCands {
 //   vol = sum_k D~_k F~_k with D~ = D - (interior part of the correction), i.e.
 //   vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}).
 template <int D, int P, typename T, int EE>
-__global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), 4) void k_ns_grad(
+__global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>::MIN_WAVES)) void k_ns_grad(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
     const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, T *__restrict__ fvn,
