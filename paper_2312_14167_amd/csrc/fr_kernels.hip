@@ -117,8 +117,8 @@ struct GradTile {
   static constexpr int LE = LU + LG;
   static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
-  // register budget (launch bound, waves per SIMD): 4 (128 VGPRs) in FP64, 6 (80 VGPRs) in FP32
-  static constexpr int MIN_WAVES = sizeof(T) == 4 ? 6 : 4;
+  // register budget (launch bound, waves per SIMD): 4 (128 VGPRs) in FP64, 7 (72 VGPRs) in FP32
+  static constexpr int MIN_WAVES = sizeof(T) == 4 ? 7 : 4;
 };
 
 template <int D, int P, typename T, int EE = 0>
