@@ -169,3 +169,27 @@ def test_probe_vjp_node_adjoint_matches_oracle(name, gpu):
     err = float((xb.cpu() - ref).norm() / ref.norm())
     print(f"{name}: probe node adjoint rel L2 {err:.3e}")
     assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("dim,eq,bc", [(2, "ns", "channel"), (3, "ns", "channel"), (2, "euler", "periodic")])
+def test_rhs_vjp_degree_one(dim, eq, bc, gpu):
+    """The residual's VJP at p = 1 (smallest tiles of the reverse kernels) against the oracle's
+    autograd, with walls in the NS cases."""
+    import fr_inputs as fi
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m = fi.periodic_box(dim, (7, 5) if dim == 2 else (3, 3, 2), q=1, bc=bc, seed=6)
+    fp = fi.freestream_params(dim, 0.3, 100.0 if eq == "ns" else None, aoa_deg=25.0)
+    s = OracleSystem(m, 1, fp, equations=eq)
+    x = s.solpt_coords()
+    u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (dim + 2,), 4, 0.01))
+    u0 = u0.permute(0, 2, 1).contiguous()
+    rbar = torch.tensor(np.random.default_rng(37).normal(size=u0.shape))
+    ref = _oracle_vjp(s, u0, rbar)
+    sol = Solver(m, 1, fp, equations=eq)
+    ub = torch.zeros_like(u0).to(gpu)
+    sol.rhs_vjp(u0.to(gpu), rbar.to(gpu), ub)
+    torch.cuda.synchronize()
+    err = rel_l2(ub, ref)
+    print(f"p=1 {dim}-D {eq}: vjp fp64 rel L2 {err:.3e}")
+    assert err <= 1e-10, err
