@@ -193,3 +193,10 @@ def test_rhs_vjp_degree_one(dim, eq, bc, gpu):
     err = rel_l2(ub, ref)
     print(f"p=1 {dim}-D {eq}: vjp fp64 rel L2 {err:.3e}")
     assert err <= 1e-10, err
+    # mesh-node adjoint (geometry degree 1) against autograd through the oracle's geometry
+    xref = _oracle_node_vjp(m, 1, fp, eq, u0, rbar)
+    xb = torch.zeros(xref.shape, dtype=torch.float64, device=gpu)
+    sol.rhs_vjp(u0.to(gpu), rbar.to(gpu), torch.zeros_like(u0).to(gpu), x_bar=xb)
+    ex = float((xb.cpu() - xref).norm() / xref.norm())
+    print(f"p=1 {dim}-D {eq}: node adjoint rel L2 {ex:.3e}")
+    assert ex <= 1e-10, ex
