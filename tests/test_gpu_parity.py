@@ -204,24 +204,26 @@ def test_autotuned_tiles_give_the_same_step(name, gpu):
     assert rel_l2(u, ref) <= 1e-14
 
 
-@pytest.mark.parametrize("dim,eq,bc", [(2, "ns", "channel"), (3, "ns", "channel"), (2, "euler", "periodic")])
-def test_degree_one(dim, eq, bc, gpu):
+@pytest.mark.parametrize("p,dim,eq,bc", [(1, 2, "ns", "channel"), (1, 3, "ns", "channel"), (1, 2, "euler", "periodic"),
+                                         (3, 3, "ns", "channel"), (3, 3, "euler", "periodic")])
+def test_small_degree_and_3d_p3(p, dim, eq, bc, gpu):
     """p = 1 (2 points per direction: the smallest tiles and the NS tile whose LDS region is sized
-    for the neighbour codes rather than the gradient): residual and one RK4 step in FP64 against
-    the oracle; in FP32 one RK4 step within the FP32 bar (the residual, a small difference of large
-    flux terms, gets the looser bar of the other FP32 parity cases)."""
+    for the neighbour codes rather than the gradient) and 3-D p = 3 (the degree no other 3-D case
+    uses): residual and one RK4 step in FP64 against the oracle; in FP32 one RK4 step within the
+    FP32 bar (the residual, a small difference of large flux terms, gets the looser bar of the other
+    FP32 parity cases)."""
     import fr_inputs as fi
     from oracle import OracleSystem
     from paper_2312_14167_amd import Solver
     shape = (7, 5) if dim == 2 else (3, 3, 2)
     m = fi.periodic_box(dim, shape, q=1, bc=bc, seed=6)
     fp = fi.freestream_params(dim, 0.3, 100.0 if eq == "ns" else None, aoa_deg=25.0)
-    s = OracleSystem(m, 1, fp, equations=eq)
+    s = OracleSystem(m, p, fp, equations=eq)
     x = s.solpt_coords()
     nv = dim + 2
     u0 = torch.tensor(fi.freestream_state(x, fp) + fi.noise_like(x.shape[:-1] + (nv,), 4, 0.01)).permute(0, 2, 1)
     u0 = u0.contiguous()
-    sol = Solver(m, 1, fp, equations=eq, forces=(eq == "ns"), max_samples=4)
+    sol = Solver(m, p, fp, equations=eq, forces=(eq == "ns"), max_samples=4)
     R = sol.rhs(u0.to(gpu))
     assert rel_l2(R, s.residual(u0)) <= 1e-11
     dt = np.array([2e-3])
@@ -230,7 +232,7 @@ def test_degree_one(dim, eq, bc, gpu):
     uref, _, _ = s.run(u0, torch.tensor(dt), 1, sample_every=1)
     torch.cuda.synchronize()
     assert rel_l2(u, uref) <= 1e-12
-    s32 = Solver(m, 1, fp, equations=eq, precision="fp32")
+    s32 = Solver(m, p, fp, equations=eq, precision="fp32")
     R32 = s32.rhs(u0.float().to(gpu))
     assert rel_l2(R32, s.residual(u0)) <= 2e-3
     u32 = u0.float().to(gpu).clone()
