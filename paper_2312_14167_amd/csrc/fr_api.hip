@@ -265,6 +265,7 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->probe_dw = (double *)upload(s, pdw);
     s->probe_dxi = (double *)upload(s, pdxi);
     s->probe_nodes = (int64_t *)upload(s, pnodes);
+    s->probe_coef = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * (s->NV + s->dim) * sizeof(double));
     s->series = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * s->cap * sizeof(double));
     s->sums = (double *)dalloc(s, (size_t)std::max(1, s->n_probe) * 2 * sizeof(double));
     s->force_acc = (double *)dalloc(s, (size_t)n_mesh * s->dim * sizeof(double));

@@ -796,73 +796,88 @@ __global__ __launch_bounds__(64) void k_wall_force_sum(const double *__restrict_
   if (l < D) force_acc[m * D + l] += red[0][l];
 }
 
-// adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du (one workgroup, probes in order)
-// u_bar += p_bar dp/du at every probe.  With x_bar: the probe is fixed in physical space, so its
-// reference coordinates xi move with its element's nodes (d xi / d X_n = -A^{-1} phi_n, tabulated
-// per probe), and x_bar += p_bar (dp/dxi) (d xi / d X).  One workgroup, probes in a fixed order.
+// adjoint of the probe samples: u_bar += sum_a p_bar[a] dp_a/du.  With x_bar: the probe is fixed
+// in physical space, so its reference coordinates xi move with its element's nodes
+// (d xi / d X_n = -A^{-1} phi_n, tabulated per probe), and x_bar += p_bar (dp/dxi) (d xi / d X).
+// k_probe_vjp_coef (one workgroup per probe, fixed reduction trees) forms each probe's
+// coefficients p_bar dp/du_v and p_bar dp/dxi_k; k_probe_vjp_scatter (one workgroup) adds them into
+// u_bar and x_bar probe by probe, so probes that share an element or nodes add in a fixed order.
 template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void k_probe_vjp(const T *__restrict__ u, const int64_t *__restrict__ pelem,
-                                                   const double *__restrict__ pw, const double *__restrict__ pdw,
-                                                   const double *__restrict__ pdxi, const int64_t *__restrict__ pnodes,
-                                                   int nn, int n_probe, double gm1, const double *__restrict__ pbar,
-                                                   T *ubar, double *xbar) {
+__global__ __launch_bounds__(PROBE_BS) void k_probe_vjp_coef(const T *__restrict__ u, const int64_t *__restrict__ pelem,
+                                                             const double *__restrict__ pw,
+                                                             const double *__restrict__ pdw, double gm1,
+                                                             const double *__restrict__ pbar, bool geo,
+                                                             double *__restrict__ coef) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Ns = S::Ns;
-  __shared__ double red[256];
+  __shared__ double red[NV][PROBE_BS];
   __shared__ double dpdu[NV];
-  __shared__ double xib[D];
-  auto block_sum = [&](double s) {
-    red[threadIdx.x] = s;
+  const int a = blockIdx.x, i = threadIdx.x;
+  const int64_t e = pelem[a];
+  double uv[NV];
+  for (int v = 0; v < NV; ++v) uv[v] = i < Ns ? (double)u[(e * NV + v) * Ns + i] : 0.0;
+  const double w = i < Ns ? pw[(int64_t)a * Ns + i] : 0.0;
+  for (int v = 0; v < NV; ++v) red[v][i] = w * uv[v];
+  __syncthreads();
+  for (int st = PROBE_BS / 2; st > 0; st >>= 1) {
+    if (i < st)
+      for (int v = 0; v < NV; ++v) red[v][i] += red[v][i + st];
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
-    }
-    const double r = red[0];
+  }
+  const double pb = pbar[a];
+  if (i == 0) {
+    // p = (gamma-1)(E - |m|^2 / (2 rho)) at the interpolated state
+    double m2 = 0.0;
+    for (int j = 0; j < D; ++j) m2 += red[1 + j][0] * red[1 + j][0];
+    dpdu[0] = gm1 * 0.5 * m2 / (red[0][0] * red[0][0]);
+    for (int j = 0; j < D; ++j) dpdu[1 + j] = -gm1 * red[1 + j][0] / red[0][0];
+    dpdu[D + 1] = gm1;
+    for (int v = 0; v < NV; ++v) coef[(int64_t)a * (NV + D) + v] = pb * dpdu[v];
+  }
+  if (!geo) return;
+  __syncthreads();
+  // dp/dxi_k = sum_v dp/du_v sum_i (d w_i / d xi_k) u_{v,i}
+  double t[D];
+  for (int k = 0; k < D; ++k) {
+    t[k] = 0.0;
+    if (i < Ns)
+      for (int v = 0; v < NV; ++v) t[k] += dpdu[v] * pdw[((int64_t)a * D + k) * Ns + i] * uv[v];
+  }
+  __syncthreads();
+  for (int k = 0; k < D; ++k) red[k][i] = t[k];
+  __syncthreads();
+  for (int st = PROBE_BS / 2; st > 0; st >>= 1) {
+    if (i < st)
+      for (int k = 0; k < D; ++k) red[k][i] += red[k][i + st];
     __syncthreads();
-    return r;
-  };
+  }
+  if (i == 0)
+    for (int k = 0; k < D; ++k) coef[(int64_t)a * (NV + D) + NV + k] = pb * red[k][0];
+}
+
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_probe_vjp_scatter(const int64_t *__restrict__ pelem,
+                                                           const double *__restrict__ pw,
+                                                           const double *__restrict__ pdxi,
+                                                           const int64_t *__restrict__ pnodes, int nn, int n_probe,
+                                                           const double *__restrict__ coef, T *ubar, double *xbar) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns;
   for (int a = 0; a < n_probe; ++a) {
     const int64_t e = pelem[a];
-    double up[NV];
-    for (int v = 0; v < NV; ++v) {
-      double s = 0.0;
-      for (int i = threadIdx.x; i < Ns; i += blockDim.x) s += pw[(int64_t)a * Ns + i] * (double)u[(e * NV + v) * Ns + i];
-      up[v] = block_sum(s);
-    }
-    if (threadIdx.x == 0) {
-      // p = (gamma-1)(E - |m|^2 / (2 rho)) at the interpolated state
-      double m2 = 0.0;
-      for (int j = 0; j < D; ++j) m2 += up[1 + j] * up[1 + j];
-      dpdu[0] = gm1 * 0.5 * m2 / (up[0] * up[0]);
-      for (int j = 0; j < D; ++j) dpdu[1 + j] = -gm1 * up[1 + j] / up[0];
-      dpdu[D + 1] = gm1;
-    }
-    __syncthreads();
-    const double pb = pbar[a];
+    const double *c = coef + (int64_t)a * (NV + D);
     for (int idx = threadIdx.x; idx < NV * Ns; idx += blockDim.x) {
       const int v = idx / Ns, i = idx % Ns;
-      ubar[(e * NV + v) * Ns + i] += (T)(pb * dpdu[v] * pw[(int64_t)a * Ns + i]);
+      ubar[(e * NV + v) * Ns + i] += (T)(c[v] * pw[(int64_t)a * Ns + i]);
     }
-    if (xbar) {
-      for (int k = 0; k < D; ++k) {
-        double s = 0.0;
-        for (int idx = threadIdx.x; idx < NV * Ns; idx += blockDim.x) {
-          const int v = idx / Ns, i = idx % Ns;
-          s += dpdu[v] * pdw[((int64_t)a * D + k) * Ns + i] * (double)u[(e * NV + v) * Ns + i];
-        }
-        s = block_sum(s);
-        if (threadIdx.x == 0) xib[k] = pb * s;
-      }
-      __syncthreads();
+    if (xbar)
       for (int idx = threadIdx.x; idx < nn * D; idx += blockDim.x) {
         const int n = idx / D, j = idx % D;
-        double s = 0.0;
-        for (int k = 0; k < D; ++k) s += pdxi[(((int64_t)a * nn + n) * D + j) * D + k] * xib[k];
-        xbar[pnodes[(int64_t)a * nn + n] * D + j] += s;
+        double sx = 0.0;
+        for (int k = 0; k < D; ++k) sx += pdxi[(((int64_t)a * nn + n) * D + j) * D + k] * c[NV + k];
+        xbar[pnodes[(int64_t)a * nn + n] * D + j] += sx;
       }
-    }
-    __syncthreads();
+    __syncthreads();  // the next probe may share this element or its nodes
   }
 }
 
@@ -1102,10 +1117,12 @@ Dispatch make_dispatch() {
                             residuals ? (T *)residuals + 4 * nb * k : nullptr);
   };
   d.probe_vjp = [](const fr_solver *s, const void *u, const double *pbar, void *ub, double *xbar, hipStream_t st) {
-    if (s->n_probe > 0)
-      k_probe_vjp<D, P, T><<<1, 256, 0, st>>>((const T *)u, s->probe_elem, s->probe_w, s->probe_dw, s->probe_dxi,
-                                              s->probe_nodes, s->geo_nn, s->n_probe, s->gamma - 1.0, pbar,
-                                              (T *)ub, xbar);
+    if (s->n_probe > 0) {
+      k_probe_vjp_coef<D, P, T><<<(unsigned)s->n_probe, PROBE_BS, 0, st>>>(
+          (const T *)u, s->probe_elem, s->probe_w, s->probe_dw, s->gamma - 1.0, pbar, xbar != nullptr, s->probe_coef);
+      k_probe_vjp_scatter<D, P, T><<<1, 256, 0, st>>>(s->probe_elem, s->probe_w, s->probe_dxi, s->probe_nodes,
+                                                       s->geo_nn, s->n_probe, s->probe_coef, (T *)ub, xbar);
+    }
   };
   d.rk_adj_combine = [](const fr_solver *s, void *a, void *z, void *kb, void *ub, void *zz, double ca, double cz,
                         const double *dt, hipStream_t st) {

@@ -101,6 +101,7 @@ struct fr_solver {
   int64_t *probe_elem = nullptr;  // [n_probe]
   double *probe_w = nullptr;      // [n_probe][Ns]
   double *probe_pinf = nullptr;   // [n_probe]
+  double *probe_coef = nullptr;   // [n_probe][NV + dim] probe adjoint coefficients (scratch)
   double *series = nullptr;       // [n_probe][cap]
   double *sums = nullptr;         // [n_probe][2]
   double *force_acc = nullptr;    // [n_mesh][dim]

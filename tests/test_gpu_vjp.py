@@ -200,3 +200,41 @@ def test_rhs_vjp_degree_one(dim, eq, bc, gpu):
     ex = float((xb.cpu() - xref).norm() / xref.norm())
     print(f"p=1 {dim}-D {eq}: node adjoint rel L2 {ex:.3e}")
     assert ex <= 1e-10, ex
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_probe_vjp_many_probes_sharing_elements(precision, gpu):
+    """fr_probe_vjp with several probes, two of them in the same element and others in elements
+    that share nodes: u_bar and x_bar against autograd of the oracle's probe pressures (the
+    per-probe adjoints are formed in parallel and added into u_bar / x_bar in probe order)."""
+    import fr_inputs as fi
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m = fi.periodic_box(2, (6, 5), q=2, curv=0.15, seed=9)
+    fp = fi.freestream_params(2, 0.3, 100.0, aoa_deg=10.0)
+    # cells are (10/6) x 2 wide on [-5, 5]^2: the first two probes share a cell, the next ones sit
+    # in the neighbouring cells
+    probes = [[0.3, 0.4], [1.2, -0.5], [2.1, 0.6], [0.5, -1.2], [-1.0, 0.2], [3.9, 3.9]]
+    s0 = OracleSystem(m, 3, fp, equations="ns", probes=probes)
+    u0 = torch.tensor(fi.freestream_state(s0.solpt_coords(), fp)
+                      + fi.noise_like(s0.solpt_coords().shape[:-1] + (4,), 8, 0.02)).permute(0, 2, 1).contiguous()
+    pbar = torch.tensor(np.random.default_rng(47).normal(size=len(probes)))
+    X = torch.tensor(m.node_xyz, dtype=torch.float64, requires_grad=True)
+    uq = u0.clone().requires_grad_(True)
+    s = OracleSystem(m, 3, fp, equations="ns", probes=probes, node_xyz=X)
+    (s.probe_pressure(uq) * pbar).sum().backward()
+    ref_x, ref_u = X.grad.detach(), uq.grad.detach()
+    sol = Solver(m, 3, fp, equations="ns", precision=precision, probes=probes, max_samples=4)
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    ub = torch.zeros_like(u0, dtype=dtype).to(gpu)
+    xb = torch.zeros(ref_x.shape, dtype=torch.float64, device=gpu)
+    sol.probe_vjp(u0.to(dtype).to(gpu), pbar.to(gpu), ub, x_bar=xb)
+    torch.cuda.synchronize()
+    # FP32: the state itself is rounded, and d p / d xi sums derivative weights (zero sum) over a
+    # near-uniform state, so x_bar gets the node-adjoint FP32 bar of the residual VJP tests
+    tol_u, tol_x = (1e-10, 1e-10) if precision == "fp64" else (1e-5, 5e-3)
+    eu = rel_l2(ub, ref_u)
+    ex = float((xb.cpu() - ref_x).norm() / ref_x.norm())
+    print(f"{precision}: probe vjp u_bar {eu:.3e}, x_bar {ex:.3e}")
+    assert eu <= tol_u, eu
+    assert ex <= tol_x, ex
