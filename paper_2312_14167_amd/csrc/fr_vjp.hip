@@ -557,14 +557,17 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
   T *ldu = lA + E * NV * Ns;             // [E][NV][Nf]
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  __shared__ int s_mesh[E];  // mesh of each element (free-stream data)
   {
-    // both tiles in one round trip
+    // both tiles and the elements' mesh indices in one round trip
     TileLoad<E * NV * Ns, TL::BS, T> tu, tv;
     tu.load(u + e0 * NV * Ns, ne * NV * Ns);
     tv.load(volbar + e0 * NV * Ns, ne * NV * Ns);
+    const int mesh = (int)threadIdx.x < ne ? elem_mesh[e0 + threadIdx.x] : 0;
     stage_ops(ops, ops_arg);
     tu.store(lu, ne * NV * Ns);
     tv.store(lvb, ne * NV * Ns);
+    if ((int)threadIdx.x < ne) s_mesh[threadIdx.x] = mesh;
   }
   __syncthreads();
   const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;
@@ -601,7 +604,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       } else {
         T n[D];
         for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
-        farfield<D>(uo, n, flow[elem_mesh[e]], ph.gamma, ph.gm1, uh);
+        farfield<D>(uo, n, flow[s_mesh[el]], ph.gamma, ph.gm1, uh);
       }
       for (int v = 0; v < NV; ++v) ufb_nbr[(e * NV + v) * Nf + fp] = T(0);  // no neighbour here
     }
@@ -687,15 +690,15 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
         heat = false;
         wall = true;
       } else {
-        farfield<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ub);
+        farfield<D>(st, n, flow[s_mesh[elf]], ph.gamma, ph.gm1, ub);
       }
     }
     T ubb[NV];
     for (int v = 0; v < NV; ++v) ubb[v] = T(0);
-    fvis_vjp<D>(ub, g, n, flow[elem_mesh[ef]].mu, ph, heat, fb, ubb, gbf);
+    fvis_vjp<D>(ub, g, n, flow[s_mesh[elf]].mu, ph, heat, fb, ubb, gbf);
     if (GEO) {  // fvn = F_vis(ub, g) . n
       Visc<D, T> vs;
-      visc_state<D>(ub, g, flow[elem_mesh[ef]].mu, ph, heat, vs);
+      visc_state<D>(ub, g, flow[s_mesh[elf]].mu, ph, heat, vs);
       fvis_columns_dot<D>(vs, fb, nbv);
       // the common flux is F^ . |N| and enters with this side's fvn_bar: |N|_bar += fvn_bar . fvn / |N|
       // (stored at this point; the node mapping folds an R point's share into its L partner)
@@ -709,7 +712,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       if (wall)
         wall_state_vjp<D>(st, ubb, stb);
       else
-        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, ubb, stb, GEO ? nbv : nullptr);
+        farfield_vjp<D>(st, n, flow[s_mesh[elf]], ph.gamma, ph.gm1, ubb, stb, GEO ? nbv : nullptr);
     } else {
       for (int v = 0; v < NV; ++v) stb[v] = ubb[v];
     }
@@ -734,7 +737,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
     for (int q = 0; q < D * NV; ++q) gxb[q] = T(0);
     for (int v = 0; v < NV; ++v) ubs[v] = T(0);
     Visc<D, T> vs0;
-    if (GEO) visc_state<D>(uv, &gx[0][0], flow[elem_mesh[e]].mu, ph, true, vs0);
+    if (GEO) visc_state<D>(uv, &gx[0][0], flow[s_mesh[el]].mu, ph, true, vs0);
 #pragma unroll 1
     for (int k = 0; k < D; ++k) {
       int base, stride, ik, t;
@@ -758,7 +761,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       pick_row<D>(Sm, k, Sk);
       finv_dot_vjp<D>(uv, Sk, ph.gm1, ftb, ubs);
       for (int v = 0; v < NV; ++v) ftb[v] = -ftb[v];
-      fvis_vjp<D>(uv, &gx[0][0], Sk, flow[elem_mesh[e]].mu, ph, true, ftb, ubs, gxb);
+      fvis_vjp<D>(uv, &gx[0][0], Sk, flow[s_mesh[el]].mu, ph, true, ftb, ubs, gxb);
       // flux-point gradient adjoint back to this solution point (M0^T along the k-line)
       for (int j = 0; j < D; ++j)
         for (int v = 0; v < NV; ++v) {
@@ -855,7 +858,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       } else {
         T n[D];
         for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
-        farfield_vjp<D>(st, n, flow[elem_mesh[ef]], ph.gamma, ph.gm1, dub, own, GEO ? nbv : nullptr);
+        farfield_vjp<D>(st, n, flow[s_mesh[elf]], ph.gamma, ph.gm1, dub, own, GEO ? nbv : nullptr);
       }
     }
     for (int v = 0; v < NV; ++v) ufb_own[(ef * NV + v) * Nf + fpl] = own[v];
