@@ -946,28 +946,43 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_final(const T
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   if (el >= ne) return;
   const int64_t e = e0 + el;
-  const T dt = rk.ub ? (T)rk.dt[rk.elem_mesh[e]] : T(0);
+  // every operand of the point is requested before the first product
+  int ik[D], fm[D], fpp[D];
+  for (int k = 0; k < D; ++k) {
+    int base, stride, t;
+    line_of_sol<D, P>(i, k, base, stride, ik[k], t);
+    fm[k] = (2 * k) * Nfp + t;
+    fpp[k] = (2 * k + 1) * Nfp + t;
+  }
+  T sv[NV], am[NV][D], ap[NV][D], prev[NV];
+  const int mesh = rk.ub ? rk.elem_mesh[e] : 0;
   for (int v = 0; v < NV; ++v) {
-    T s = ubvol[(e * NV + v) * Ns + i];
+    const int64_t o = (e * NV + v) * Ns + i;
+    sv[v] = ubvol[o];
     const T *fo = ufb_own + (e * NV + v) * Nf;
-    const T *fn = ufb_nbr ? ufb_nbr + (e * NV + v) * Nf : nullptr;
     for (int k = 0; k < D; ++k) {
-      int base, stride, ik, t;
-      line_of_sol<D, P>(i, k, base, stride, ik, t);
-      const int fm = (2 * k) * Nfp + t, fpp = (2 * k + 1) * Nfp + t;
-      T am = fo[fm], ap = fo[fpp];
-      if (fn) {
-        am += fn[fm];
-        ap += fn[fpp];
-      }
-      s += ops.lm[ik] * am + ops.lp[ik] * ap;
+      am[v][k] = fo[fm[k]];
+      ap[v][k] = fo[fpp[k]];
     }
+    if (ufb_nbr) {
+      const T *fn = ufb_nbr + (e * NV + v) * Nf;
+      for (int k = 0; k < D; ++k) {
+        am[v][k] += fn[fm[k]];
+        ap[v][k] += fn[fpp[k]];
+      }
+    }
+    prev[v] = rk.ub ? rk.a[o] : ubar[o];
+  }
+  const T dt = rk.ub ? (T)rk.dt[mesh] : T(0);
+  for (int v = 0; v < NV; ++v) {
+    T s = sv[v];
+    for (int k = 0; k < D; ++k) s += ops.lm[ik[k]] * am[v][k] + ops.lp[ik[k]] * ap[v][k];
     const int64_t o = (e * NV + v) * Ns + i;
     if (rk.ub) {
       rk.ub[o] += s;
-      rk.kb[o] = dt * (rk.ca * rk.a[o] + rk.cz * s);
+      rk.kb[o] = dt * (rk.ca * prev[v] + rk.cz * s);
     } else {
-      ubar[o] += s;
+      ubar[o] = prev[v] + s;
     }
   }
 }
