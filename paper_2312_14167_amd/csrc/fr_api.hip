@@ -275,7 +275,7 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
       s->wall_nchunk = (int)std::max<int64_t>(1, (mx + WALL_CHUNK - 1) / WALL_CHUNK);
       s->wall_partial = (double *)dalloc(s, (size_t)n_mesh * s->wall_nchunk * s->dim * sizeof(double));
     }
-    s->count = (unsigned long long *)dalloc(s, sizeof(unsigned long long));
+    s->count = (unsigned long long *)dalloc(s, 2 * sizeof(unsigned long long));  // sample index, probe ticket
     s->nonfinite = (int *)dalloc(s, sizeof(int));
     HIP_OK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     const char *ng = std::getenv("FRMI_NO_GRAPH");

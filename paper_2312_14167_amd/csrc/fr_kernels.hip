@@ -698,14 +698,15 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
 }
 
 // probe pressure samples (FP64): one workgroup per probe, the weighted sum over the element's
-// solution points reduced in a fixed tree; the sample counter is advanced afterwards by
-// k_probe_count, so every workgroup of a sample reads the same index
+// solution points reduced in a fixed tree.  count[0] is the sample index, count[1] a ticket: each
+// workgroup reads the index, stores its sample, then takes a ticket, and the last one advances
+// the index (every workgroup has read it by then) and clears the ticket
 constexpr int PROBE_BS = 128;  // >= Ns for p <= 4
 template <int D, int P, typename T>
 __global__ __launch_bounds__(PROBE_BS) void k_probe(const T *__restrict__ u, const int64_t *__restrict__ pelem,
                                                     const double *__restrict__ pw, const double *__restrict__ pinf,
                                                     double gm1, double *series, int cap, double *sums,
-                                                    const unsigned long long *__restrict__ count, int *nonfinite) {
+                                                    unsigned long long *count, int *nonfinite) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Ns = S::Ns;
   static_assert(Ns <= PROBE_BS, "one solution point per thread");
@@ -730,11 +731,17 @@ __global__ __launch_bounds__(PROBE_BS) void k_probe(const T *__restrict__ u, con
     sums[2 * a] += dp;
     sums[2 * a + 1] += dp * dp;
     if (!isfinite(p)) *nonfinite = 1;
+    __threadfence();
+    if (atomicAdd(&count[1], 1ull) == (unsigned long long)(gridDim.x - 1)) {
+      count[0] = n + 1;
+      count[1] = 0ull;
+    }
   }
 }
 
+// the sample index of a sample without probes (forces only)
 __global__ void k_probe_count(unsigned long long *count) {
-  if (threadIdx.x == 0) *count += 1;
+  if (threadIdx.x == 0) count[0] += 1;
 }
 
 // wall force per mesh (FP64): sum over wall flux points of w |N| (p n - tau n), tau n being the
@@ -916,7 +923,11 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
 }
 
 __global__ void k_reset_counters(unsigned long long *count, int *nonfinite) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) { *count = 0ull; *nonfinite = 0; }
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    count[0] = 0ull;  // sample index
+    count[1] = 0ull;  // probe workgroups done in the current sample
+    *nonfinite = 0;
+  }
 }
 
 // ------------------------------------------------------------------------------------ engine
@@ -1062,7 +1073,8 @@ struct Engine {
       k_probe<D, P, T><<<(unsigned)s->n_probe, PROBE_BS, 0, st>>>(u, s->probe_elem, s->probe_w, s->probe_pinf,
                                                                    s->gamma - 1.0, s->series, s->cap, s->sums,
                                                                    s->count, s->nonfinite);
-    k_probe_count<<<1, 64, 0, st>>>(s->count);
+    else
+      k_probe_count<<<1, 64, 0, st>>>(s->count);
   }
 
   // one classical RK4 step of u in place; `fresh`: s->uf does not hold u_f of u yet (first step
