@@ -121,6 +121,16 @@ struct GradTile {
   static constexpr int MIN_WAVES = sizeof(T) == 4 ? 7 : 4;
 };
 
+// index of a thread's flux point in pass `pass` over a face-list-ordered tile: odd passes walk the
+// threads backwards, so that the points beyond one pass land on the last wave, which holds the
+// cheap end of the list (faces without gather or flux work), and not on wave 0, which holds the
+// costly front.  Pass k covers [k BS, (k+1) BS), so a thread's index grows with the pass.
+template <int BS>
+__device__ __forceinline__ int flux_pass_index(int pass) {
+  const int t = (int)threadIdx.x;
+  return pass * BS + ((pass & 1) ? BS - 1 - t : t);
+}
+
 template <int D, int P, typename T, int EE = 0>
 struct DivTile {
   using S = Shape<D, P>;
@@ -225,7 +235,9 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
   __syncthreads();
   const T wl = T(0.5) + ph.beta, wr = T(0.5) - ph.beta;     // LDG common solution: weights of u_L, u_R
   const T wlf = T(0.5) - ph.beta, wrf = T(0.5) + ph.beta;   // LDG common viscous flux: weights of F_L, F_R
-  for (int idx = threadIdx.x; idx < ne * Nf; idx += blockDim.x) {
+  for (int pass = 0;; ++pass) {
+    const int idx = flux_pass_index<TL::BS>(pass);
+    if (idx >= ne * Nf) break;
     const int fc0 = s_face[idx / Nfp];
     const int el = fc0 / NFACE, fp = (fc0 % NFACE) * Nfp + idx % Nfp;
     int base, stride, fs;
@@ -351,7 +363,9 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
   // the finished common flux goes to both sides of the pair (boundary points: own side only).
   // fvn is stored on boundary points in both modes (wall-force integral).
   const int nfc = s_nface;
-  for (int idx = threadIdx.x; idx < nfc * Nfp; idx += blockDim.x) {
+  for (int pass = 0;; ++pass) {
+    const int idx = flux_pass_index<TL::BS>(pass);
+    if (idx >= nfc * Nfp) break;
     const int fc = s_face[idx / Nfp];
     const int elf = fc / NFACE, fp = (fc % NFACE) * Nfp + idx % Nfp;
     int base, stride, fs;
