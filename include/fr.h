@@ -137,7 +137,8 @@ fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, i
 fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl, double *mean_force,
                          int64_t *n_samples, void *stream);
 
-/* Synchronise and copy the FP64 pressure series series[a*cap + k] (k < min(n, cap)). */
+/* Synchronise and copy the FP64 pressure series series[a*cap + k] for k < min(n, cap, max_samples);
+ * *n = samples taken since the last reset (the device keeps the first max_samples of them). */
 fr_status fr_probe_series(fr_solver *s, double *series, int64_t cap, int64_t *n, void *stream);
 
 /* Zero the sample counter, probe sums / series and force sums (kernel fill, graph safe). */

@@ -23,6 +23,8 @@ class FRTrajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, solver, dt, n_steps: int, checkpoint_every: int, nodes):
         C = max(1, int(checkpoint_every))
+        if solver.n_probe < 1 or solver.max_samples < n_steps:
+            raise ValueError("the solver needs probes and max_samples >= n_steps (one sample per step)")
         if nodes is not None:
             ref = torch.as_tensor(solver.node_xyz, dtype=torch.float64)
             if tuple(nodes.shape) != tuple(ref.shape) or not torch.equal(nodes.detach().cpu(), ref):

@@ -69,6 +69,7 @@ class Solver:
                         probe_xyz=_ptr(pxyz), probe_mesh=_ptr(pm), forces=1 if forces else 0, reserved0=0)
         self.n_node = int(node.shape[0])
         self.node_xyz = node.copy()
+        self.max_samples = int(prm.max_samples)  # capacity of the device series
         h = C.c_void_p()
         check(L.fr_build_operators(C.byref(md), C.byref(prm), C.byref(h)))
         self._h = h
@@ -135,7 +136,7 @@ class Solver:
         out = np.zeros((max(self.n_probe, 1), cap))
         n = C.c_int64()
         check(lib().fr_probe_series(self._h, out.ctypes.data_as(C.c_void_p), int(cap), C.byref(n), _stream(stream)))
-        return out[:self.n_probe, :min(int(n.value), cap)]
+        return out[:self.n_probe, :min(int(n.value), cap, self.max_samples)]
 
     def autotune(self, u: torch.Tensor, dt: torch.Tensor, reps: int = 3, stream=None) -> dict:
         """Time the candidate tile sizes of the volume kernels on this mesh (u is not modified) and

@@ -239,3 +239,42 @@ def test_small_degree_and_3d_p3(p, dim, eq, bc, gpu):
     s32.rk_step(u32, torch.tensor(dt, dtype=torch.float64, device=gpu), 1)
     torch.cuda.synchronize()
     assert rel_l2(u32, uref) <= 1e-5
+
+
+def test_many_probes_sampling_interval_and_series_cap(gpu):
+    """Six probes (two in one element): every probe workgroup of a sample stores at the same
+    sample index and the last one to finish advances it, so across two rk_step calls with a
+    sampling interval of 2 the samples land where the oracle takes them; the series keeps the
+    first max_samples of them while the sums (p_RMS) cover all; a reset starts again at index 0."""
+    import fr_inputs as fi
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m = fi.periodic_box(2, (6, 5), q=2, curv=0.15, seed=9)
+    fp = fi.freestream_params(2, 0.3, 100.0, aoa_deg=10.0)
+    probes = [[0.3, 0.4], [1.2, -0.5], [2.1, 0.6], [0.5, -1.2], [-1.0, 0.2], [3.9, 3.9]]
+    s = OracleSystem(m, 3, fp, equations="ns", probes=probes)
+    u0 = torch.tensor(fi.freestream_state(s.solpt_coords(), fp)
+                      + fi.noise_like(s.solpt_coords().shape[:-1] + (4,), 8, 0.02)).permute(0, 2, 1).contiguous()
+    dt = np.array([1e-3])
+    dtt = torch.tensor(dt, dtype=torch.float64, device=gpu)
+    sol = Solver(m, 3, fp, equations="ns", probes=probes, max_samples=3, forces=False)
+    u = u0.to(gpu).clone()
+    sol.reset_accumulators()
+    sol.rk_step(u, dtt, 5, sample_every=2)
+    sol.rk_step(u, dtt, 4, sample_every=2)
+    uref, P, _ = s.run(u0, torch.tensor(dt), 9, sample_every=2, forces=False)
+    torch.cuda.synchronize()
+    assert rel_l2(u, uref) <= 1e-12
+    assert P.shape == (5, 6)
+    st = sol.probe_oaspl(p_ref=2e-5)
+    assert st["n_samples"] == 5
+    np.testing.assert_allclose(sol.probe_series(8).T, P.numpy()[:3], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(st["prms"], P.numpy().std(axis=0), rtol=1e-6, atol=1e-13)
+    # a reset clears the index and the sums; sampling every step from the current state
+    sol.reset_accumulators()
+    sol.rk_step(u, dtt, 2, sample_every=1)
+    _, P2, _ = s.run(uref, torch.tensor(dt), 2, sample_every=1, forces=False)
+    st2 = sol.probe_oaspl(p_ref=2e-5)
+    assert st2["n_samples"] == 2
+    np.testing.assert_allclose(sol.probe_series(8).T, P2.numpy(), rtol=1e-12, atol=0)
+    np.testing.assert_allclose(st2["prms"], P2.numpy().std(axis=0), rtol=1e-6, atol=1e-13)

@@ -175,3 +175,21 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=300, cwd=root)
     assert r.returncode != 0
     assert "one GPU" in r.stderr or "1 GPU" in r.stderr, r.stderr
+
+
+def test_trajectory_adjoint_needs_one_stored_sample_per_step():
+    """The trajectory adjoint reads back one probe sample per step, so a solver whose device series
+    holds fewer samples than the steps (or that has no probes) is refused before any step runs."""
+    import torch
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+
+    class _Small:
+        n_probe, max_samples = 2, 3
+
+    class _NoProbe:
+        n_probe, max_samples = 0, 0
+
+    for s in (_Small(), _NoProbe()):
+        with pytest.raises(ValueError, match="max_samples"):
+            FRTrajectory.apply(torch.zeros(4, dtype=torch.float64), s, torch.zeros(1, dtype=torch.float64),
+                               5, 1, None)
