@@ -20,6 +20,19 @@ struct Shape {
   static constexpr int NM = D * D + 1;
 };
 
+// index of u_f(e, v, fp) in the face-blocked flux-point layout (see uf_face_stride)
+template <int D, int P, typename T>
+struct UfLayout {
+  using S = Shape<D, P>;
+  static constexpr int NFACE = 2 * D, FB = S::NV * S::Nfp;
+  static constexpr int LINE = 128 / (int)sizeof(T);
+  static constexpr int FS = (FB + LINE - 1) / LINE * LINE;  // face stride
+  static constexpr int EB = NFACE * FS;                      // element stride
+  __device__ __forceinline__ static int64_t at(int64_t e, int v, int fp) {
+    return e * EB + (fp / S::Nfp) * FS + v * S::Nfp + fp % S::Nfp;
+  }
+};
+
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int round64(int x) { return (x + 63) / 64 * 64; }

@@ -53,8 +53,8 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
     const int fL = cL % Nf, fR = cR % Nf;
     T uL[NV], uR[NV], n[D], F[NV];
     for (int v = 0; v < NV; ++v) {
-      uL[v] = uf[(eL * NV + v) * Nf + fL];
-      uR[v] = uf[(eR * NV + v) * Nf + fR];
+      uL[v] = uf[UfLayout<D, P, T>::at(eL, v, fL)];
+      uR[v] = uf[UfLayout<D, P, T>::at(eR, v, fR)];
     }
     for (int j = 0; j < D; ++j) n[j] = pnrm[gid * (D + 1) + j];
     const T mag = pnrm[gid * (D + 1) + D];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
     const int64_t e = c / Nf;
     const int fp = c % Nf;
     T uB[NV], ug[NV], n[D], F[NV];
-    for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
+    for (int v = 0; v < NV; ++v) uB[v] = uf[UfLayout<D, P, T>::at(e, v, fp)];
     for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
     const T mag = bnrm[b * (D + 1) + D];
     if (b < n_wall) {
@@ -266,7 +266,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
       const T wn = isR ? wl : wr;  // weight of the neighbour's value; zero on the one-sided LDG's other side
       T un[NV];
       for (int v = 0; v < NV; ++v) {
-        un[v] = wn != T(0) ? uf[(e2 * NV + v) * Nf + f2] : T(0);
+        un[v] = wn != T(0) ? uf[UfLayout<D, P, T>::at(e2, v, f2)] : T(0);
         uh[v] = isR ? wl * un[v] + wr * uo[v] : wl * uo[v] + wr * un[v];
       }
       if (side != 0 && wn != T(0)) {
@@ -494,6 +494,7 @@ struct RKArgs {
   T cA, cB;          // u_next = u0 + cA dt R ; acc += cB dt R
   int first, last;
   T *uf_next;        // flux-point values of the new stage state, or nullptr
+  const uint8_t *uf_faces;  // faces whose flux-point values are written (bit f per element)
   T *ustage_copy;    // optional second copy of the new stage state (adjoint recording)
   T *u0_copy;        // optional copy of the base state (adjoint recording, first stage)
   T *r_copy;         // optional copy of this stage's residual (adjoint recording)
@@ -552,41 +553,53 @@ __device__ __forceinline__ void rk_epilogue(const T *R, int64_t e, int i, const 
   }
 }
 
+// u_f = M0 u of a tile from its state in LDS ([E][NV][Ns]), for the faces flagged in faces[el]
+// (bit f; an LDS copy of the tile's entries): each flagged face block is written as one run of
+// whole lines
 template <int D, int P, typename T>
-__device__ __forceinline__ void tile_interp(const T *lw, int ne, const OpsDev<T, P> &ops, T *uf_tile) {
+__device__ __forceinline__ void tile_interp(const T *lw, int ne, const OpsDev<T, P> &ops, T *uf_tile,
+                                            const uint8_t *faces) {
   using S = Shape<D, P>;
-  constexpr int NV = S::NV, Ns = S::Ns, Nf = S::Nf;
-  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) {
-    const int fp = idx % Nf, rest = idx / Nf;
+  using L = UfLayout<D, P, T>;
+  constexpr int NV = S::NV, Ns = S::Ns, Nfp = S::Nfp, FB = L::FB, NFACE = L::NFACE;
+  for (int idx = threadIdx.x; idx < ne * NFACE * FB; idx += blockDim.x) {
+    const int ef = idx / FB, r = idx % FB;  // ef = element * NFACE + face
+    const int el = ef / NFACE, f = ef % NFACE;
+    if (!((faces[el] >> f) & 1)) continue;
+    const int v = r / Nfp, fp = f * Nfp + r % Nfp;
     int base, stride, side;
     line_of_fpt<D, P>(fp, base, stride, side);
     const T *lv = side ? ops.lp : ops.lm;
-    const T *lin = lw + rest * Ns + base;
+    const T *lin = lw + (el * NV + v) * Ns + base;
     T s = T(0);
 #pragma unroll
     for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-    uf_tile[idx] = s;
+    uf_tile[ef * L::FS + r] = s;
   }
 }
 
-// u_f = M0 u, E elements per workgroup: the state tile is staged in LDS (contiguous loads, one
-// round trip) and every flux-point value is written once, contiguously
+// u_f = M0 u on the flagged faces, E elements per workgroup: the state tile is staged in LDS
+// (contiguous loads, one round trip) and every flux-point value is written once
 template <int D, int P, typename T>
 __global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_interp(const T *__restrict__ u, T *__restrict__ uf,
+                                                                   const uint8_t *__restrict__ uf_faces,
                                                                    OpsDev<T, P> ops_arg, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = DivTile<D, P, T>;
-  constexpr int E = TL::E, NV = S::NV, Ns = S::Ns, Nf = S::Nf;
+  constexpr int E = TL::E, NV = S::NV, Ns = S::Ns;
   __shared__ __attribute__((aligned(16))) T lu[E * NV * Ns];
   __shared__ OpsDev<T, P> ops;
+  __shared__ uint8_t s_faces[E];
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
   TileLoad<E * NV * Ns, TL::BS, T> tu;
   tu.load(u + e0 * NV * Ns, ne * NV * Ns);
+  const uint8_t fmask = (int)threadIdx.x < ne ? uf_faces[e0 + threadIdx.x] : 0;
   stage_ops(ops, ops_arg);
+  if ((int)threadIdx.x < ne) s_faces[threadIdx.x] = fmask;
   tu.store(lu, ne * NV * Ns);
   __syncthreads();
-  tile_interp<D, P>(lu, ne, ops, uf + e0 * NV * Nf);
+  tile_interp<D, P>(lu, ne, ops, uf + e0 * UfLayout<D, P, T>::EB, s_faces);
 }
 
 // NS: R = -(1/J)(vol + Lift F^), RK update, u_f of the new stage state
@@ -600,14 +613,17 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
+  __shared__ uint8_t s_faces[E];
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
   const int64_t e = e0 + el;
-  // the common-flux tile, this point's volume term, 1/J and the RK inputs in one round trip
+  // the common-flux tile, this point's volume term, 1/J, the RK inputs and the tile's u_f face
+  // flags in one round trip
   TileLoad<E * NV * Nf, TL::BS, T> tf;
   tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
+  const uint8_t fmask = (rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
   T R[NV], invJ = T(0);
   RKIn<T, NV> in;
   if (act) {
@@ -617,6 +633,7 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
   }
   stage_ops(ops, ops_arg);
   tf.store(lds, ne * NV * Nf);
+  if ((int)threadIdx.x < ne) s_faces[threadIdx.x] = fmask;
   __syncthreads();
   T w[NV];
   if (act) {
@@ -637,7 +654,7 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
     if (act)
       for (int v = 0; v < NV; ++v) lds[(el * NV + v) * Ns + i] = w[v];
     __syncthreads();
-    tile_interp<D, P>(lds, ne, ops, rk.uf_next + e0 * NV * Nf);
+    tile_interp<D, P>(lds, ne, ops, rk.uf_next + e0 * UfLayout<D, P, T>::EB, s_faces);
   }
 }
 
@@ -653,6 +670,7 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
+  __shared__ uint8_t s_faces[E];
   T *lF = lds;                  // [E][D][NV][Ns]
   T *lf = lds + E * D * NV * Ns;  // [E][NV][Nf]
   const int64_t e0 = (int64_t)blockIdx.x * E;
@@ -660,9 +678,11 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
   const bool act = el < ne;
   const int64_t e = e0 + el;
-  // the common-flux tile, this point's state and metric terms and the RK inputs in one round trip
+  // the common-flux tile, this point's state and metric terms, the RK inputs and the tile's u_f
+  // face flags in one round trip
   TileLoad<E * NV * Nf, TL::BS, T> tf;
   tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
+  const uint8_t fmask = (rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
   T invJ = T(0), uv[NV], Sm[D][D];
   RKIn<T, NV> in;
   if (act) {
@@ -674,6 +694,7 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   }
   stage_ops(ops, ops_arg);
   tf.store(lf, ne * NV * Nf);
+  if ((int)threadIdx.x < ne) s_faces[threadIdx.x] = fmask;
   if (act) {
     for (int k = 0; k < D; ++k) {
       T fi[NV];
@@ -707,7 +728,7 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
     if (act)
       for (int v = 0; v < NV; ++v) lds[(el * NV + v) * Ns + i] = w[v];
     __syncthreads();
-    tile_interp<D, P>(lds, ne, ops, rk.uf_next + e0 * NV * Nf);
+    tile_interp<D, P>(lds, ne, ops, rk.uf_next + e0 * UfLayout<D, P, T>::EB, s_faces);
   }
 }
 
@@ -780,7 +801,7 @@ __global__ __launch_bounds__(WALL_CHUNK) void k_wall_force(const T *__restrict__
     const int64_t e = code / Nf;
     const int fp = code % Nf;
     T uB[NV];
-    for (int v = 0; v < NV; ++v) uB[v] = uf[(e * NV + v) * Nf + fp];
+    for (int v = 0; v < NV; ++v) uB[v] = uf[UfLayout<D, P, T>::at(e, v, fp)];
     T rho, vel[D], p;
     primitives<D>(uB, ph.gm1, rho, vel, p);
     const double wm = bw[b] * (double)bnrm[b * (D + 1) + D];
@@ -1008,7 +1029,7 @@ struct Engine {
   static void interp(const fr_solver *s, const T *u, T *uf, hipStream_t st) {
     ProfScope ps(s, 0, st);
     using TL = DivTile<D, P, T>;
-    k_interp<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, uf, ops(s), s->Ne);
+    k_interp<D, P, T><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(u, uf, s->uf_faces, ops(s), s->Ne);
   }
 
   // one residual evaluation of `u` whose flux-point values are already in s->uf; the epilogue
@@ -1110,6 +1131,7 @@ struct Engine {
       rk.first = k == 0;
       rk.last = k == 3;
       rk.uf_next = (T *)s->uf;
+      rk.uf_faces = s->uf_faces;
       rk.ustage_copy = (record && k < 3) ? record + (int64_t)k * s->Ne * S::NV * S::Ns : nullptr;
       rk.u0_copy = k == 0 ? record_u0 : nullptr;
       rk.r_copy = record_r ? record_r + (int64_t)k * s->Ne * S::NV * S::Ns : nullptr;

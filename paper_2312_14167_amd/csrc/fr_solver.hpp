@@ -53,6 +53,14 @@ struct PhysDev {
   int side;
 };
 
+// flux-point state u_f: element-major, then face; a face block holds the face's NV x Nfp values
+// (variable-major) padded to whole 128-byte lines, so that a stage writing only some faces of an
+// element writes whole lines.  Values per face block:
+inline int uf_face_stride(int nv, int nfp, int bytes) {
+  const int line = 128 / bytes;
+  return (nv * nfp + line - 1) / line * line;
+}
+
 // LDG flux side for beta in precision T
 template <typename T>
 inline int ldg_side_of(double beta) {
@@ -80,7 +88,8 @@ struct fr_solver {
 
   // device arrays (precision T unless noted)
   void *metric = nullptr;   // [Ne][dim*dim+1][Ns]
-  void *uf = nullptr;       // [Ne][NV][Nf]
+  void *uf = nullptr;       // [Ne][2 dim][face stride]: u_f by face (uf_face_stride)
+  uint8_t *uf_faces = nullptr;  // [Ne] faces (bit f) whose u_f the stage kernels write
   void *fvn = nullptr;      // [Ne][NV][Nf]   viscous normal flux at own flux points (NS)
   void *vol = nullptr;      // [Ne][NV][Ns]   volume divergence (NS)
   void *fnrm = nullptr;     // [Ne][dim+1][Nf] outward unit normal at own flux points, then |N|
