@@ -123,13 +123,18 @@ def algorithmic_bytes(info, dim, T, eq, ldg_beta=0.5):
     once; RK kernels averaged over the four stages of a step).  With the one-sided LDG flux
     (beta = +-1/2) only one side of each interior face pair takes the neighbour's u_f and
     supplies a viscous normal flux, and that side forms the pair's whole common flux inside the
-    Navier-Stokes volume kernel (no face kernel runs)."""
+    Navier-Stokes volume kernel (no face kernel runs); the stage kernels then write u_f only on
+    the faces whose values the flux side takes and on boundary faces when a face's values fill at
+    least two cache lines (one byte of face flags per element tells which)."""
     Ne, NV, Ns, Nf, npair, nbnd, nwall, nmesh = info
     NM = dim * dim + 1
     I = 4
     one_sided = abs(ldg_beta) == 0.5
+    # u_f written: face blocks of at least 256 bytes skip the faces no later kernel reads
+    skip = (NV * Nf // (2 * dim)) * T >= 256
+    uf_vals = (npair + nbnd) * NV if (eq == "ns" and one_sided and skip) else Ne * Nf * NV
     b = {}
-    b["interp"] = Ne * (NV * Ns + NV * Nf) * T
+    b["interp"] = Ne * NV * Ns * T + uf_vals * T + Ne
     # u, metrics, neighbour codes -> vol
     vol_part = Ne * ((2 * NV * Ns + NM * Ns) * T + Nf * I)
     if eq == "ns" and one_sided:
@@ -146,9 +151,9 @@ def algorithmic_bytes(info, dim, T, eq, ldg_beta=0.5):
                           + nbnd * ((NV + (NV if eq == "ns" else 0) + dim + 1) * T + I)
                           + (2 * npair + nbnd) * NV * T)
     rk_rw = (4 * (NV * Ns + NV * Nf + Ns + NV * Ns) + 3 * NV * Ns       # reads: vol/u, fhat, invJ, u0; acc
-             + 4 * NV * Nf + 3 * 2 * NV * Ns + NV * Ns) / 4.0            # writes: u_f, acc + stage state / u0
-    b["div_rk"] = Ne * (rk_rw * T + I)
-    b["euler_vol_rk"] = Ne * ((rk_rw + (NM - 1) * Ns) * T + I)
+             + 3 * 2 * NV * Ns + NV * Ns) / 4.0                          # writes: acc + stage state / u0
+    b["div_rk"] = Ne * (rk_rw * T + I + 1) + uf_vals * T                 # + u_f of the new stage state
+    b["euler_vol_rk"] = Ne * ((rk_rw + (NM - 1) * Ns) * T + I + 1) + uf_vals * T
     b["probe"] = 0.0
     b["wall_force"] = nwall * ((NV + dim + dim + 1) * T + 8 + I)
     return b

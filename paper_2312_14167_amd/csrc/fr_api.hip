@@ -250,17 +250,18 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->flow = s->precision == FR_FP64 ? upload_flow<double>(s) : upload_flow<float>(s);
     const size_t T = s->tsize;
     const size_t nsol = (size_t)s->Ne * s->NV * s->Ns, nf = (size_t)s->Ne * s->NV * s->Nf;
-    // u_f by face; the stage kernels write only the faces something reads later: with the
-    // one-sided LDG the side whose values the flux side takes, and boundary faces (wall force);
-    // otherwise (two-sided LDG, Euler: the face kernel reads both sides) every face
+    // u_f by face; where face blocks are line-sized (uf_face_skip) the stage kernels write only
+    // the faces something reads later: with the one-sided LDG the side whose values the flux side
+    // takes, and boundary faces (wall force); otherwise (small blocks, two-sided LDG, Euler: the
+    // face kernel reads both sides) every face
     {
       const int nface = 2 * s->dim;
-      const size_t fs = (size_t)uf_face_stride(s->NV, s->Nfp, (int)T);
+      const size_t fs = (size_t)uf_face_stride(s->NV * s->Nfp, (int)T);
       s->uf = dalloc(s, (size_t)s->Ne * nface * fs * T);
       const int side = s->precision == FR_FP64 ? ldg_side_of<double>(s->beta) : ldg_side_of<float>(s->beta);
       const uint8_t all = (uint8_t)((1u << nface) - 1u);
       std::vector<uint8_t> faces((size_t)s->Ne, all);
-      if (s->equations == FR_NAVIER_STOKES && side != 0) {
+      if (s->equations == FR_NAVIER_STOKES && side != 0 && uf_face_skip(s->NV * s->Nfp, (int)T)) {
         for (int64_t e = 0; e < s->Ne; ++e) {
           uint8_t m = 0;
           for (int f = 0; f < nface; ++f) {

@@ -20,16 +20,17 @@ struct Shape {
   static constexpr int NM = D * D + 1;
 };
 
-// index of u_f(e, v, fp) in the face-blocked flux-point layout (see uf_face_stride)
+// index of u_f(e, v, fp) in the flux-point layout (see uf_face_skip)
 template <int D, int P, typename T>
 struct UfLayout {
   using S = Shape<D, P>;
   static constexpr int NFACE = 2 * D, FB = S::NV * S::Nfp;
-  static constexpr int LINE = 128 / (int)sizeof(T);
-  static constexpr int FS = (FB + LINE - 1) / LINE * LINE;  // face stride
-  static constexpr int EB = NFACE * FS;                      // element stride
+  static constexpr bool SKIP = uf_face_skip(FB, (int)sizeof(T));  // face-blocked, faces skipped
+  static constexpr int FS = uf_face_stride(FB, (int)sizeof(T));   // face stride (face-blocked)
+  static constexpr int EB = NFACE * FS;                            // element stride
   __device__ __forceinline__ static int64_t at(int64_t e, int v, int fp) {
-    return e * EB + (fp / S::Nfp) * FS + v * S::Nfp + fp % S::Nfp;
+    if constexpr (SKIP) return e * EB + (fp / S::Nfp) * FS + v * S::Nfp + fp % S::Nfp;
+    else return (e * S::NV + v) * S::Nf + fp;
   }
 };
 

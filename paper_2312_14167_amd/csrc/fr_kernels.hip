@@ -553,28 +553,42 @@ __device__ __forceinline__ void rk_epilogue(const T *R, int64_t e, int i, const 
   }
 }
 
-// u_f = M0 u of a tile from its state in LDS ([E][NV][Ns]), for the faces flagged in faces[el]
-// (bit f; an LDS copy of the tile's entries): each flagged face block is written as one run of
-// whole lines
+// u_f = M0 u of a tile from its state in LDS ([E][NV][Ns]).  Face-blocked layout: the faces
+// flagged in faces[el] (bit f; an LDS copy of the tile's entries), each block one run of whole
+// lines; otherwise every value, contiguously
 template <int D, int P, typename T>
 __device__ __forceinline__ void tile_interp(const T *lw, int ne, const OpsDev<T, P> &ops, T *uf_tile,
                                             const uint8_t *faces) {
   using S = Shape<D, P>;
   using L = UfLayout<D, P, T>;
-  constexpr int NV = S::NV, Ns = S::Ns, Nfp = S::Nfp, FB = L::FB, NFACE = L::NFACE;
-  for (int idx = threadIdx.x; idx < ne * NFACE * FB; idx += blockDim.x) {
-    const int ef = idx / FB, r = idx % FB;  // ef = element * NFACE + face
-    const int el = ef / NFACE, f = ef % NFACE;
-    if (!((faces[el] >> f) & 1)) continue;
-    const int v = r / Nfp, fp = f * Nfp + r % Nfp;
-    int base, stride, side;
-    line_of_fpt<D, P>(fp, base, stride, side);
-    const T *lv = side ? ops.lp : ops.lm;
-    const T *lin = lw + (el * NV + v) * Ns + base;
-    T s = T(0);
+  constexpr int NV = S::NV, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, FB = L::FB, NFACE = L::NFACE;
+  if constexpr (L::SKIP) {
+    for (int idx = threadIdx.x; idx < ne * NFACE * FB; idx += blockDim.x) {
+      const int ef = idx / FB, r = idx % FB;  // ef = element * NFACE + face
+      const int el = ef / NFACE, f = ef % NFACE;
+      if (!((faces[el] >> f) & 1)) continue;
+      const int v = r / Nfp, fp = f * Nfp + r % Nfp;
+      int base, stride, side;
+      line_of_fpt<D, P>(fp, base, stride, side);
+      const T *lv = side ? ops.lp : ops.lm;
+      const T *lin = lw + (el * NV + v) * Ns + base;
+      T s = T(0);
 #pragma unroll
-    for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
-    uf_tile[ef * L::FS + r] = s;
+      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+      uf_tile[ef * L::FS + r] = s;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) {
+      const int fp = idx % Nf, rest = idx / Nf;  // rest = element * NV + v
+      int base, stride, side;
+      line_of_fpt<D, P>(fp, base, stride, side);
+      const T *lv = side ? ops.lp : ops.lm;
+      const T *lin = lw + rest * Ns + base;
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += lv[a] * lin[a * stride];
+      uf_tile[idx] = s;
+    }
   }
 }
 
@@ -594,7 +608,7 @@ __global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_interp(const T *__re
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
   TileLoad<E * NV * Ns, TL::BS, T> tu;
   tu.load(u + e0 * NV * Ns, ne * NV * Ns);
-  const uint8_t fmask = (int)threadIdx.x < ne ? uf_faces[e0 + threadIdx.x] : 0;
+  const uint8_t fmask = (UfLayout<D, P, T>::SKIP && (int)threadIdx.x < ne) ? uf_faces[e0 + threadIdx.x] : 0;
   stage_ops(ops, ops_arg);
   if ((int)threadIdx.x < ne) s_faces[threadIdx.x] = fmask;
   tu.store(lu, ne * NV * Ns);
@@ -623,7 +637,8 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
   // flags in one round trip
   TileLoad<E * NV * Nf, TL::BS, T> tf;
   tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
-  const uint8_t fmask = (rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
+  const uint8_t fmask =
+      (UfLayout<D, P, T>::SKIP && rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
   T R[NV], invJ = T(0);
   RKIn<T, NV> in;
   if (act) {
@@ -682,7 +697,8 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   // face flags in one round trip
   TileLoad<E * NV * Nf, TL::BS, T> tf;
   tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
-  const uint8_t fmask = (rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
+  const uint8_t fmask =
+      (UfLayout<D, P, T>::SKIP && rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
   T invJ = T(0), uv[NV], Sm[D][D];
   RKIn<T, NV> in;
   if (act) {

@@ -53,12 +53,15 @@ struct PhysDev {
   int side;
 };
 
-// flux-point state u_f: element-major, then face; a face block holds the face's NV x Nfp values
-// (variable-major) padded to whole 128-byte lines, so that a stage writing only some faces of an
-// element writes whole lines.  Values per face block:
-inline int uf_face_stride(int nv, int nfp, int bytes) {
-  const int line = 128 / bytes;
-  return (nv * nfp + line - 1) / line * line;
+// flux-point state u_f.  Where a face's NV x Nfp values (fb of `bytes` each) fill at least two
+// 128-byte lines: element-major, then face, each face block (variable-major) padded to whole
+// lines, and the stage kernels write only the faces read later, so every write covers whole
+// lines.  Smaller faces: [Ne][NV][Nf] with every face written (skipping some would leave partly
+// written lines, which cost more than the bytes they save).
+constexpr bool uf_face_skip(int fb, int bytes) { return fb * bytes >= 256; }
+// values per face block in the face-blocked layout
+constexpr int uf_face_stride(int fb, int bytes) {
+  return uf_face_skip(fb, bytes) ? (fb * bytes + 127) / 128 * 128 / bytes : fb;
 }
 
 // LDG flux side for beta in precision T
