@@ -1018,6 +1018,9 @@ struct VjpEngine {
     T *ufbface = fhatbar + nf;
     T *fvnbar = ufbface + nf;
     T *ufbnbr = fvnbar + nf;
+    // the forward flux-point buffer is scratch here: k_vjp_div fills every point of it in
+    // [Ne][NV][Nf] order (the buffer holds either layout), and every forward call starts by
+    // recomputing u_f in its own layout
     T *uf = (T *)s->uf;
     const T *metric = (const T *)s->metric;
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
