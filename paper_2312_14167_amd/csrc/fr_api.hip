@@ -274,7 +274,7 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
       }
       s->uf_faces = (uint8_t *)upload(s, faces);
     }
-    s->fhat = dalloc(s, nf * T);
+    s->fhat = dalloc(s, (size_t)s->Ne * 2 * s->dim * (size_t)uf_face_stride(s->NV * s->Nfp, (int)T) * T);
     s->acc = dalloc(s, nsol * T);
     s->ustage = dalloc(s, nsol * T);
     if (s->equations == FR_NAVIER_STOKES) {

@@ -20,7 +20,8 @@ struct Shape {
   static constexpr int NM = D * D + 1;
 };
 
-// index of u_f(e, v, fp) in the flux-point layout (see uf_face_skip)
+// index of value (e, v, fp) in the flux-point layout of u_f and the common flux (see
+// uf_face_skip): face-blocked where faces fill two lines, else [Ne][NV][Nf]
 template <int D, int P, typename T>
 struct UfLayout {
   using S = Shape<D, P>;
@@ -28,10 +29,14 @@ struct UfLayout {
   static constexpr bool SKIP = uf_face_skip(FB, (int)sizeof(T));  // face-blocked, faces skipped
   static constexpr int FS = uf_face_stride(FB, (int)sizeof(T));   // face stride (face-blocked)
   static constexpr int EB = NFACE * FS;                            // element stride
-  __device__ __forceinline__ static int64_t at(int64_t e, int v, int fp) {
-    if constexpr (SKIP) return e * EB + (fp / S::Nfp) * FS + v * S::Nfp + fp % S::Nfp;
-    else return (e * S::NV + v) * S::Nf + fp;
+  static constexpr int VS = SKIP ? S::Nfp : S::Nf;                 // variable stride
+  static constexpr int FST = SKIP ? FS : S::Nfp;                   // face stride of one variable
+  // offset of point fp of element e (variable 0); variable v adds v * VS
+  __device__ __forceinline__ static int64_t point(int64_t e, int fp) {
+    if constexpr (SKIP) return e * EB + (fp / S::Nfp) * FST + fp % S::Nfp;
+    else return e * EB + fp;
   }
+  __device__ __forceinline__ static int64_t at(int64_t e, int v, int fp) { return point(e, fp) + v * VS; }
 };
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }

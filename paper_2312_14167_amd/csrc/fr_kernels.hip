@@ -76,8 +76,8 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
       }
     }
     for (int v = 0; v < NV; ++v) {
-      fhat[(eL * NV + v) * Nf + fL] = F[v] * mag;
-      fhat[(eR * NV + v) * Nf + fR] = -F[v] * mag;
+      fhat[UfLayout<D, P, T>::at(eL, v, fL)] = F[v] * mag;
+      fhat[UfLayout<D, P, T>::at(eR, v, fR)] = -F[v] * mag;
     }
   } else if (gid < npair + nbnd) {
     const int64_t b = gid - npair;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
     rusanov<D>(uB, ug, n, ph.gamma, ph.gm1, F);
     if (NS)
       for (int v = 0; v < NV; ++v) F[v] -= fvn[(e * NV + v) * Nf + fp];
-    for (int v = 0; v < NV; ++v) fhat[(e * NV + v) * Nf + fp] = F[v] * mag;
+    for (int v = 0; v < NV; ++v) fhat[UfLayout<D, P, T>::at(e, v, fp)] = F[v] * mag;
   }
 }
 
@@ -134,7 +134,7 @@ __device__ __forceinline__ int flux_pass_index(int pass) {
 template <int D, int P, typename T, int EE = 0>
 struct DivTile {
   using S = Shape<D, P>;
-  static constexpr int LE = S::NV * cmax(S::Nf, S::Ns);
+  static constexpr int LE = cmax(UfLayout<D, P, T>::EB, S::NV * S::Ns);  // common-flux tile, then state
   static constexpr int E = EE > 0 ? EE : tile_elems<S::Ns>(LE, sizeof(T));
   static constexpr int BS = round64(E * S::Ns);
 };
@@ -142,7 +142,7 @@ struct DivTile {
 template <int D, int P, typename T, int EE = 0>
 struct EulerTile {
   using S = Shape<D, P>;
-  static constexpr int LE = D * S::NV * S::Ns + S::NV * S::Nf;
+  static constexpr int LE = D * S::NV * S::Ns + UfLayout<D, P, T>::EB;
   static constexpr int E = EE > 0 ? EE : tile_elems<S::Ns>(LE, sizeof(T));
   static constexpr int BS = round64(E * S::Ns);
 };
@@ -180,7 +180,8 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
   // tile bases are uniform; per-thread offsets inside the tile are 32-bit
   const int32_t *nbr_t = nbr + e0 * Nf;
   const T *fnrm_t = fnrm + e0 * (D + 1) * Nf, *metric_t = metric + e0 * NM * Ns;
-  T *fvn_t = fvn + e0 * NV * Nf, *fhat_t = fhat + e0 * NV * Nf, *vol_t = vol + e0 * NV * Ns;
+  using UL = UfLayout<D, P, T>;  // layout of fhat (and u_f)
+  T *fvn_t = fvn + e0 * NV * Nf, *fhat_t = fhat + e0 * UL::EB, *vol_t = vol + e0 * NV * Ns;
   T *lu = lds;                // [E][NV][Ns]
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][Ns][D][NV] gradient; [E][D][NV][Ns] F~
   int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
@@ -275,14 +276,14 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
         T n[D], F[NV];
         for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((el * (D + 1) + j) * Nf + fp)];
         const T mag = fnrm_t[(uint32_t)((el * (D + 1) + D) * Nf + fp)];
-        T *fo = fhat_t + (uint32_t)(el * NV * Nf + fp);
+        T *fo = fhat_t + (uint32_t)UL::point(el, fp);
         if (isR) {
           for (int j = 0; j < D; ++j) n[j] = -n[j];  // n_L
           rusanov<D>(un, uo, n, ph.gamma, ph.gm1, F);
-          for (int v = 0; v < NV; ++v) fo[v * Nf] = (F[v] + ph.tau * (un[v] - uo[v])) * mag;
+          for (int v = 0; v < NV; ++v) fo[v * UL::VS] = (F[v] + ph.tau * (un[v] - uo[v])) * mag;
         } else {
           rusanov<D>(uo, un, n, ph.gamma, ph.gm1, F);
-          for (int v = 0; v < NV; ++v) fo[v * Nf] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
+          for (int v = 0; v < NV; ++v) fo[v * UL::VS] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
         }
       }
     } else {
@@ -307,8 +308,8 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
         }
         rusanov<D>(uo, ug, n, ph.gamma, ph.gm1, F);
         const T mag = bnrm[b * (D + 1) + D];
-        T *fo = fhat_t + (uint32_t)(el * NV * Nf + fp);
-        for (int v = 0; v < NV; ++v) fo[v * Nf] = F[v] * mag;
+        T *fo = fhat_t + (uint32_t)UL::point(el, fp);
+        for (int v = 0; v < NV; ++v) fo[v * UL::VS] = F[v] * mag;
       }
     }
     for (int v = 0; v < NV; ++v) lw[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
@@ -388,11 +389,11 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     const int32_t code = nbr_t[(uint32_t)(elf * Nf + fp)];
     const FlowDev<T> &fl = flow[s_mesh[elf]];
     // the common-flux partial of the first phase and |N| are requested with the other loads
-    T *fo = fhat_t + (uint32_t)(elf * NV * Nf + fp);
+    T *fo = fhat_t + (uint32_t)UL::point(elf, fp);
     T fprev[NV], mag = T(0);
     if (side != 0) {
       mag = fnrm_t[(uint32_t)((elf * (D + 1) + D) * Nf + fp)];
-      for (int v = 0; v < NV; ++v) fprev[v] = fo[v * Nf];
+      for (int v = 0; v < NV; ++v) fprev[v] = fo[v * UL::VS];
     }
     bool heat = true, wall = false;
     if (code < 0) {
@@ -422,21 +423,21 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     if (side == 0) continue;
     // complete the common flux started in the first phase (same workgroup, ordered by the barriers)
     if (code < 0) {
-      for (int v = 0; v < NV; ++v) fo[v * Nf] = fprev[v] - fv[v] * mag;
+      for (int v = 0; v < NV; ++v) fo[v * UL::VS] = fprev[v] - fv[v] * mag;
     } else {
       const int32_t c = code & (NBR_R_BIT - 1);
-      T *fq = fhat + (int64_t)(c / Nf) * NV * Nf + c % Nf;
+      T *fq = fhat + UL::point((int64_t)(c / Nf), c % Nf);
       if (code & NBR_R_BIT) {  // F^ . n_L = ... + (1/2 + b) fvn_R
         for (int v = 0; v < NV; ++v) {
           const T t = fprev[v] + wrf * fv[v] * mag;
-          fo[v * Nf] = -t;
-          fq[v * Nf] = t;
+          fo[v * UL::VS] = -t;
+          fq[v * UL::VS] = t;
         }
       } else {                 // F^ . n_L = ... - (1/2 - b) fvn_L
         for (int v = 0; v < NV; ++v) {
           const T t = fprev[v] - wlf * fv[v] * mag;
-          fo[v * Nf] = t;
-          fq[v * Nf] = -t;
+          fo[v * UL::VS] = t;
+          fq[v * UL::VS] = -t;
         }
       }
     }
@@ -635,10 +636,10 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
   const int64_t e = e0 + el;
   // the common-flux tile, this point's volume term, 1/J, the RK inputs and the tile's u_f face
   // flags in one round trip
-  TileLoad<E * NV * Nf, TL::BS, T> tf;
-  tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
-  const uint8_t fmask =
-      (UfLayout<D, P, T>::SKIP && rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
+  using UL = UfLayout<D, P, T>;
+  TileLoad<E * UL::EB, TL::BS, T> tf;
+  tf.load(fhat + e0 * UL::EB, ne * UL::EB);
+  const uint8_t fmask = (UL::SKIP && rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
   T R[NV], invJ = T(0);
   RKIn<T, NV> in;
   if (act) {
@@ -647,7 +648,7 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
     rk_prefetch<D, P>(e, i, rk, elem_mesh, in);
   }
   stage_ops(ops, ops_arg);
-  tf.store(lds, ne * NV * Nf);
+  tf.store(lds, ne * UL::EB);
   if ((int)threadIdx.x < ne) s_faces[threadIdx.x] = fmask;
   __syncthreads();
   T w[NV];
@@ -657,8 +658,8 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
       line_of_sol<D, P>(i, k, base, stride, ik, t);
       const T gm = ops.gm[ik], gp = ops.gp[ik];
       for (int v = 0; v < NV; ++v) {
-        const T *lf = lds + (el * NV + v) * Nf;
-        R[v] += gm * lf[(2 * k) * Nfp + t] + gp * lf[(2 * k + 1) * Nfp + t];
+        const T *lf = lds + el * UL::EB + v * UL::VS;
+        R[v] += gm * lf[(2 * k) * UL::FST + t] + gp * lf[(2 * k + 1) * UL::FST + t];
       }
     }
     for (int v = 0; v < NV; ++v) R[v] = -invJ * R[v];
@@ -687,7 +688,7 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   __shared__ OpsDev<T, P> ops;
   __shared__ uint8_t s_faces[E];
   T *lF = lds;                  // [E][D][NV][Ns]
-  T *lf = lds + E * D * NV * Ns;  // [E][NV][Nf]
+  T *lf = lds + E * D * NV * Ns;  // common-flux tile, layout of fhat
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
   const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
@@ -695,10 +696,10 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
   const int64_t e = e0 + el;
   // the common-flux tile, this point's state and metric terms, the RK inputs and the tile's u_f
   // face flags in one round trip
-  TileLoad<E * NV * Nf, TL::BS, T> tf;
-  tf.load(fhat + e0 * NV * Nf, ne * NV * Nf);
-  const uint8_t fmask =
-      (UfLayout<D, P, T>::SKIP && rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
+  using UL = UfLayout<D, P, T>;
+  TileLoad<E * UL::EB, TL::BS, T> tf;
+  tf.load(fhat + e0 * UL::EB, ne * UL::EB);
+  const uint8_t fmask = (UL::SKIP && rk.uf_next && (int)threadIdx.x < ne) ? rk.uf_faces[e0 + threadIdx.x] : 0;
   T invJ = T(0), uv[NV], Sm[D][D];
   RKIn<T, NV> in;
   if (act) {
@@ -709,7 +710,7 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
     rk_prefetch<D, P>(e, i, rk, elem_mesh, in);
   }
   stage_ops(ops, ops_arg);
-  tf.store(lf, ne * NV * Nf);
+  tf.store(lf, ne * UL::EB);
   if ((int)threadIdx.x < ne) s_faces[threadIdx.x] = fmask;
   if (act) {
     for (int k = 0; k < D; ++k) {
@@ -732,8 +733,8 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
         T ds = T(0);
 #pragma unroll
         for (int a = 0; a < P; ++a) ds += ops.Dt[ik * P + a] * lin[a * stride];
-        const T *lfv = lf + (el * NV + v) * Nf;
-        accv += ds + ops.gm[ik] * lfv[(2 * k) * Nfp + t] + ops.gp[ik] * lfv[(2 * k + 1) * Nfp + t];
+        const T *lfv = lf + el * UL::EB + v * UL::VS;
+        accv += ds + ops.gm[ik] * lfv[(2 * k) * UL::FST + t] + ops.gp[ik] * lfv[(2 * k + 1) * UL::FST + t];
       }
       R[v] = -invJ * accv;
     }

@@ -96,7 +96,7 @@ struct fr_solver {
   void *fvn = nullptr;      // [Ne][NV][Nf]   viscous normal flux at own flux points (NS)
   void *vol = nullptr;      // [Ne][NV][Ns]   volume divergence (NS)
   void *fnrm = nullptr;     // [Ne][dim+1][Nf] outward unit normal at own flux points, then |N|
-  void *fhat = nullptr;     // [Ne][NV][Nf]
+  void *fhat = nullptr;     // common flux x |N|, in the layout of uf
   void *acc = nullptr;      // [Ne][NV][Ns]
   void *ustage = nullptr;   // [Ne][NV][Ns]
   void *pair_nrm = nullptr; // [npair][dim+1]
