@@ -109,12 +109,16 @@ struct GradTile {
   using S = Shape<D, P>;
   // per element: the state [NV][Ns], kept to the flux-point viscous phase, then one region that
   // holds u^ - u_f [NV][Nf] (with the tile's neighbour codes [Nf] behind all elements' u^ - u_f),
-  // the physical gradient point-major [Ns][D][NV] and the transformed flux [D][NV][Ns] in turn.
-  // The default E fits four workgroups in 160 KB of LDS.
+  // the physical gradient point-major [Ns][D][NV] and the transformed flux [D][NV][Ns] in turn;
+  // in 2-D also the metric terms S [D*D][Ns], which each thread keeps there from the gradient to
+  // the transformed flux (2-D tiles are small enough that this costs no occupancy; 3-D re-reads
+  // them).  The default E fits four workgroups in 160 KB of LDS.
+  static constexpr bool KEEP_S = D == 2;
   static constexpr int LU = S::NV * S::Ns;
   static constexpr int LC = (S::Nf * (int)sizeof(int32_t) + (int)sizeof(T) - 1) / (int)sizeof(T);
   static constexpr int LG = cmax(S::NV * S::Nf + LC, D * S::NV * S::Ns);
-  static constexpr int LE = LU + LG;
+  static constexpr int LS = KEEP_S ? D * D * S::Ns : 0;
+  static constexpr int LE = LU + LG + LS;
   static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
   // register budget (launch bound, waves per SIMD): 4 (128 VGPRs) in FP64, 7 (72 VGPRs) in FP32
@@ -185,6 +189,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
   T *lu = lds;                // [E][NV][Ns]
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][Ns][D][NV] gradient; [E][D][NV][Ns] F~
   int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
+  T *ls = lds + E * (TL::LU + TL::LG);  // [E][D*D][Ns] (2-D): S of each thread's own point
   const int side = ph.side;
   // the state, the neighbour codes and the mesh indices arrive in one round trip, so the first
   // flux-point phase starts its neighbour gathers without another one; wave 0 also requests the
@@ -324,6 +329,9 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     for (int k = 0; k < D; ++k)
       for (int j = 0; j < D; ++j) Sm[k][j] = metric_t[(uint32_t)((el * NM + k * D + j) * Ns + i)];
     const T invJ = metric_t[(uint32_t)((el * NM + D * D) * Ns + i)];
+    if constexpr (TL::KEEP_S)
+      for (int k = 0; k < D; ++k)
+        for (int j = 0; j < D; ++j) ls[(el * D * D + k * D + j) * Ns + i] = Sm[k][j];
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) gx[j][v] = T(0);
 #pragma unroll
@@ -453,7 +461,9 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     visc_state<D>(uv, g, flow[s_mesh[el]].mu, ph, true, vs);
     for (int k = 0; k < D; ++k) {
       T Sk[D], fi[NV], fv[NV];
-      for (int j = 0; j < D; ++j) Sk[j] = metric_t[(uint32_t)((el * NM + k * D + j) * Ns + i)];  // second read
+      for (int j = 0; j < D; ++j)
+        Sk[j] = TL::KEEP_S ? ls[(el * D * D + k * D + j) * Ns + i]                  // own LDS copy
+                           : metric_t[(uint32_t)((el * NM + k * D + j) * Ns + i)];  // second read
       finv_dot<D>(uv, Sk, ph.gm1, fi);
       fvis_dot<D>(vs, Sk, fv);
       for (int v = 0; v < NV; ++v) ft[k][v] = fi[v] - fv[v];
