@@ -111,13 +111,14 @@ struct GradTile {
   // holds u^ - u_f [NV][Nf] (with the tile's neighbour codes [Nf] behind all elements' u^ - u_f),
   // the physical gradient point-major [Ns][D][NV] and the transformed flux [D][NV][Ns] in turn;
   // in 2-D also the metric terms S [D*D][Ns], which each thread keeps there from the gradient to
-  // the transformed flux (2-D tiles are small enough that this costs no occupancy; 3-D re-reads
-  // them).  The default E fits four workgroups in 160 KB of LDS.
+  // the transformed flux, and the first phase's partial common flux [NV][Nf] for the viscous
+  // flux-point phase (2-D tiles are small enough that this costs no occupancy; 3-D re-reads S
+  // and passes the partial flux through fhat).  The default E fits four workgroups in 160 KB.
   static constexpr bool KEEP_S = D == 2;
   static constexpr int LU = S::NV * S::Ns;
   static constexpr int LC = (S::Nf * (int)sizeof(int32_t) + (int)sizeof(T) - 1) / (int)sizeof(T);
   static constexpr int LG = cmax(S::NV * S::Nf + LC, D * S::NV * S::Ns);
-  static constexpr int LS = KEEP_S ? D * D * S::Ns : 0;
+  static constexpr int LS = KEEP_S ? D * D * S::Ns + S::NV * S::Nf : 0;
   static constexpr int LE = LU + LG + LS;
   static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
@@ -190,6 +191,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][Ns][D][NV] gradient; [E][D][NV][Ns] F~
   int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
   T *ls = lds + E * (TL::LU + TL::LG);  // [E][D*D][Ns] (2-D): S of each thread's own point
+  T *lp = ls + E * D * D * Ns;          // [E][NV][Nf] (2-D): partial common flux
   const int side = ph.side;
   // the state, the neighbour codes and the mesh indices arrive in one round trip, so the first
   // flux-point phase starts its neighbour gathers without another one; wave 0 also requests the
@@ -281,14 +283,19 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
         T n[D], F[NV];
         for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((el * (D + 1) + j) * Nf + fp)];
         const T mag = fnrm_t[(uint32_t)((el * (D + 1) + D) * Nf + fp)];
-        T *fo = fhat_t + (uint32_t)UL::point(el, fp);
         if (isR) {
           for (int j = 0; j < D; ++j) n[j] = -n[j];  // n_L
           rusanov<D>(un, uo, n, ph.gamma, ph.gm1, F);
-          for (int v = 0; v < NV; ++v) fo[v * UL::VS] = (F[v] + ph.tau * (un[v] - uo[v])) * mag;
+          for (int v = 0; v < NV; ++v) F[v] = (F[v] + ph.tau * (un[v] - uo[v])) * mag;
         } else {
           rusanov<D>(uo, un, n, ph.gamma, ph.gm1, F);
-          for (int v = 0; v < NV; ++v) fo[v * UL::VS] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
+          for (int v = 0; v < NV; ++v) F[v] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
+        }
+        if constexpr (TL::KEEP_S) {
+          for (int v = 0; v < NV; ++v) lp[(el * NV + v) * Nf + fp] = F[v];
+        } else {
+          T *fo = fhat_t + (uint32_t)UL::point(el, fp);
+          for (int v = 0; v < NV; ++v) fo[v * UL::VS] = F[v];
         }
       }
     } else {
@@ -313,8 +320,12 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
         }
         rusanov<D>(uo, ug, n, ph.gamma, ph.gm1, F);
         const T mag = bnrm[b * (D + 1) + D];
-        T *fo = fhat_t + (uint32_t)UL::point(el, fp);
-        for (int v = 0; v < NV; ++v) fo[v * UL::VS] = F[v] * mag;
+        if constexpr (TL::KEEP_S) {
+          for (int v = 0; v < NV; ++v) lp[(el * NV + v) * Nf + fp] = F[v] * mag;
+        } else {
+          T *fo = fhat_t + (uint32_t)UL::point(el, fp);
+          for (int v = 0; v < NV; ++v) fo[v * UL::VS] = F[v] * mag;
+        }
       }
     }
     for (int v = 0; v < NV; ++v) lw[(el * NV + v) * Nf + fp] = uh[v] - uo[v];
@@ -401,7 +412,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     T fprev[NV], mag = T(0);
     if (side != 0) {
       mag = fnrm_t[(uint32_t)((elf * (D + 1) + D) * Nf + fp)];
-      for (int v = 0; v < NV; ++v) fprev[v] = fo[v * UL::VS];
+      for (int v = 0; v < NV; ++v) fprev[v] = TL::KEEP_S ? lp[(elf * NV + v) * Nf + fp] : fo[v * UL::VS];
     }
     bool heat = true, wall = false;
     if (code < 0) {
