@@ -114,11 +114,11 @@ struct GradTile {
   // the transformed flux, and the first phase's partial common flux [NV][Nf] for the viscous
   // flux-point phase (2-D tiles are small enough that this costs no occupancy; 3-D re-reads S
   // and passes the partial flux through fhat).  The default E fits four workgroups in 160 KB.
-  static constexpr bool KEEP_S = D == 2;
+  static constexpr bool KEEP2D = D == 2;
   static constexpr int LU = S::NV * S::Ns;
   static constexpr int LC = (S::Nf * (int)sizeof(int32_t) + (int)sizeof(T) - 1) / (int)sizeof(T);
   static constexpr int LG = cmax(S::NV * S::Nf + LC, D * S::NV * S::Ns);
-  static constexpr int LS = KEEP_S ? D * D * S::Ns + S::NV * S::Nf : 0;
+  static constexpr int LS = KEEP2D ? D * D * S::Ns + S::NV * S::Nf : 0;
   static constexpr int LE = LU + LG + LS;
   static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
@@ -279,7 +279,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
       }
       if (side != 0 && wn != T(0)) {
         // flux side of a one-sided pair: inviscid common flux along n_L plus the penalty, x |N|,
-        // into this point's fhat; the flux-point phase adds the viscous part
+        // into this point's fhat (2-D: its LDS slot); the flux-point phase adds the viscous part
         T n[D], F[NV];
         for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((el * (D + 1) + j) * Nf + fp)];
         const T mag = fnrm_t[(uint32_t)((el * (D + 1) + D) * Nf + fp)];
@@ -291,7 +291,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
           rusanov<D>(uo, un, n, ph.gamma, ph.gm1, F);
           for (int v = 0; v < NV; ++v) F[v] = (F[v] + ph.tau * (uo[v] - un[v])) * mag;
         }
-        if constexpr (TL::KEEP_S) {
+        if constexpr (TL::KEEP2D) {
           for (int v = 0; v < NV; ++v) lp[(el * NV + v) * Nf + fp] = F[v];
         } else {
           T *fo = fhat_t + (uint32_t)UL::point(el, fp);
@@ -320,7 +320,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
         }
         rusanov<D>(uo, ug, n, ph.gamma, ph.gm1, F);
         const T mag = bnrm[b * (D + 1) + D];
-        if constexpr (TL::KEEP_S) {
+        if constexpr (TL::KEEP2D) {
           for (int v = 0; v < NV; ++v) lp[(el * NV + v) * Nf + fp] = F[v] * mag;
         } else {
           T *fo = fhat_t + (uint32_t)UL::point(el, fp);
@@ -340,7 +340,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     for (int k = 0; k < D; ++k)
       for (int j = 0; j < D; ++j) Sm[k][j] = metric_t[(uint32_t)((el * NM + k * D + j) * Ns + i)];
     const T invJ = metric_t[(uint32_t)((el * NM + D * D) * Ns + i)];
-    if constexpr (TL::KEEP_S)
+    if constexpr (TL::KEEP2D)
       for (int k = 0; k < D; ++k)
         for (int j = 0; j < D; ++j) ls[(el * D * D + k * D + j) * Ns + i] = Sm[k][j];
     for (int j = 0; j < D; ++j)
@@ -379,8 +379,9 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
   // Flux points of the listed faces: viscous normal flux fvn = F_vis(u_f, M0 grad_x u) . n_out.
   // Two-sided LDG: stored for the face kernel.  One-sided LDG: this point's side alone supplies
   // the viscous part of the common flux and holds both states, so the first phase already put
-  // the inviscid part and the penalty (x |N|) into its fhat; here the viscous part is added and
-  // the finished common flux goes to both sides of the pair (boundary points: own side only).
+  // the inviscid part and the penalty (x |N|) into its fhat (2-D: LDS); here the viscous part is
+  // added and the finished common flux goes to both sides of the pair (boundary points: own side
+  // only).
   // fvn is stored on boundary points in both modes (wall-force integral).
   const int nfc = s_nface;
   for (int pass = 0;; ++pass) {
@@ -407,12 +408,13 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     for (int j = 0; j < D; ++j) n[j] = fnrm_t[(uint32_t)((elf * (D + 1) + j) * Nf + fp)];
     const int32_t code = nbr_t[(uint32_t)(elf * Nf + fp)];
     const FlowDev<T> &fl = flow[s_mesh[elf]];
-    // the common-flux partial of the first phase and |N| are requested with the other loads
+    // the common-flux partial of the first phase (2-D: from LDS) and |N| are requested with the
+    // other loads
     T *fo = fhat_t + (uint32_t)UL::point(elf, fp);
     T fprev[NV], mag = T(0);
     if (side != 0) {
       mag = fnrm_t[(uint32_t)((elf * (D + 1) + D) * Nf + fp)];
-      for (int v = 0; v < NV; ++v) fprev[v] = TL::KEEP_S ? lp[(elf * NV + v) * Nf + fp] : fo[v * UL::VS];
+      for (int v = 0; v < NV; ++v) fprev[v] = TL::KEEP2D ? lp[(elf * NV + v) * Nf + fp] : fo[v * UL::VS];
     }
     bool heat = true, wall = false;
     if (code < 0) {
@@ -473,7 +475,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     for (int k = 0; k < D; ++k) {
       T Sk[D], fi[NV], fv[NV];
       for (int j = 0; j < D; ++j)
-        Sk[j] = TL::KEEP_S ? ls[(el * D * D + k * D + j) * Ns + i]                  // own LDS copy
+        Sk[j] = TL::KEEP2D ? ls[(el * D * D + k * D + j) * Ns + i]                  // own LDS copy
                            : metric_t[(uint32_t)((el * NM + k * D + j) * Ns + i)];  // second read
       finv_dot<D>(uv, Sk, ph.gm1, fi);
       fvis_dot<D>(vs, Sk, fv);
