@@ -91,7 +91,8 @@ struct fr_solver {
 
   // device arrays (precision T unless noted)
   void *metric = nullptr;   // [Ne][dim*dim+1][Ns]
-  void *uf = nullptr;       // [Ne][2 dim][face stride]: u_f by face (uf_face_stride)
+  void *uf = nullptr;       // u_f: [Ne][2 dim][face stride] by face where faces fill two lines
+                            // (uf_face_skip), else [Ne][NV][Nf]
   uint8_t *uf_faces = nullptr;  // [Ne] faces (bit f) whose u_f the stage kernels write
   void *fvn = nullptr;      // [Ne][NV][Nf]   viscous normal flux at own flux points (NS)
   void *vol = nullptr;      // [Ne][NV][Ns]   volume divergence (NS)
@@ -119,7 +120,8 @@ struct fr_solver {
   double *force_acc = nullptr;    // [n_mesh][dim]
   int wall_nchunk = 0;            // wall-force partial sums per mesh (chunks of WALL_CHUNK points)
   double *wall_partial = nullptr; // [n_mesh][wall_nchunk][dim]
-  unsigned long long *count = nullptr;  // samples taken
+  unsigned long long *count = nullptr;  // [0] samples taken, [1] probe workgroups done in the
+                                        // current sample (k_probe's ticket)
   int *nonfinite = nullptr;
 
   // time stepping / graphs
