@@ -273,10 +273,13 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
       const bool isR = (code & NBR_R_BIT) != 0;
       const T wn = isR ? wl : wr;  // weight of the neighbour's value; zero on the one-sided LDG's other side
       T un[NV];
-      for (int v = 0; v < NV; ++v) {
-        un[v] = wn != T(0) ? uf[UfLayout<D, P, T>::at(e2, v, f2)] : T(0);
-        uh[v] = isR ? wl * un[v] + wr * uo[v] : wl * uo[v] + wr * un[v];
+      if (wn != T(0)) {  // one branch around the point's NV loads, so that they issue together
+        const T *up = uf + UfLayout<D, P, T>::at(e2, 0, f2);
+        for (int v = 0; v < NV; ++v) un[v] = up[v * UfLayout<D, P, T>::VS];
+      } else {
+        for (int v = 0; v < NV; ++v) un[v] = T(0);
       }
+      for (int v = 0; v < NV; ++v) uh[v] = isR ? wl * un[v] + wr * uo[v] : wl * uo[v] + wr * un[v];
       if (side != 0 && wn != T(0)) {
         // flux side of a one-sided pair: inviscid common flux along n_L plus the penalty, x |N|,
         // into this point's fhat (2-D: its LDS slot); the flux-point phase adds the viscous part
