@@ -193,3 +193,26 @@ def test_trajectory_adjoint_needs_one_stored_sample_per_step():
         with pytest.raises(ValueError, match="max_samples"):
             FRTrajectory.apply(torch.zeros(4, dtype=torch.float64), s, torch.zeros(1, dtype=torch.float64),
                                5, 1, None)
+
+
+def test_algorithmic_bytes_follow_the_face_flags():
+    """The bench's byte model: with the one-sided LDG and faces of at least 256 bytes (3-D p = 4)
+    the stage kernels write u_f only on the pairs' provider faces and the boundary; with smaller
+    faces (2-D p = 4 FP32) or the two-sided LDG every face is written."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    # two hexes sharing one face: 25 flux-point pairs, 250 boundary points
+    Ne, NV, Ns, Nf, npair, nbnd = 2, 5, 125, 150, 25, 250
+    info = (Ne, NV, Ns, Nf, npair, nbnd, 0, 1)
+    one = bench.algorithmic_bytes(info, 3, 8, "ns", 0.5)
+    two = bench.algorithmic_bytes(info, 3, 8, "ns", 0.3)
+    assert one["interp"] == Ne * NV * Ns * 8 + (npair + nbnd) * NV * 8 + Ne
+    assert two["interp"] == Ne * NV * Ns * 8 + Ne * Nf * NV * 8 + Ne
+    assert two["div_rk"] - one["div_rk"] == (Ne * Nf - npair - nbnd) * NV * 8
+    # 2-D p = 4 in FP32: a face is 4 x 5 x 4 = 80 bytes, every face written
+    info2 = (Ne, 4, 25, 20, 5, 30, 0, 1)
+    b2 = bench.algorithmic_bytes(info2, 2, 4, "ns", 0.5)
+    assert b2["interp"] == Ne * 4 * 25 * 4 + Ne * 20 * 4 * 4 + Ne
