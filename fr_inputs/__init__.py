@@ -11,5 +11,5 @@ from .meshes import (  # noqa: F401
 )
 from .fields import (  # noqa: F401
     FlowParams, freestream_params, vortex_params, vortex_state, freestream_state,
-    entropy_wave_state, shear_wave_state, thermal_wave_state, noise_like,
+    entropy_wave_state, shear_wave_state, thermal_wave_state, noise_like, developed_state,
 )

@@ -121,3 +121,53 @@ def thermal_wave_state(x: np.ndarray, theta0: float = 1.0, amp: float = 0.1, k: 
 def noise_like(shape, seed: int, amp: float) -> np.ndarray:
     """Seeded uniform noise in [-amp, amp]."""
     return np.random.default_rng(seed).uniform(-amp, amp, size=shape)
+
+
+def developed_state(x: np.ndarray, fp: FlowParams, seed: int, amp: float = 0.1, n_modes: int = 4,
+                    length: float = 1.0, periods=None, noise: float = 1e-3, mesh=None) -> np.ndarray:
+    """Free stream plus a smooth seeded disturbance with the magnitudes of a developed flow: every
+    velocity component carries a sum of ``n_modes`` Fourier modes of amplitude ``amp`` |U_inf|
+    (wavelengths of order ``length``, integer harmonics along the directions given in ``periods``
+    so that periodic meshes see a periodic field), density and pressure carry modes of relative
+    size ``amp``/2 and ``amp`` gamma M^2, and every point gets seeded uniform noise of ``noise``
+    on the momentum.  Evaluated per mesh (element ranges of ``mesh``) with that mesh's free
+    stream.  Points x [..., Ns, dim] with the element axis first when ``mesh`` is given."""
+    d = fp.dim
+    rng = np.random.default_rng(seed)
+    periods = [None] * d if periods is None else list(periods)
+
+    def modes():
+        ks, phs = [], []
+        for _ in range(n_modes):
+            k = np.empty(d)
+            for j in range(d):
+                if periods[j] is not None:
+                    k[j] = 2 * np.pi * rng.integers(-2, 3) / periods[j]
+                else:
+                    k[j] = 2 * np.pi * rng.uniform(-1.0, 1.0) / length
+            ks.append(k)
+            phs.append(rng.uniform(0, 2 * np.pi))
+        return np.array(ks), np.array(phs)
+
+    def field(xx, ks, phs, a):
+        return sum(a[m] * np.sin(xx @ ks[m] + phs[m]) for m in range(len(phs)))
+
+    vel_modes = [modes() for _ in range(d)]
+    rho_modes, p_modes = modes(), modes()
+    amps = [rng.uniform(0.5, 1.0, n_modes) / np.sqrt(n_modes) for _ in range(d + 2)]
+    ranges = [(0, x.shape[0], 0)] if mesh is None else [
+        (mesh.mesh_elem_begin[k], mesh.mesh_elem_begin[k + 1], k) for k in range(mesh.n_mesh)]
+    out = np.empty(x.shape[:-1] + (d + 2,))
+    for lo, hi, k in ranges:
+        xx = x[lo:hi]
+        U = float(np.linalg.norm(fp.vel_inf[k]))
+        M2 = fp.rho_inf[k] * U * U / (fp.gamma * fp.p_inf[k])
+        vel = np.empty(xx.shape[:-1] + (d,))
+        for j in range(d):
+            vel[..., j] = fp.vel_inf[k][j] + amp * U * field(xx, *vel_modes[j], amps[j])
+        rho = fp.rho_inf[k] * (1.0 + 0.5 * amp * field(xx, *rho_modes, amps[d]))
+        p = fp.p_inf[k] * (1.0 + fp.gamma * M2 * amp * field(xx, *p_modes, amps[d + 1]))
+        out[lo:hi] = _cons(rho, vel, p, fp.gamma)
+    if noise:
+        out[..., 1:-1] += np.random.default_rng(seed + 1000).uniform(-noise, noise, size=out[..., 1:-1].shape)
+    return out

@@ -251,3 +251,81 @@ def test_adjoint_full_size_node_gradient_fd_80x64(gpu):
         worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-300))
     print(f"80x64 node gradient: worst relative FD mismatch over 50 directions {worst:.3e}")
     assert worst <= 1e-4, worst
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trajectory_gradient_3d_cgrid_matches_oracle(precision, gpu):
+    """3-D p = 4 (the headline element type, whose flux-point values use the face-blocked layout)
+    on a small extruded C-grid with a wall, far field and spanwise periodicity: dJ/du0 of the
+    checkpointed trajectory adjoint against reverse-mode autograd of the oracle trajectory, in
+    FP64 and in FP32.  FP32 bound: the probe pressures carry the FP32 rounding of the state,
+    ~ eps_32 rho E ~ 3e-6 absolute, against fluctuations sigma of the series, and the gradient
+    (2/K) sum (p_n - mean p) dp_n/du inherits that relative error, so the bound is
+    2 eps_32 p_inf / sigma."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+    m = fi.c_grid_naca(n_wake=3, n_foil=8, n_normal=3, n_span=2, q=2, camber=0.02, r_out=4.0, x_out=6.0,
+                       h_wall=0.05)
+    fp = fi.freestream_params(3, 0.2, 23000.0, aoa_deg=4.0)
+    probes = [[0.6, 0.4, 0.05]]
+    s = OracleSystem(m, 4, fp, equations="ns", probes=probes)
+    u0 = torch.tensor(fi.developed_state(s.solpt_coords(), fp, 13, periods=[None, None, m.info["span"]]))
+    u0 = u0.permute(0, 2, 1).contiguous()
+    K, C, dt = 6, 4, 5e-4
+    uo = u0.clone().requires_grad_(True)
+    u, ps = uo, []
+    for n in range(K):
+        ps.append(s.probe_pressure(u))
+        u = s.rk4_step(u, torch.tensor([dt], dtype=torch.float64))
+    Jref = _objective(torch.stack(ps))
+    Jref.backward()
+    gref = uo.grad
+    pref = torch.stack(ps).detach()
+    sig = float(pref.std())
+    sol = Solver(m, 4, fp, equations="ns", precision=precision, probes=probes, max_samples=K)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    ug = u0.to(device=gpu, dtype=sol.dtype).clone().requires_grad_(True)
+    P = FRTrajectory.apply(ug, sol, dtt, K, C, None)
+    J = _objective(P)
+    J.backward()
+    err = float((ug.grad.double().cpu() - gref).norm() / gref.norm())
+    dp = float((P.detach().cpu() - pref).abs().max())
+    print(f"3-D C-grid trajectory adjoint {precision}: probe series max diff {dp:.3e} (sigma {sig:.3e}), "
+          f"J {float(J.detach()):.6e} vs {float(Jref.detach()):.6e}, gradient rel L2 vs oracle {err:.3e}")
+    if precision == "fp64":
+        assert dp <= 1e-12 * float(pref.abs().max()), dp
+        assert err <= max(1e-9, 20 * dp / sig), err
+    else:
+        bound = 2 * 6e-8 * float(fp.p_inf[0]) / sig
+        assert err <= bound, (err, bound)
+    sol.close()
+
+
+def test_trajectory_gradient_fp32_2d_matches_oracle(gpu):
+    """The FP32 trajectory adjoint (FP32 state, stage records and reverse sweep; FP64 probe
+    series) on the 2-D cylinder case against the FP64 oracle's autograd, within the bound derived
+    in the 3-D test."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd.adjoint import FRTrajectory
+    m, p, fp, probes = _case()
+    s = OracleSystem(m, p, fp, equations="ns", probes=probes)
+    u0 = torch.tensor(fi.developed_state(s.solpt_coords(), fp, 17)).permute(0, 2, 1).contiguous()
+    K, C, dt = 12, 5, 2e-4
+    uo = u0.clone().requires_grad_(True)
+    u, ps = uo, []
+    for n in range(K):
+        ps.append(s.probe_pressure(u))
+        u = s.rk4_step(u, torch.tensor([dt], dtype=torch.float64))
+    _objective(torch.stack(ps)).backward()
+    gref = uo.grad
+    sig = float(torch.stack(ps).detach().std())
+    sol = Solver(m, p, fp, equations="ns", precision="fp32", probes=probes, max_samples=K)
+    ug = u0.float().to(gpu).clone().requires_grad_(True)
+    _objective(FRTrajectory.apply(ug, sol, torch.tensor([dt], dtype=torch.float64, device=gpu), K, C, None)).backward()
+    err = float((ug.grad.double().cpu() - gref).norm() / gref.norm())
+    bound = 2 * 6e-8 * float(fp.p_inf[0]) / sig
+    print(f"2-D trajectory adjoint fp32: gradient rel L2 vs oracle {err:.3e} (sigma {sig:.3e}, bound {bound:.2e})")
+    assert err <= bound, (err, bound)
+    sol.close()

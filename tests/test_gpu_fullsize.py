@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import fr_inputs as fi
+from cases import rel_l2
 
 pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -82,19 +83,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _tol(s, le, Rref_e, p_inf):
-    """Round-off bound for one element's residual.  R is a difference of flux terms of size
-    ~ p_inf |S| / J, so relative to ||R_e|| round-off is amplified by
-    kappa_flux = p_inf max|S/J| / max|R_e|; the metric terms are differences of node coordinates
-    of size |x| over an element of size h ~ 2 J^(1/d), amplifying by kappa_geo = max|x| / h; the
-    Lagrange derivative and lifting operators have norms ~ (p+1)^2.
-    Bound: 1e-14 (p+1)^2 kappa_flux kappa_geo (about 100 unit round-offs), never below 1e-11."""
-    d = s.dim
-    SJ = (s.geo["S"][le].abs().amax(dim=(-1, -2)) / s.geo["J"][le]).max().item()
-    kappa_flux = p_inf * SJ / max(float(np.abs(Rref_e).max()), 1e-300)
-    h = 2.0 * float(s.geo["J"][le].min()) ** (1.0 / d)
-    kappa_geo = float(s.geo["x_s"][le].abs().max()) / h
-    return max(1e-11, 1e-14 * (s.p + 1) ** 2 * kappa_flux * kappa_geo)
+# Bound on one element's residual, relative L2.  The small parity meshes use 1e-11; the
+# full-size meshes have cells 1e-2 to 1e-3 of their coordinate range (wall cells of the C-grid
+# and the O-grid), and the metric terms, differences of node coordinates over a cell, lose
+# about one more decimal digit there (measured up to 7.7e-12 on the C-grid and 3.9e-11 on the
+# O-grid, against <= 6.2e-13 on the small meshes).
+FULL_SIZE_TOL = 1e-10
 
 
 def test_naca_cgrid_full_size_sampled_residual(gpu):
@@ -127,9 +121,8 @@ def test_naca_cgrid_full_size_sampled_residual(gpu):
         Rp = s.residual(up)
         np.testing.assert_allclose(s.solpt_coords()[le], xs[e], atol=1e-12)
         err = _rel(R[e].numpy(), Rp[le].numpy())
-        tol = _tol(s, le, Rp[le].numpy(), fp.p_inf[0])
-        print(f"element {e} grid {(i, j, k)}: patch of {len(sel)}; residual rel L2 {err:.3e} (bound {tol:.1e})")
-        assert err <= tol, err
+        print(f"element {e} grid {(i, j, k)}: patch of {len(sel)}; residual rel L2 {err:.3e}")
+        assert err <= FULL_SIZE_TOL, err
 
 
 def test_cylinder_ogrid_full_size_sampled_residual_and_fp32(gpu):
@@ -151,28 +144,36 @@ def test_cylinder_ogrid_full_size_sampled_residual_and_fp32(gpu):
         le = int(np.nonzero(sel == e)[0][0])
         Rp = s.residual(u[sel])[le].numpy()
         err = _rel(R[e].numpy(), Rp)
-        tol = _tol(s, le, Rp, fp.p_inf[0])
-        print(f"cylinder element {(ir, it)}: residual rel L2 {err:.3e} (bound {tol:.1e})")
-        assert err <= tol, err
-    # FP32 at full size: one RK4 step against the FP64 GPU step (itself pinned above)
-    dt = torch.tensor([2e-5], dtype=torch.float64, device=gpu)
-    u64 = u.to(gpu).clone()
-    sol.rk_step(u64, dt, 1)
+        print(f"cylinder element {(ir, it)}: residual rel L2 {err:.3e}")
+        assert err <= FULL_SIZE_TOL, err
+    # FP32 at full size: one RK4 step against the oracle's FP64 step, per variable.
+    s_full = OracleSystem(mesh, 4, fp, equations="ns")
     s32 = Solver(mesh, 4, fp, equations="ns", precision="fp32")
-    u32 = u.float().to(gpu).clone()
-    s32.rk_step(u32, dt, 1)
-    # Relative L2 of density, momentum (as one vector: a per-component measure would depend on the
-    # free stream's orientation, and a cross-stream component is ~1e-3 of the momentum) and energy.
-    e2 = ((u32.double() - u64) ** 2).sum(dim=(0, 2))
-    n2 = (u64 ** 2).sum(dim=(0, 2))
+    dt = 2e-5
+    dtg = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    # (a) a state with a developed flow's magnitudes (10 % disturbances on every velocity component)
+    ud = torch.tensor(fi.developed_state(s_full.solpt_coords(), fp, 7)).permute(0, 2, 1).contiguous()
+    uref = s_full.rk4_step(ud, torch.tensor([dt], dtype=torch.float64))
+    u32 = ud.float().to(gpu)
+    s32.rk_step(u32, dtg, 1)
+    e_dev = rel_l2(u32, uref)
+    # (b) the bench's start, a uniform stream with 1e-3 momentum noise: the cross-stream momentum
+    # is noise only, so its error is the absolute FP32 round-off of the pressure term
+    # (~ eps_32 p_inf dt / h) over a norm 1e-3 of the momentum's; reported per component and
+    # against the momentum vector's norm
+    uref_b = s_full.rk4_step(u, torch.tensor([dt], dtype=torch.float64))
+    u32b = u.float().to(gpu)
+    s32.rk_step(u32b, dtg, 1)
+    e2 = ((u32b.double().cpu() - uref_b) ** 2).sum(dim=(0, 2))
+    n2 = (uref_b ** 2).sum(dim=(0, 2))
+    per_comp = (e2 / n2).sqrt().numpy()
     d = sol.dim
-    grouped = [(0, 1), (1, 1 + d), (1 + d, 2 + d)]
-    rel = max(float((e2[a:b].sum() / n2[a:b].sum()).sqrt()) for a, b in grouped)
-    per_comp = (e2 / n2).sqrt().cpu().numpy()
-    whole = float((e2.sum() / n2.sum()).sqrt())
-    print(f"cylinder full size: FP32 vs FP64 after one step rel L2 {rel:.3e} (whole state {whole:.3e}, "
-          f"per component {np.array2string(per_comp, precision=2)})")
-    assert rel <= 1e-5
+    mom_vec = float((e2[1:1 + d].sum() / n2[1:1 + d].sum()).sqrt())
+    print(f"cylinder full size FP32 one step vs oracle: developed state per-variable rel L2 {e_dev:.3e}; "
+          f"uniform-stream start per component {np.array2string(per_comp, precision=2)}, "
+          f"momentum vector {mom_vec:.3e}")
+    assert e_dev <= 1e-5, e_dev
+    assert max(per_comp[0], per_comp[-1], mom_vec) <= 1e-5, per_comp
 
 
 def test_vortex_full_size_20_steps(gpu):

@@ -4,8 +4,10 @@ Tolerances: FP64 relative L2 (max over variables) <= 1e-12 on the state after RK
 (the stated per-step target) and <= 1e-11 on the residual itself (the residual is a difference
 of fluxes ~ p_inf / h, so its round-off is amplified relative to its size; the bound is the
 FP64 unit round-off 1.1e-16 times a conservative 1e5 amplification).  FP32: relative L2 <= 1e-5
-on the state after one step; the residual within 2e-3 relative (FP32 unit round-off 6e-8 times
-the same amplification, rounded up).
+on the state after one step (measured <= 1.4e-6); the residual within 5e-4 relative (measured
+<= 4.9e-5).  p_RMS from the stored FP64 series (two passes about the mean): 1e-9 relative; from
+the running sums once the series capacity is exceeded, where S2/n - (S1/n)^2 cancels
+(p_inf / sigma)^2 ~ 1e8 of its digits: 1e-6.
 """
 import numpy as np
 import pytest
@@ -87,7 +89,7 @@ def test_rk4_fp64_1_and_20_steps_with_probe(name, gpu):
     assert st["n_samples"] == 20
     np.testing.assert_allclose(ser.T, P.numpy(), rtol=1e-12, atol=0)
     pr = P.numpy()
-    np.testing.assert_allclose(st["prms"], pr.std(axis=0), rtol=1e-6, atol=1e-13)
+    np.testing.assert_allclose(st["prms"], pr.std(axis=0), rtol=1e-9, atol=1e-15)
     if s.viscous and (s.bT == 1).any():
         Fm = F.mean(dim=0).numpy()
         scale = np.abs(Fm).max()
@@ -109,7 +111,7 @@ def test_fp32_vs_fp64_oracle(name, gpu):
     e1 = rel_l2(u, uref)
     print(f"{name}: fp32 rhs rel L2 {eR:.3e}, 1 step {e1:.3e}")
     assert e1 <= 1e-5, e1
-    assert eR <= 2e-3, eR
+    assert eR <= 5e-4, eR
 
 
 def test_graph_replay_matches_direct_launches(gpu, monkeypatch):
@@ -234,7 +236,7 @@ def test_small_degree_and_3d_p3(p, dim, eq, bc, gpu):
     assert rel_l2(u, uref) <= 1e-12
     s32 = Solver(m, p, fp, equations=eq, precision="fp32")
     R32 = s32.rhs(u0.float().to(gpu))
-    assert rel_l2(R32, s.residual(u0)) <= 2e-3
+    assert rel_l2(R32, s.residual(u0)) <= 5e-4
     u32 = u0.float().to(gpu).clone()
     s32.rk_step(u32, torch.tensor(dt, dtype=torch.float64, device=gpu), 1)
     torch.cuda.synchronize()
@@ -277,4 +279,4 @@ def test_many_probes_sampling_interval_and_series_cap(gpu):
     st2 = sol.probe_oaspl(p_ref=2e-5)
     assert st2["n_samples"] == 2
     np.testing.assert_allclose(sol.probe_series(8).T, P2.numpy(), rtol=1e-12, atol=0)
-    np.testing.assert_allclose(st2["prms"], P2.numpy().std(axis=0), rtol=1e-6, atol=1e-13)
+    np.testing.assert_allclose(st2["prms"], P2.numpy().std(axis=0), rtol=1e-9, atol=1e-15)

@@ -3,7 +3,8 @@ autograd of the FP64 oracle on the same seeded inputs, plus a dot-product test a
 differences of the GPU residual itself.
 
 Tolerance: FP64 relative L2 <= 1e-10 (a VJP chains one more round of flux-derivative arithmetic
-than the residual, whose own bound is 1e-11); FP32 <= 5e-3.
+than the residual, whose own bound is 1e-11); FP32 <= 1.5e-3 (measured <= 1.3e-4); the FP32
+node adjoint <= 2e-5 (measured <= 1.4e-6).
 """
 import numpy as np
 import pytest
@@ -72,7 +73,7 @@ def test_rhs_vjp_fp32(name, gpu):
     sol.rhs_vjp(u0.float().to(gpu), rbar.float().to(gpu), ub)
     err = rel_l2(ub, ref)
     print(f"{name}: vjp fp32 rel L2 {err:.3e}")
-    assert err <= 5e-3, err
+    assert err <= 1.5e-3, err
 
 
 @pytest.mark.parametrize("name", ["ns_ogrid", "euler_farfield_curved"])
@@ -144,7 +145,7 @@ def test_rhs_vjp_node_adjoint_fp32(name, gpu):
     sol.rhs_vjp(u0.float().to(gpu), rbar.float().to(gpu), ub, x_bar=xb)
     err = float((xb.cpu() - ref).norm() / ref.norm())
     print(f"{name}: node adjoint fp32 rel L2 {err:.3e}")
-    assert err <= 5e-3, err
+    assert err <= 2e-5, err
 
 
 @pytest.mark.parametrize("name", ["ns_ogrid", "ns_cgrid_p4", "ns_cavity_batch"])
@@ -232,7 +233,7 @@ def test_probe_vjp_many_probes_sharing_elements(precision, gpu):
     torch.cuda.synchronize()
     # FP32: the state itself is rounded, and d p / d xi sums derivative weights (zero sum) over a
     # near-uniform state, so x_bar gets the node-adjoint FP32 bar of the residual VJP tests
-    tol_u, tol_x = (1e-10, 1e-10) if precision == "fp64" else (1e-5, 5e-3)
+    tol_u, tol_x = (1e-10, 1e-10) if precision == "fp64" else (1e-6, 3e-4)
     eu = rel_l2(ub, ref_u)
     ex = float((xb.cpu() - ref_x).norm() / ref_x.norm())
     print(f"{precision}: probe vjp u_bar {eu:.3e}, x_bar {ex:.3e}")
