@@ -61,12 +61,17 @@ def log(msg):
 
 
 # ------------------------------------------------------------------------------------ workloads
-def naca_workload(scale: float = 1.0, seed: int = 2):
+def naca_workload(scale: float = 1.0, seed: int = 2, cells=None):
+    """The seeded C-grid workload: 200 x 80 x 12 hexes at scale 1 (2 x 40 wake + 120 around the
+    section, 80 normal, 12 spanwise); ``cells`` = (n_wake, n_foil, n_normal, n_span) overrides the
+    scaled counts (the section, angle of attack and extents stay those of the seed)."""
     import fr_inputs as fi
     rng = np.random.default_rng(seed)
     aoa = float(rng.uniform(0.0, 6.0))
     nw, nf, nn, ns = (max(2, int(round(40 * scale))), max(4, int(round(120 * scale))),
                       max(2, int(round(80 * scale))), max(2, int(round(12 * scale))))
+    if cells is not None:
+        nw, nf, nn, ns = cells
     m = fi.c_grid_naca(n_wake=nw, n_foil=nf, n_normal=nn, n_span=ns, q=2, seed=seed)
     fp = fi.freestream_params(3, 0.2, 23000.0, aoa_deg=aoa)
     return m, fp, aoa
@@ -270,10 +275,12 @@ def adjoint_ratio(K=200, C=20):
     sol = Solver(m, 3, fp, equations="ns", probes=probe, max_samples=K, forces=False)
     u0 = initial_state(sol, fp, m, 9).cuda()
     dt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
-    # warm-up (graph capture, work allocation)
-    ug = u0.clone().requires_grad_(True)
-    P = FRTrajectory.apply(ug, sol, dt, 4, 2, None)
-    ((P - P.mean(0)) ** 2).mean(0).sum().backward()
+    # warm-up with the timed shapes (graph capture, work and record-buffer allocation)
+    X = torch.tensor(m.node_xyz, dtype=torch.float64, device="cuda", requires_grad=True)
+    for nodes in (None, X):
+        ug = u0.clone().requires_grad_(True)
+        P = FRTrajectory.apply(ug, sol, dt, K, C, nodes)
+        ((P - P.mean(0)) ** 2).mean(0).sum().backward()
     torch.cuda.synchronize()
     ug = u0.clone().requires_grad_(True)
     t0 = time.perf_counter()
