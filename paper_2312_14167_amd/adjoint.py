@@ -3,13 +3,39 @@
 Forward: K RK4 steps of the FR residual from u_0 with the probe pressure sampled before every
 step (p_n = p(u_n), n = 0..K-1), keeping the state every `checkpoint_every` steps.  Backward:
 segment by segment in reverse, the segment's states and RK stage states are recomputed from its
-checkpoint in one fr_rk_step_stages call, then each step is reversed with fr_rk_step_vjp and the probe
+checkpoint in one fr_rk_step_stages call (on a second stream, overlapping the reverse sweep of
+the segment after it), then each step is reversed with fr_rk_step_vjp and the probe
 adjoint fr_probe_vjp:  u_bar_n = (du_{n+1}/du_n)^T u_bar_{n+1} + (dp_n/du_n)^T p_bar_n.
 All arithmetic runs in the library's kernels; torch provides the tensors and the tape.
 """
 from __future__ import annotations
 
 import torch
+
+
+_SIDE_STREAMS = {}
+
+
+def _side_stream(dev):
+    """One extra stream per device (default priority) for the recompute of checkpoint segments."""
+    key = torch.device(dev).index
+    if key not in _SIDE_STREAMS:
+        _SIDE_STREAMS[key] = torch.cuda.Stream(device=dev)
+    return _SIDE_STREAMS[key]
+
+
+def _record_slots(sol, C, nslot, with_res, dev):
+    """Record buffers of the reverse sweep (base states, stage states, stage residuals of C steps),
+    kept on the solver and reused by later backward passes of the same segment length."""
+    key = (C, nslot, with_res, str(dev))
+    cache = sol.__dict__.setdefault("_adjoint_slots", {})
+    if key not in cache:
+        cache[key] = [{"u": torch.empty(sol.shape, dtype=sol.dtype, device=dev),
+                       "states": torch.empty((C,) + sol.shape, dtype=sol.dtype, device=dev),
+                       "stages": torch.empty((C, 3) + sol.shape, dtype=sol.dtype, device=dev),
+                       "res": torch.empty((C, 4) + sol.shape, dtype=sol.dtype, device=dev) if with_res else None}
+                      for _ in range(nslot)]
+    return cache[key]
 
 
 class FRTrajectory(torch.autograd.Function):
@@ -50,22 +76,49 @@ class FRTrajectory(torch.autograd.Function):
         xb = None
         if ctx.with_nodes and ctx.needs_input_grad[5]:
             xb = torch.zeros((sol.n_node, sol.dim), dtype=torch.float64, device=dev)
-        states = torch.empty((C,) + sol.shape, dtype=sol.dtype, device=dev)      # reused by every segment
-        stages = torch.empty((C, 3) + sol.shape, dtype=sol.dtype, device=dev)
-        res = torch.empty((C, 4) + sol.shape, dtype=sol.dtype, device=dev) if xb is not None else None
+        # Segments in reverse order.  The recompute of a segment needs only its checkpoint, so it
+        # runs on a second stream while the previous (later-in-time) segment is being reversed;
+        # two record slots alternate, and a slot is refilled only after the reverse sweep that
+        # read it has finished.  At adjoint-workload sizes single kernels leave most of the chip
+        # idle, so the two chains overlap; the reverse kernels touch only their own work arrays.
+        segs = [(s0, min(s0 + C, K)) for s0 in range(0, K, C)][::-1]
+        nslot = min(2, len(segs))
+        slots = _record_slots(sol, C, nslot, xb is not None, dev)
+        main = torch.cuda.current_stream(dev)
+        side = _side_stream(dev) if nslot > 1 else main
+        recorded = [torch.cuda.Event() for _ in segs]
+        reversed_ = [torch.cuda.Event() for _ in segs]
         if xb is not None:
-            sol.geo_adjoint_begin()   # metric / normal adjoints of all steps mapped to the nodes once
-        for s0 in reversed(range(0, K, C)):
-            s1 = min(s0 + C, K)
-            u = ctx.ckpts[s0].clone()
-            sol.rk_step_stages(u, dt, stages[:s1 - s0], states=states[:s1 - s0],
-                               residuals=None if res is None else res[:s1 - s0])
+            sol.geo_adjoint_begin(stream=main)   # metric / normal adjoints of all steps mapped to the nodes once
+        side.wait_stream(main)
+
+        def record(i):
+            s0, s1 = segs[i]
+            sl = slots[i % nslot]
+            if i >= nslot:
+                side.wait_event(reversed_[i - nslot])
+            with torch.cuda.stream(side):
+                sl["u"].copy_(ctx.ckpts[s0])
+                sol.rk_step_stages(sl["u"], dt, sl["stages"][:s1 - s0], states=sl["states"][:s1 - s0],
+                                   residuals=None if sl["res"] is None else sl["res"][:s1 - s0], stream=side)
+            recorded[i].record(side)
+
+        for i in range(nslot):
+            record(i)
+        for i, (s0, s1) in enumerate(segs):
+            sl = slots[i % nslot]
+            main.wait_event(recorded[i])
             for n in reversed(range(s0, s1)):
-                sol.rk_step_vjp(states[n - s0], dt, ub, stages[n - s0], x_bar=xb,
-                                residuals=None if res is None else res[n - s0])
-                sol.probe_vjp(states[n - s0], p_bar[n], ub, x_bar=xb)
+                j = n - s0
+                sol.rk_step_vjp(sl["states"][j], dt, ub, sl["stages"][j], x_bar=xb,
+                                residuals=None if sl["res"] is None else sl["res"][j], stream=main)
+                sol.probe_vjp(sl["states"][j], p_bar[n], ub, x_bar=xb, stream=main)
+            reversed_[i].record(main)
+            if i + nslot < len(segs):
+                record(i + nslot)
+        main.wait_stream(side)
         if xb is not None:
-            sol.geo_adjoint_end(xb)
+            sol.geo_adjoint_end(xb, stream=main)
         return ub, None, None, None, None, xb
 
 

@@ -1018,10 +1018,11 @@ struct VjpEngine {
     T *ufbface = fhatbar + nf;
     T *fvnbar = ufbface + nf;
     T *ufbnbr = fvnbar + nf;
-    // the forward flux-point buffer is scratch here: k_vjp_div fills every point of it in
-    // [Ne][NV][Nf] order (the buffer holds either layout), and every forward call starts by
-    // recomputing u_f in its own layout
-    T *uf = (T *)s->uf;
+    // forward flux-point state of the linearisation point, [Ne][NV][Nf], filled by k_vjp_div.
+    // The reverse sweep touches only its own work arrays, so a forward recording of another
+    // state may run concurrently on another stream (the trajectory adjoint overlaps the
+    // recompute of one checkpoint segment with the reverse sweep of the next).
+    T *uf = ufbnbr + nf;
     const T *metric = (const T *)s->metric;
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
     T *Gm = (T *)geo.Gm, *Gn = (T *)geo.Gn;
@@ -1050,7 +1051,7 @@ struct VjpEngine {
 
 // work-array size in elements of the state type
 size_t vjp_work_elems(const fr_solver *s) {
-  return (size_t)s->Ne * s->NV * (s->Ns + 4 * s->Nf);
+  return (size_t)s->Ne * s->NV * (s->Ns + 5 * s->Nf);
 }
 
 // u_bar += (dR/du (u))^T r_bar when rk_a is NULL.  Otherwise the RK4-step adjoint epilogue:
