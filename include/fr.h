@@ -154,6 +154,19 @@ fr_status fr_reset_accumulators(fr_solver *s, void *stream);
  * and allocates the geometric adjoint tables on first use. */
 fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar, double *x_bar, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fr_rhs_vjp without x_bar, u_bar += (dR/du)^T r_bar,
+ * with the same kernels and the same result, whose work area (n_elem * nv * (Ns + 5 Nf) values
+ * of the state dtype) is a library-owned static device buffer of FR_NOALLOC_SCRATCH_BYTES per
+ * GPU instead of a per-solver allocation made on first use.  Allocates and frees nothing.  The
+ * buffer is shared by every call on one GPU and keeps the last call's contents (every value is
+ * written before it is read): calls that overlap in time on one GPU (other streams, other host
+ * threads) race and must be ordered by the caller.  FR_ERR_ARG, before any launch, when the
+ * solver's work area exceeds the buffer (the message gives both sizes) or on NULL / aliased
+ * arguments.  Leaves the solver's forward work arrays untouched. */
+#define FR_NOALLOC_SCRATCH_BYTES (32u << 20)
+fr_status fr_rhs_vjp_noalloc(fr_solver *s, const void *u, const void *r_bar, void *u_bar, void *stream);
+
 /* Counts of the discretisation: info[0..7] = {n_elem, nv, Ns, Nf, n_face_pairs (interior and
  * periodic flux-point pairs), n_boundary_points, n_wall_points, n_mesh}. */
 fr_status fr_solver_info(const fr_solver *s, int64_t info[8]);

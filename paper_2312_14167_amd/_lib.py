@@ -8,6 +8,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfrmi.so")
 
 FR_OK, FR_ERR_ARG, FR_ERR_MESH, FR_ERR_UNSUPPORTED, FR_ERR_HIP, FR_ERR_NONFINITE, FR_ERR_OOM = 0, -1, -2, -3, -4, -5, -6
+FR_NOALLOC_SCRATCH_BYTES = 32 << 20   # include/fr.h
 FR_EULER, FR_NAVIER_STOKES = 0, 1
 FR_FP64, FR_FP32 = 0, 1
 
@@ -60,6 +61,7 @@ def lib() -> C.CDLL:
     L.fr_probe_series.argtypes = [vp, vp, i64, C.POINTER(i64), vp]
     L.fr_reset_accumulators.argtypes = [vp, vp]
     L.fr_rhs_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fr_rhs_vjp_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.fr_solver_info.argtypes = [vp, vp]
     L.fr_profile_enable.argtypes = [vp, i32]
     L.fr_profile_read.argtypes = [vp, vp, vp, vp]
@@ -77,7 +79,8 @@ def lib() -> C.CDLL:
     L.fr_last_error.argtypes = []
     L.fr_last_error.restype = C.c_char_p
     for name in ("fr_build_operators", "fr_state_shape", "fr_solpt_coords", "fr_rhs", "fr_rk_step",
-                 "fr_probe_oaspl", "fr_probe_series", "fr_reset_accumulators", "fr_rhs_vjp", "fr_solver_info",
+                 "fr_probe_oaspl", "fr_probe_series", "fr_reset_accumulators", "fr_rhs_vjp", "fr_rhs_vjp_noalloc",
+                 "fr_solver_info",
                  "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp",
                  "fr_autotune", "fr_geo_adjoint_begin", "fr_geo_adjoint_end", "fr_stats_prms_cumulative",
                  "fr_stats_observer_oaspl", "fr_stats_psd_welch"):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,34 @@ fr_status fail(int code, const std::string &msg) {
       throw FrError(e_ == hipErrorOutOfMemory ? FR_ERR_OOM : FR_ERR_HIP,                     \
                     std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
+
+// Work area of fr_rhs_vjp_noalloc: one per GPU, held until the process ends.  In host code the
+// array's name is only a host-side stand-in; its device address is taken once per device with
+// hipGetSymbolAddress at solver set-up and only that address is handed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)FR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of this device's scratch array (the device must be current); taken once per device
+void acquire_scratch(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) throw FrError(FR_ERR_UNSUPPORTED, "device index beyond 64");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw FrError(FR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = p;
+}
+
+void *scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (dev >= 0 && dev < MAX_DEVICES) ? g_scratch_ptr[dev] : nullptr;
+}
 
 void *dalloc(fr_solver *s, size_t bytes) {
   void *p = nullptr;
@@ -230,6 +259,9 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
       s->h_elem_nodes.assign(mesh->elem_nodes, mesh->elem_nodes + mesh->n_elem * nn);
     }
     s->xsol = std::move(g.xsol);
+    // device work starts here (host-side validation of the mesh and probes is done)
+    HIP_OK(hipGetDevice(&s->device));
+    acquire_scratch(s->device);
     s->metric = upload_real(s, g.metric);
     g.metric.clear();
     g.metric.shrink_to_fit();
@@ -466,6 +498,26 @@ fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl
     if (mean_force)
       for (size_t k = 0; k < frc.size(); ++k) mean_force[k] = cnt > 0 ? frc[k] / (double)cnt : 0.0;
     if (nf) return fail(FR_ERR_NONFINITE, "a sampled probe pressure is not finite");
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_rhs_vjp_noalloc(fr_solver *s, const void *u, const void *r_bar, void *u_bar, void *stream) {
+  if (!s || !u || !r_bar || !u_bar) return fail(FR_ERR_ARG, "NULL argument");
+  if (u_bar == u || u_bar == r_bar) return fail(FR_ERR_ARG, "u_bar must not alias u or r_bar");
+  const size_t need = vjp_work_elems(s) * s->tsize;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(FR_ERR_ARG, "fr_rhs_vjp_noalloc needs " + std::to_string(need) + " bytes of work area; the static "
+                            "buffer holds " + std::to_string(NOALLOC_SCRATCH_BYTES) + " (use fr_rhs_vjp)");
+  void *work = scratch_of(s->device);
+  if (!work) return fail(FR_ERR_HIP, "no scratch address for the solver's device");
+  try {
+    if (!launch_vjp(s, u, r_bar, u_bar, work, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, GeoVjpArgs{},
+                    (hipStream_t)stream))
+      throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+    HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
   }

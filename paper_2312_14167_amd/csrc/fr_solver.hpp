@@ -143,6 +143,7 @@ struct fr_solver {
   int64_t prof_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   // mesh-node adjoint: host copy of the mesh; tables and work arrays uploaded / allocated on first use
+  int device = 0;  // HIP device current at fr_build_operators (all device arrays live there)
   int geom_q = 1;
   int64_t n_node = 0;
   std::vector<double> h_node_xyz;

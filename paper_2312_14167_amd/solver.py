@@ -266,6 +266,16 @@ class Solver:
         check(lib().fr_geo_adjoint_end(self._h, self._xbar_ptr(x_bar), _stream(stream)))
         return x_bar
 
+    def rhs_vjp_noalloc(self, u: torch.Tensor, r_bar: torch.Tensor, u_bar: torch.Tensor, stream=None):
+        """u_bar += (dR/du)^T r_bar with the library's static per-GPU work area (no device
+        allocation; see fr_rhs_vjp_noalloc)."""
+        self._check_state(u, "u")
+        self._check_state(r_bar, "r_bar")
+        self._check_state(u_bar, "u_bar")
+        check(lib().fr_rhs_vjp_noalloc(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(r_bar.data_ptr()),
+                                       C.c_void_p(u_bar.data_ptr()), _stream(stream)))
+        return u_bar
+
     def rhs_vjp(self, u: torch.Tensor, r_bar: torch.Tensor, u_bar: torch.Tensor, x_bar: torch.Tensor | None = None,
                 stream=None):
         self._check_state(u, "u")
