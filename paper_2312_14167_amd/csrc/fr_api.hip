@@ -435,6 +435,37 @@ fr_status fr_reset_accumulators(fr_solver *s, void *stream) {
   return FR_OK;
 }
 
+fr_status fr_force_coefficients(fr_solver *s, int32_t n_dir, const double *dirs, const double *ref_area,
+                                double *coef, void *stream) {
+  if (!s || !dirs || !ref_area || !coef || n_dir < 1) return fail(FR_ERR_ARG, "NULL argument or n_dir < 1");
+  if (!s->forces) return fail(FR_ERR_ARG, "wall forces are not accumulated by this solver (forces = 0)");
+  try {
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    unsigned long long cnt = 0;
+    std::vector<double> frc((size_t)s->n_mesh * s->dim);
+    HIP_OK(hipMemcpy(&cnt, s->count, sizeof(cnt), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(frc.data(), s->force_acc, frc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (cnt == 0) return fail(FR_ERR_ARG, "no samples taken since the last reset");
+    for (int m = 0; m < s->n_mesh; ++m) {
+      double u2 = 0.0;
+      for (int j = 0; j < s->dim; ++j) u2 += s->h_vel[(size_t)m * s->dim + j] * s->h_vel[(size_t)m * s->dim + j];
+      const double q = 0.5 * s->h_rho[m] * u2;
+      if (!(q > 0.0) || !(ref_area[m] > 0.0))
+        return fail(FR_ERR_ARG, "mesh " + std::to_string(m) + ": free-stream dynamic pressure and reference area "
+                                "must be positive");
+      for (int k = 0; k < n_dir; ++k) {
+        const double *e = dirs + ((size_t)m * n_dir + k) * s->dim;
+        double f = 0.0;
+        for (int j = 0; j < s->dim; ++j) f += frc[(size_t)m * s->dim + j] / (double)cnt * e[j];
+        coef[(size_t)m * n_dir + k] = f / (q * ref_area[m]);
+      }
+    }
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
 fr_status fr_probe_series(fr_solver *s, double *series, int64_t cap, int64_t *n, void *stream) {
   if (!s || !n) return fail(FR_ERR_ARG, "NULL argument");
   if (cap < 0 || (cap > 0 && !series)) return fail(FR_ERR_ARG, "bad series buffer");
@@ -611,6 +642,18 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
     if (x_bar) {
       ensure_geo(s);
       if (!s->geo_deferred) zero_geo(s, st);
+    }
+    if (!x_bar || Rs) {  // the fused step sequence (stage residuals at hand when x_bar is wanted)
+      const void *rs[4] = {nullptr, nullptr, nullptr, nullptr};
+      if (x_bar)
+        for (int k = 0; k < 4; ++k) rs[k] = Rs + (size_t)k * nb;
+      if (!launch_vjp_rk_step(s, ys, u_bar, A, dt, x_bar ? rs : nullptr, x_bar ? s->geo_Gm : nullptr,
+                              x_bar ? s->geo_Gn : nullptr, s->vjp_work, st))
+        throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+      if (x_bar && !s->geo_deferred && !launch_geo_nodes(s, x_bar, st))
+        throw FrError(FR_ERR_UNSUPPORTED, "unsupported geometry degree");
+      HIP_OK(hipGetLastError());
+      return FR_OK;
     }
     d.rk_adj_combine(s, A, nullptr, KB, u_bar, Z, cA[3], 0.0, dt, st);  // A = a, KB = dt/6 a, Z = 0
     // each stage's VJP ends in the RK epilogue: u_bar += z_s, KB = k_{s-1}_bar; with x_bar the

@@ -38,6 +38,9 @@ bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar,
                 void *rk_kb, void *rk_ub, double ca, double cz, const double *dt, const GeoVjpArgs &geo,
                 hipStream_t st);
 
+bool launch_vjp_rk_step(const fr_solver *s, const void *const ys[4], void *u_bar, void *A, const double *dt,
+                        const void *const Rs[4], void *Gm, void *Gn, void *work, hipStream_t st);
+
 // mesh-node adjoint (fr_geo.hip): x_bar += (d metrics / d X)^T (Gm, Gn)
 bool launch_geo_nodes(const fr_solver *s, double *x_bar, hipStream_t st);
 

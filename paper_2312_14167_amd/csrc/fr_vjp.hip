@@ -354,14 +354,19 @@ struct VjpDivTile {
 // w = -(1/J) r_bar -> vol_bar (solution points) and F^_bar = Lift^T w (flux points); also the
 // forward flux-point values u_f = M0 u at the linearisation point (read by the face adjoint)
 // GEO: also the adjoint of 1/J, r_bar . R / (1/J) (R the forward residual), into Gm
-template <int D, int P, typename T, bool GEO>
+// RKIN (first reverse stage of an RK4 step): rbar is the step's entry adjoint a, r_bar = dt ca a
+// is formed here and a is copied to rk_a (read by every stage's epilogue)
+template <int D, int P, typename T, bool GEO, bool RKIN = false>
 __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *__restrict__ rbar,
                                                                        const T *__restrict__ u,
                                                                        const T *__restrict__ metric,
                                                                        OpsDev<T, P> ops_arg, T *__restrict__ volbar,
                                                                        T *__restrict__ fhatbar, T *__restrict__ uf,
                                                                        const T *__restrict__ Rf, T *__restrict__ Gm,
-                                                                       int64_t Ne) {
+                                                                       int64_t Ne, T *__restrict__ rk_a = nullptr,
+                                                                       const double *__restrict__ dt = nullptr,
+                                                                       const int32_t *__restrict__ elem_mesh = nullptr,
+                                                                       T ca = T(0)) {
   using S = Shape<D, P>;
   using TL = VjpDivTile<D, P, T>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, NV = S::NV, NM = S::NM;
@@ -375,7 +380,7 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
   // the state tile and this point's operands in one round trip
   TileLoad<E * NV * Ns, TL::BS, T> tu;
   tu.load(u + e0 * NV * Ns, ne * NV * Ns);
-  T invJ = T(0), rb[NV], rf[NV], gprev = T(0);
+  T invJ = T(0), rb[NV], rf[NV], gprev = T(0), scale = T(1);
   if (el < ne) {
     invJ = metric[(e * NM + D * D) * Ns + i];
     for (int v = 0; v < NV; ++v) {
@@ -383,10 +388,16 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
       if (GEO) rf[v] = Rf[(e * NV + v) * Ns + i];
     }
     if (GEO) gprev = Gm[(e * NM + D * D) * Ns + i];
+    if (RKIN) scale = (T)dt[elem_mesh[e]] * ca;
   }
   stage_ops(ops, ops_arg);
   tu.store(lu, ne * NV * Ns);
   if (el < ne) {
+    if (RKIN)
+      for (int v = 0; v < NV; ++v) {
+        rk_a[(e * NV + v) * Ns + i] = rb[v];
+        rb[v] *= scale;
+      }
     T gj = T(0);
     for (int v = 0; v < NV; ++v) {
       const T w = -invJ * rb[v];
@@ -416,7 +427,84 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_div(const T *
   }
 }
 
-// adjoint of the common-flux kernel: u_f_bar of both sides and (NS) the viscous-normal-flux adjoints
+// Adjoint of one interior pair's common flux F^ |N| = [Rusanov(u_L, u_R, n) + tau (u_L - u_R)
+// - viscous share] |N| (written with + on the L side, - on the R side): from the common-flux
+// adjoints of both sides, the u_f adjoints of both sides and (NS) the adjoints of each side's
+// viscous normal flux.  GEO: the adjoint of the unit normal (nb, +=) and of |N| (mb, =).
+template <int D, typename T, bool NS, bool GEO>
+__device__ __forceinline__ void pair_flux_vjp(const T *uL, const T *uR, const T *n, T mag, const T *fhbL,
+                                              const T *fhbR, const PhysDev<T> &ph, T *uLb, T *uRb, T *fvbL,
+                                              T *fvbR, T *nb, T &mb) {
+  constexpr int NV = D + 2;
+  T Fb[NV];
+  for (int v = 0; v < NV; ++v) {
+    Fb[v] = mag * (fhbL[v] - fhbR[v]);
+    uLb[v] = T(0);
+    uRb[v] = T(0);
+  }
+  rusanov_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, uLb, uRb);
+  if (GEO) {
+    // |N|_bar = sum (F^_bar_L - F^_bar_R) . F with F = Rusanov + penalty - viscous part; the
+    // viscous part is added by the volume adjoint, which recomputes each side's fvn
+    T Fr[NV];
+    rusanov_n_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, nb);
+    rusanov<D>(uL, uR, n, ph.gamma, ph.gm1, Fr);
+    mb = T(0);
+    for (int v = 0; v < NV; ++v) mb += Fb[v] * (Fr[v] + (NS ? ph.tau * (uL[v] - uR[v]) : T(0)));
+  }
+  if (NS) {
+    const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
+    for (int v = 0; v < NV; ++v) {
+      uLb[v] += ph.tau * Fb[v];
+      uRb[v] -= ph.tau * Fb[v];
+      fvbL[v] = -wl * Fb[v];
+      fvbR[v] = wr * Fb[v];
+    }
+  }
+}
+
+// Adjoint of a boundary point's common flux (Rusanov against the wall reflection or the far-field
+// state, minus the viscous normal flux): u_f adjoint and (NS) the viscous-normal-flux adjoint.
+template <int D, typename T, bool NS, bool GEO>
+__device__ __forceinline__ void bnd_flux_vjp(const T *uB, const T *n, T mag, const T *fhb, bool wall,
+                                             const FlowDev<T> &fl, const PhysDev<T> &ph, T *uBb, T *fvb, T *nb,
+                                             T &mb) {
+  constexpr int NV = D + 2;
+  T ug[NV], Fb[NV], ugb[NV];
+  for (int v = 0; v < NV; ++v) {
+    Fb[v] = mag * fhb[v];
+    uBb[v] = T(0);
+    ugb[v] = T(0);
+  }
+  if (wall) {
+    ug[0] = uB[0];
+    for (int j = 0; j < D; ++j) ug[1 + j] = -uB[1 + j];
+    ug[D + 1] = uB[D + 1];
+  } else {
+    farfield<D>(uB, n, fl, ph.gamma, ph.gm1, ug);
+  }
+  rusanov_vjp<D>(uB, ug, n, ph.gamma, ph.gm1, Fb, uBb, ugb);
+  if (GEO) rusanov_n_vjp<D>(uB, ug, n, ph.gamma, ph.gm1, Fb, nb);
+  if (wall) {
+    uBb[0] += ugb[0];
+    for (int j = 0; j < D; ++j) uBb[1 + j] -= ugb[1 + j];
+    uBb[D + 1] += ugb[D + 1];
+  } else {
+    farfield_vjp<D>(uB, n, fl, ph.gamma, ph.gm1, ugb, uBb, GEO ? nb : nullptr);
+  }
+  if (GEO) {
+    T Fr[NV];
+    rusanov<D>(uB, ug, n, ph.gamma, ph.gm1, Fr);
+    mb = T(0);
+    for (int v = 0; v < NV; ++v) mb += Fb[v] * Fr[v];
+  }
+  if (NS)
+    for (int v = 0; v < NV; ++v) fvb[v] = -Fb[v];
+}
+
+// adjoint of the common-flux kernel, one thread per pair or boundary point: u_f_bar of both sides
+// and (NS) the viscous-normal-flux adjoints.  (The Navier-Stokes volume adjoint forms the same
+// per side itself; this kernel serves the Euler path.)
 // GEO: also the adjoints of the unit normal (Rusanov, far-field ghost) and the inviscid and
 // penalty part of the adjoint of |N| at the owning point (L side / boundary point), into Gn
 template <int D, int P, typename T, bool NS, bool GEO>
@@ -435,39 +523,28 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
     const int32_t cL = pairL[gid], cR = pairR[gid];
     const int64_t eL = cL / Nf, eR = cR / Nf;
     const int fL = cL % Nf, fR = cR % Nf;
-    T uL[NV], uR[NV], n[D], Fb[NV], uLb[NV], uRb[NV];
-    for (int j = 0; j < D; ++j) n[j] = pnrm[gid * (D + 1) + j];
+    T uL[NV], uR[NV], n[D], fhL[NV], fhR[NV], uLb[NV], uRb[NV], fvL[NV], fvR[NV], nb[D], mb = T(0);
+    for (int j = 0; j < D; ++j) {
+      n[j] = pnrm[gid * (D + 1) + j];
+      nb[j] = T(0);
+    }
     const T mag = pnrm[gid * (D + 1) + D];
     for (int v = 0; v < NV; ++v) {
       uL[v] = uf[(eL * NV + v) * Nf + fL];
       uR[v] = uf[(eR * NV + v) * Nf + fR];
-      Fb[v] = mag * (fhatbar[(eL * NV + v) * Nf + fL] - fhatbar[(eR * NV + v) * Nf + fR]);
-      uLb[v] = T(0);
-      uRb[v] = T(0);
+      fhL[v] = fhatbar[(eL * NV + v) * Nf + fL];
+      fhR[v] = fhatbar[(eR * NV + v) * Nf + fR];
     }
-    rusanov_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, uLb, uRb);
+    pair_flux_vjp<D, T, NS, GEO>(uL, uR, n, mag, fhL, fhR, ph, uLb, uRb, fvL, fvR, nb, mb);
     if (GEO) {
-      // |N|_bar = sum (F^_bar_L - F^_bar_R) . F with F = Rusanov + penalty - viscous part; the
-      // viscous part is added by the volume adjoint, which recomputes each side's fvn
-      T nb[D], Fr[NV];
-      for (int j = 0; j < D; ++j) nb[j] = T(0);
-      rusanov_n_vjp<D>(uL, uR, n, ph.gamma, ph.gm1, Fb, nb);
-      rusanov<D>(uL, uR, n, ph.gamma, ph.gm1, Fr);
-      T mb = T(0);
-      for (int v = 0; v < NV; ++v) mb += Fb[v] * (Fr[v] + (NS ? ph.tau * (uL[v] - uR[v]) : T(0)));
       for (int j = 0; j < D; ++j) Gn[(eL * (D + 1) + j) * Nf + fL] += nb[j];
       Gn[(eL * (D + 1) + D) * Nf + fL] += mb / mag;
     }
-    if (NS) {
-      const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
-      for (int v = 0; v < NV; ++v) {
-        uLb[v] += ph.tau * Fb[v];
-        uRb[v] -= ph.tau * Fb[v];
-        fvnbar[(eL * NV + v) * Nf + fL] = -wl * Fb[v];
-        fvnbar[(eR * NV + v) * Nf + fR] = wr * Fb[v];
-      }
-    }
     for (int v = 0; v < NV; ++v) {
+      if (NS) {
+        fvnbar[(eL * NV + v) * Nf + fL] = fvL[v];
+        fvnbar[(eR * NV + v) * Nf + fR] = fvR[v];
+      }
       ufbar[(eL * NV + v) * Nf + fL] = uLb[v];
       ufbar[(eR * NV + v) * Nf + fR] = uRb[v];
     }
@@ -476,46 +553,24 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
     const int32_t c = bnd[b];
     const int64_t e = c / Nf;
     const int fp = c % Nf;
-    T uB[NV], ug[NV], n[D], Fb[NV], uBb[NV], ugb[NV];
-    for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
+    T uB[NV], n[D], fh[NV], uBb[NV], fv[NV], nb[D], mb = T(0);
+    for (int j = 0; j < D; ++j) {
+      n[j] = bnrm[b * (D + 1) + j];
+      nb[j] = T(0);
+    }
     const T mag = bnrm[b * (D + 1) + D];
     for (int v = 0; v < NV; ++v) {
       uB[v] = uf[(e * NV + v) * Nf + fp];
-      Fb[v] = mag * fhatbar[(e * NV + v) * Nf + fp];
-      uBb[v] = T(0);
-      ugb[v] = T(0);
+      fh[v] = fhatbar[(e * NV + v) * Nf + fp];
     }
-    const bool wall = b < n_wall;
-    const FlowDev<T> fl = flow[elem_mesh[e]];
-    if (wall) {
-      ug[0] = uB[0];
-      for (int j = 0; j < D; ++j) ug[1 + j] = -uB[1 + j];
-      ug[D + 1] = uB[D + 1];
-    } else {
-      farfield<D>(uB, n, fl, ph.gamma, ph.gm1, ug);
-    }
-    rusanov_vjp<D>(uB, ug, n, ph.gamma, ph.gm1, Fb, uBb, ugb);
-    T nb[D];
-    for (int j = 0; j < D; ++j) nb[j] = T(0);
-    if (GEO) rusanov_n_vjp<D>(uB, ug, n, ph.gamma, ph.gm1, Fb, nb);
-    if (wall) {
-      uBb[0] += ugb[0];
-      for (int j = 0; j < D; ++j) uBb[1 + j] -= ugb[1 + j];
-      uBb[D + 1] += ugb[D + 1];
-    } else {
-      farfield_vjp<D>(uB, n, fl, ph.gamma, ph.gm1, ugb, uBb, GEO ? nb : nullptr);
-    }
+    bnd_flux_vjp<D, T, NS, GEO>(uB, n, mag, fh, b < n_wall, flow[elem_mesh[e]], ph, uBb, fv, nb, mb);
     if (GEO) {
-      T Fr[NV];
-      rusanov<D>(uB, ug, n, ph.gamma, ph.gm1, Fr);
-      T mb = T(0);
-      for (int v = 0; v < NV; ++v) mb += Fb[v] * Fr[v];
       for (int j = 0; j < D; ++j) Gn[(e * (D + 1) + j) * Nf + fp] += nb[j];
       Gn[(e * (D + 1) + D) * Nf + fp] += mb / mag;
     }
     for (int v = 0; v < NV; ++v) {
       ufbar[(e * NV + v) * Nf + fp] = uBb[v];
-      if (NS) fvnbar[(e * NV + v) * Nf + fp] = -Fb[v];
+      if (NS) fvnbar[(e * NV + v) * Nf + fp] = fv[v];
     }
   }
 }
@@ -531,18 +586,22 @@ struct VjpVolTile {
   static constexpr int BS = round64(cmax(E * S::Ns, E * S::Nf));
 };
 
-// NS volume adjoint (see the file header); writes the solution-point adjoint ubvol (may alias
-// volbar: each tile reads its vol_bar before writing), the own-flux-point adjoint ufb_own and the
-// neighbour-slot adjoint ufb_nbr
+// NS volume adjoint (see the file header), including the adjoint of the common flux at its own
+// flux points: each point forms its pair's flux adjoint (both sides' u_f and common-flux adjoints,
+// complete before this kernel) and keeps its own side's share, so no face kernel runs and each
+// pair is differentiated once from each side.  Writes the solution-point adjoint ubvol (may alias
+// volbar: each tile reads its vol_bar before writing), the own-flux-point adjoint ufb_own (must
+// not alias fhatbar, which neighbouring tiles read) and the neighbour-slot adjoint ufb_nbr.
 // GEO: also the metric adjoints (S rows from F~_k = S_k . F and from the gradient transform,
-// 1/J from the gradient transform) into Gm, and the unit-normal adjoints of the viscous normal
-// flux and of the far-field states at own flux points into Gn
+// 1/J from the gradient transform) into Gm, and the unit-normal and |N| adjoints of the common
+// flux (at the L point of a pair and at boundary points), of the viscous normal flux and of the
+// far-field states at own flux points into Gn
 template <int D, int P, typename T, bool GEO>
 __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
     const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, const T *volbar,
-    const T *__restrict__ fvnbar, const T *ufb_face, T *ubvol, T *ufb_own, T *__restrict__ ufb_nbr,
+    const T *__restrict__ fhatbar, T *ubvol, T *__restrict__ ufb_own, T *__restrict__ ufb_nbr,
     T *__restrict__ Gm, T *__restrict__ Gn, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = VjpVolTile<D, P, T>;
@@ -652,7 +711,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
   // adjoint of the viscous normal flux at own flux points (one flux point per thread)
   const int ef_idx = threadIdx.x;
   const bool actf = ef_idx < ne * Nf;
-  T gbf[D * NV], stb[NV], nbv[D];
+  T gbf[D * NV], stb[NV], nbv[D], ufa_face[NV];
   for (int j = 0; j < D; ++j) nbv[j] = T(0);
   int fpl = 0, elf = 0;
   if (actf) {
@@ -674,11 +733,47 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
       }
     for (int v = 0; v < NV; ++v) {
       st[v] = luf[(elf * NV + v) * Nf + fpl];
-      fb[v] = fvnbar[(ef * NV + v) * Nf + fpl];
       stb[v] = T(0);
     }
     for (int j = 0; j < D; ++j) n[j] = fnrm[(ef * (D + 1) + j) * Nf + fpl];
     const int32_t code = nbr[ef * Nf + fpl];
+    {  // adjoint of this point's common flux: own u_f adjoint (face part) and fvn adjoint
+      T fho[NV], nbc[D], mbc = T(0), dummy[NV];
+      for (int v = 0; v < NV; ++v) fho[v] = fhatbar[(ef * NV + v) * Nf + fpl];
+      for (int j = 0; j < D; ++j) nbc[j] = T(0);
+      if (code >= 0) {
+        const int32_t c = code & (NBR_R_BIT - 1);
+        const int64_t e2 = c / Nf;
+        const int f2 = c % Nf;
+        const bool isR = (code & NBR_R_BIT) != 0;
+        T un[NV], fhn[NV], nL[D];
+        for (int v = 0; v < NV; ++v) {
+          un[v] = uf[(e2 * NV + v) * Nf + f2];
+          fhn[v] = fhatbar[(e2 * NV + v) * Nf + f2];
+        }
+        for (int j = 0; j < D; ++j) nL[j] = isR ? -n[j] : n[j];  // the pair's L normal (stored as -n_L on R)
+        const T mag = fnrm[(ef * (D + 1) + D) * Nf + fpl];
+        if (isR) {
+          pair_flux_vjp<D, T, true, false>(un, st, nL, mag, fhn, fho, ph, dummy, ufa_face, dummy, fb, nbc, mbc);
+        } else {
+          pair_flux_vjp<D, T, true, GEO>(st, un, nL, mag, fho, fhn, ph, ufa_face, dummy, fb, dummy, nbc, mbc);
+          if (GEO) {
+            for (int j = 0; j < D; ++j) Gn[(ef * (D + 1) + j) * Nf + fpl] += nbc[j];
+            Gn[(ef * (D + 1) + D) * Nf + fpl] += mbc / mag;
+          }
+        }
+      } else {
+        const int64_t b = -(int64_t)code - 1;
+        T nB[D];
+        for (int j = 0; j < D; ++j) nB[j] = bnrm[b * (D + 1) + j];
+        const T mag = bnrm[b * (D + 1) + D];
+        bnd_flux_vjp<D, T, true, GEO>(st, nB, mag, fho, b < n_wall, flow[s_mesh[elf]], ph, ufa_face, fb, nbc, mbc);
+        if (GEO) {
+          for (int j = 0; j < D; ++j) Gn[(ef * (D + 1) + j) * Nf + fpl] += nbc[j];
+          Gn[(ef * (D + 1) + D) * Nf + fpl] += mbc / mag;
+        }
+      }
+    }
     T ub[NV];
     bool heat = true, wall = false;
     int64_t b = -1;
@@ -722,8 +817,7 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
   if (actf) {
     for (int j = 0; j < D; ++j)
       for (int v = 0; v < NV; ++v) lgb[((elf * D + j) * NV + v) * Nf + fpl] = gbf[j * NV + v];
-    const int64_t ef = e0 + elf;
-    for (int v = 0; v < NV; ++v) lub[(elf * NV + v) * Nf + fpl] = stb[v] + ufb_face[(ef * NV + v) * Nf + fpl];
+    for (int v = 0; v < NV; ++v) lub[(elf * NV + v) * Nf + fpl] = stb[v] + ufa_face[v];
   }
   __syncthreads();
   // solution points: F~_bar from vol_bar, pointwise flux adjoints, gradient adjoint
@@ -980,10 +1074,104 @@ __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_final(const T
     const int64_t o = (e * NV + v) * Ns + i;
     if (rk.ub) {
       rk.ub[o] += s;
-      rk.kb[o] = dt * (rk.ca * prev[v] + rk.cz * s);
+      if (rk.kb) rk.kb[o] = dt * (rk.ca * prev[v] + rk.cz * s);
     } else {
       ubar[o] = prev[v] + s;
     }
+  }
+}
+
+// Epilogue of reverse stage k of an RK4 step fused with the first reverse kernel of stage k-1 on
+// the same element tile: z = ubvol + M0^T (ufb_own + ufb_nbr), u_bar += z, and the next stage's
+// r_bar = dt (ca a + cz z) is consumed at once: w = -(1/J) r_bar -> vol_bar, F^_bar = Lift^T w at
+// the flux points, and the flux-point values u_f = M0 y of the next linearisation state y.
+// vol_bar aliases ubvol: each tile reads its own elements' values before the barrier that precedes
+// its writes.  GEO: the adjoint of 1/J of stage k-1 (r_bar . R / (1/J)).
+template <int D, int P, typename T, bool GEO>
+__global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_final_div(
+    const T *ubvol, const T *ufb_own, const T *__restrict__ ufb_nbr, OpsDev<T, P> ops_arg, AdjRK<T> rk,
+    const T *__restrict__ y, const T *__restrict__ metric, T *volbar, T *fhatbar, T *__restrict__ uf,
+    const T *__restrict__ Rf, T *__restrict__ Gm, int64_t Ne) {
+  using S = Shape<D, P>;
+  using TL = VjpDivTile<D, P, T>;
+  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  __shared__ __attribute__((aligned(16))) T lw[E * TL::LE];
+  __shared__ __attribute__((aligned(16))) T lu[E * TL::LE];
+  __shared__ OpsDev<T, P> ops;
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)((Ne - e0) < E ? (Ne - e0) : E);
+  const int el = threadIdx.x / Ns, i = threadIdx.x % Ns;
+  const int64_t e = e0 + el;
+  // the next state's tile and every operand of this point in one round trip
+  TileLoad<E * NV * Ns, TL::BS, T> tu;
+  tu.load(y + e0 * NV * Ns, ne * NV * Ns);
+  int ik[D], fm[D], fpp[D];
+  T sv[NV], am[NV][D], ap[NV][D], prev[NV], rf[NV];
+  T invJ = T(0), gprev = T(0), dt = T(0);
+  if (el < ne) {
+    for (int k = 0; k < D; ++k) {
+      int base, stride, t;
+      line_of_sol<D, P>(i, k, base, stride, ik[k], t);
+      fm[k] = (2 * k) * Nfp + t;
+      fpp[k] = (2 * k + 1) * Nfp + t;
+    }
+    dt = (T)rk.dt[rk.elem_mesh[e]];
+    invJ = metric[(e * NM + D * D) * Ns + i];
+    for (int v = 0; v < NV; ++v) {
+      const int64_t o = (e * NV + v) * Ns + i;
+      sv[v] = ubvol[o];
+      const T *fo = ufb_own + (e * NV + v) * Nf;
+      for (int k = 0; k < D; ++k) {
+        am[v][k] = fo[fm[k]];
+        ap[v][k] = fo[fpp[k]];
+      }
+      if (ufb_nbr) {
+        const T *fn = ufb_nbr + (e * NV + v) * Nf;
+        for (int k = 0; k < D; ++k) {
+          am[v][k] += fn[fm[k]];
+          ap[v][k] += fn[fpp[k]];
+        }
+      }
+      prev[v] = rk.a[o];
+      if (GEO) rf[v] = Rf[o];
+    }
+    if (GEO) gprev = Gm[(e * NM + D * D) * Ns + i];
+  }
+  stage_ops(ops, ops_arg);
+  tu.store(lu, ne * NV * Ns);
+  __syncthreads();
+  if (el < ne) {
+    T gj = T(0);
+    for (int v = 0; v < NV; ++v) {
+      T z = sv[v];
+      for (int k = 0; k < D; ++k) z += ops.lm[ik[k]] * am[v][k] + ops.lp[ik[k]] * ap[v][k];
+      const int64_t o = (e * NV + v) * Ns + i;
+      rk.ub[o] += z;
+      const T rb = dt * (rk.ca * prev[v] + rk.cz * z);
+      const T w = -invJ * rb;
+      lw[(el * NV + v) * Ns + i] = w;
+      volbar[o] = w;
+      if (GEO) gj += rb * rf[v];
+    }
+    if (GEO) Gm[(e * NM + D * D) * Ns + i] = gprev + gj / invJ;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ne * NV * Nf; idx += blockDim.x) {
+    const int fp = idx % Nf, rest = idx / Nf;
+    int base, stride, side;
+    line_of_fpt<D, P>(fp, base, stride, side);
+    const T *g = side ? ops.gp : ops.gm;
+    const T *lv = side ? ops.lp : ops.lm;
+    const T *lin = lw + rest * Ns + base;
+    const T *lun = lu + rest * Ns + base;
+    T sw = T(0), su = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      sw += g[a] * lin[a * stride];
+      su += lv[a] * lun[a * stride];
+    }
+    fhatbar[e0 * NV * Nf + idx] = sw;
+    uf[e0 * NV * Nf + idx] = su;
   }
 }
 
@@ -1031,20 +1219,74 @@ struct VjpEngine {
     k_vjp_div<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, u, metric, o, volbar, fhatbar, uf, Rf, Gm, Ne);
     const int64_t nface = s->npair + s->nbnd;
     if (s->equations == 1) {
-      k_vjp_face<D, P, T, true, GEO><<<vblk(nface, 256), 256, 0, st>>>(
-          uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-          s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, fvnbar, Gn);
       using TV = VjpVolTile<D, P, T>;
       k_vjp_ns_vol<D, P, T, GEO><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
           u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
-          volbar, fvnbar, ufbface, volbar, fhatbar, ufbnbr, Gm, Gn, Ne);
-      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, fhatbar, ufbnbr, o, ubar, rk, Ne);
+          volbar, fhatbar, volbar, ufbface, ufbnbr, Gm, Gn, Ne);
+      k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, ufbnbr, o, ubar, rk, Ne);
     } else {
       k_vjp_face<D, P, T, false, GEO><<<vblk(nface, 256), 256, 0, st>>>(
           uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
           s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr, Gn);
       k_vjp_euler_vol<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(u, metric, o, ph, volbar, volbar, Gm, Ne);
       k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, nullptr, o, ubar, rk, Ne);
+    }
+  }
+};
+
+// The reverse sweep of one RK4 step (stages 4..1): the first stage's div kernel forms its r_bar
+// from the entry adjoint (no separate combine kernel), and every later stage's div work is fused
+// into the epilogue of the stage before it; with the face adjoint inside the Navier-Stokes volume
+// adjoint a step is 1 + 4 x 2 = 9 launches (Euler: 1 + 4 x 3).
+template <int D, int P, typename T>
+struct VjpStepEngine {
+  using S = Shape<D, P>;
+  template <bool GEO>
+  static void run(const fr_solver *s, const T *const ys[4], T *ub, T *A, const double *dt, const T *const Rs[4],
+                  T *Gm, T *Gn, T *work, hipStream_t st) {
+    const OpsDev<T, P> o = make_ops<T, P>(s->ops);
+    PhysDev<T> ph;
+    ph.gamma = (T)s->gamma;
+    ph.gm1 = (T)(s->gamma - 1.0);
+    ph.prandtl = (T)s->prandtl;
+    ph.beta = (T)s->beta;
+    ph.tau = (T)s->tau;
+    ph.side = ldg_side_of<T>(s->beta);
+    const int64_t Ne = s->Ne, nsol = Ne * S::NV * S::Ns, nf = Ne * S::NV * S::Nf;
+    T *volbar = work, *fhatbar = volbar + nsol, *ufbface = fhatbar + nf, *fvnbar = ufbface + nf;
+    T *ufbnbr = fvnbar + nf, *uf = ufbnbr + nf;
+    const T *metric = (const T *)s->metric;
+    const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
+    static const double cA[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    static const double cZ[4] = {0.5, 0.5, 1.0, 0.0};
+    using TD = VjpDivTile<D, P, T>;
+    using TV = VjpVolTile<D, P, T>;
+    const bool ns = s->equations == 1;
+    k_vjp_div<D, P, T, GEO, true><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(
+        ub, ys[3], metric, o, volbar, fhatbar, uf, GEO ? Rs[3] : nullptr, Gm, Ne, A, dt, s->elem_mesh, (T)cA[3]);
+    const int64_t nface = s->npair + s->nbnd;
+    for (int k = 3; k >= 0; --k) {
+      T *own = ufbface;  // own flux-point adjoint (NS volume adjoint, or the Euler face adjoint)
+      T *nbr = ns ? ufbnbr : nullptr;
+      if (ns) {
+        k_vjp_ns_vol<D, P, T, GEO><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
+            ys[k], uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o,
+            ph, volbar, fhatbar, volbar, ufbface, ufbnbr, Gm, Gn, Ne);
+      } else {
+        k_vjp_face<D, P, T, false, GEO><<<vblk(nface, 256), 256, 0, st>>>(
+            uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
+            s->n_wall, s->nbnd, s->elem_mesh, fl, ph, ufbface, nullptr, Gn);
+        k_vjp_euler_vol<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(ys[k], metric, o, ph, volbar, volbar,
+                                                                          Gm, Ne);
+      }
+      if (k > 0) {
+        AdjRK<T> rk{A, nullptr, ub, dt, s->elem_mesh, (T)cA[k - 1], (T)cZ[k - 1]};
+        k_vjp_final_div<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(
+            volbar, own, nbr, o, rk, ys[k - 1], metric, volbar, fhatbar, uf, GEO ? Rs[k - 1] : nullptr, Gm, Ne);
+      } else {
+        AdjRK<T> rk{A, nullptr, ub, dt, s->elem_mesh, T(0), T(0)};
+        k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, own, nbr, o, nullptr, rk, Ne);
+      }
     }
   }
 };
@@ -1078,6 +1320,36 @@ bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar,
   FR_VCASE(2, 2) FR_VCASE(2, 3) FR_VCASE(2, 4) FR_VCASE(2, 5)
   FR_VCASE(3, 2) FR_VCASE(3, 3) FR_VCASE(3, 4) FR_VCASE(3, 5)
 #undef FR_VCASE
+  return false;
+}
+
+// u_bar <- (d u_{n+1} / d u_n)^T u_bar for one RK4 step with stage states ys[0..3] (ys[0] = u_n);
+// A: state-sized scratch for the entry adjoint.  With Gm / Gn (mesh-node adjoint) the stage
+// residuals Rs[0..3] are required.
+bool launch_vjp_rk_step(const fr_solver *s, const void *const ys[4], void *u_bar, void *A, const double *dt,
+                        const void *const Rs[4], void *Gm, void *Gn, void *work, hipStream_t st) {
+#define FR_SCASE(DD, PP)                                                                                  \
+  if (s->dim == DD && s->p + 1 == PP) {                                                                   \
+    if (s->precision == 0) {                                                                              \
+      using T = double;                                                                                   \
+      const T *y[4] = {(const T *)ys[0], (const T *)ys[1], (const T *)ys[2], (const T *)ys[3]};           \
+      const T *r[4] = {nullptr, nullptr, nullptr, nullptr};                                               \
+      if (Rs) for (int k = 0; k < 4; ++k) r[k] = (const T *)Rs[k];                                         \
+      if (Gm) VjpStepEngine<DD, PP, T>::run<true>(s, y, (T *)u_bar, (T *)A, dt, r, (T *)Gm, (T *)Gn, (T *)work, st); \
+      else VjpStepEngine<DD, PP, T>::run<false>(s, y, (T *)u_bar, (T *)A, dt, r, nullptr, nullptr, (T *)work, st); \
+    } else {                                                                                              \
+      using T = float;                                                                                    \
+      const T *y[4] = {(const T *)ys[0], (const T *)ys[1], (const T *)ys[2], (const T *)ys[3]};           \
+      const T *r[4] = {nullptr, nullptr, nullptr, nullptr};                                               \
+      if (Rs) for (int k = 0; k < 4; ++k) r[k] = (const T *)Rs[k];                                         \
+      if (Gm) VjpStepEngine<DD, PP, T>::run<true>(s, y, (T *)u_bar, (T *)A, dt, r, (T *)Gm, (T *)Gn, (T *)work, st); \
+      else VjpStepEngine<DD, PP, T>::run<false>(s, y, (T *)u_bar, (T *)A, dt, r, nullptr, nullptr, (T *)work, st); \
+    }                                                                                                     \
+    return true;                                                                                          \
+  }
+  FR_SCASE(2, 2) FR_SCASE(2, 3) FR_SCASE(2, 4) FR_SCASE(2, 5)
+  FR_SCASE(3, 2) FR_SCASE(3, 3) FR_SCASE(3, 4) FR_SCASE(3, 5)
+#undef FR_SCASE
   return false;
 }
 

@@ -99,13 +99,18 @@ def test_rk_step_vjp_recompute_equals_recorded_stages(gpu):
     st2 = torch.empty_like(st)
     sol.rk_step_stages(u0.clone(), dtt, st2, residuals=res)
     assert torch.equal(st2, st)
-    xbs = []
+    # u_bar in the node-adjoint mode: the same value to rounding (the mode's extra normal and |N|
+    # terms share subexpressions with the state adjoint, so the compiler contracts a few products
+    # into FMAs differently), and bit-identical among the mode's three ways of getting the stages
+    xbs, bs = [], []
     for stages, residuals in [(st2, res), (None, None), (st2, None)]:
         b = a.clone()
         xb = torch.zeros((sol.n_node, 2), dtype=torch.float64, device=gpu)
         sol.rk_step_vjp(u0, dtt, b, stages, x_bar=xb, residuals=residuals)
-        assert torch.equal(b, b1)
+        assert float((b - b1).norm() / b1.norm()) <= 1e-14
+        bs.append(b)
         xbs.append(xb)
+    assert torch.equal(bs[0], bs[1]) and torch.equal(bs[0], bs[2])
     assert torch.equal(xbs[0], xbs[1])
     assert float((xbs[2] - xbs[0]).norm() / xbs[0].norm()) <= 1e-13
 
