@@ -137,6 +137,17 @@ fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, i
 fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl, double *mean_force,
                          int64_t *n_samples, void *stream);
 
+/* Force coefficients of Eq. (8) (cavity drag; the airfoil's lift and drag): synchronise, then
+ * coef[m*n_dir + k] = (time-mean wall force of mesh m) . dirs[(m*n_dir + k)*dim ...]
+ *                     / (1/2 rho_inf,m |U_inf,m|^2 ref_area[m])
+ * for n_dir caller-chosen directions per mesh (host arrays: dirs [n_mesh][n_dir][dim], unit
+ * vectors, e.g. along and normal to the free stream; ref_area [n_mesh], e.g. chord x span; coef
+ * [n_mesh][n_dir]).  The mean force is the FP64 sum of fr_probe_oaspl's mean_force.  FR_ERR_ARG
+ * when the solver accumulates no forces, no sample was taken since the last reset, or an area or
+ * free-stream dynamic pressure is not positive. */
+fr_status fr_force_coefficients(fr_solver *s, int32_t n_dir, const double *dirs, const double *ref_area,
+                                double *coef, void *stream);
+
 /* Synchronise and copy the FP64 pressure series series[a*cap + k] for k < min(n, cap, max_samples);
  * *n = samples taken since the last reset (the device keeps the first max_samples of them). */
 fr_status fr_probe_series(fr_solver *s, double *series, int64_t cap, int64_t *n, void *stream);

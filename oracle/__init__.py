@@ -24,5 +24,5 @@ Parity status per function is listed in ``oracle/PINS.md``.
 from .basis import (  # noqa: F401
     gauss_legendre, lagrange_eval, lagrange_deriv, correction_deriv, gll_nodes, TensorOps,
 )
-from .fr import OracleSystem, oaspl_from_series, cumulative_prms  # noqa: F401
+from .fr import OracleSystem, airfoil_objective, cumulative_prms, force_coefficients, oaspl_from_series  # noqa: F401
 from .spectra import observer_oaspl, welch_psd  # noqa: F401

@@ -292,3 +292,27 @@ def oaspl_from_series(p: np.ndarray, p_ref: float) -> float:
     prms = cumulative_prms(p)[-1]
     with np.errstate(divide="ignore"):
         return float(20.0 * np.log10(prms / p_ref))
+
+
+def force_coefficients(force: np.ndarray, rho_inf, vel_inf, directions: np.ndarray, ref_area) -> np.ndarray:
+    """Force coefficients of Eq. (8): the time-mean wall force of each mesh projected on each
+    given unit direction, over the free-stream dynamic pressure 1/2 rho_inf |U_inf|^2 times the
+    reference area (span times length).  force [n_mesh][dim], rho_inf [n_mesh],
+    vel_inf [n_mesh][dim], directions [n_mesh][n_dir][dim], ref_area [n_mesh] -> [n_mesh][n_dir]."""
+    force = np.asarray(force, float)
+    q = 0.5 * np.asarray(rho_inf, float) * np.sum(np.asarray(vel_inf, float) ** 2, axis=-1)
+    out = np.empty(np.asarray(directions).shape[:2])
+    for m in range(force.shape[0]):
+        for j in range(out.shape[1]):
+            out[m, j] = float(np.dot(force[m], directions[m][j])) / (q[m] * float(ref_area[m]))
+    return out
+
+
+def airfoil_objective(oaspl, cl, cd, cl_base, cd_base, eps1: float = 8000.0, eps2: float = 400000.0):
+    """Penalised objective of the airfoil optimisation: OASPL plus eps1 times the squared departure
+    of the mean lift coefficient from the baseline's, plus eps2 times the squared excess of the
+    mean drag coefficient when it is above the baseline's (eps1 = 8000, eps2 = 400000)."""
+    f = float(oaspl) + eps1 * (float(cl) - cl_base) ** 2
+    if float(cd) > cd_base:
+        f += eps2 * (float(cd) - cd_base) ** 2
+    return f

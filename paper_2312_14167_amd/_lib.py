@@ -59,6 +59,7 @@ def lib() -> C.CDLL:
     L.fr_rk_step.argtypes = [vp, vp, vp, i32, i32, vp]
     L.fr_probe_oaspl.argtypes = [vp, dbl, vp, vp, vp, C.POINTER(i64), vp]
     L.fr_probe_series.argtypes = [vp, vp, i64, C.POINTER(i64), vp]
+    L.fr_force_coefficients.argtypes = [vp, i32, vp, vp, vp, vp]
     L.fr_reset_accumulators.argtypes = [vp, vp]
     L.fr_rhs_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fr_rhs_vjp_noalloc.argtypes = [vp, vp, vp, vp, vp]
@@ -79,7 +80,7 @@ def lib() -> C.CDLL:
     L.fr_last_error.argtypes = []
     L.fr_last_error.restype = C.c_char_p
     for name in ("fr_build_operators", "fr_state_shape", "fr_solpt_coords", "fr_rhs", "fr_rk_step",
-                 "fr_probe_oaspl", "fr_probe_series", "fr_reset_accumulators", "fr_rhs_vjp", "fr_rhs_vjp_noalloc",
+                 "fr_probe_oaspl", "fr_probe_series", "fr_force_coefficients", "fr_reset_accumulators", "fr_rhs_vjp", "fr_rhs_vjp_noalloc",
                  "fr_solver_info",
                  "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp",
                  "fr_autotune", "fr_geo_adjoint_begin", "fr_geo_adjoint_end", "fr_stats_prms_cumulative",

@@ -2,7 +2,8 @@
 camber, its chordwise position, thickness, angle of attack) gets its own extruded C-grid, the
 meshes are concatenated into one batched solver (one launch per kernel for all candidates), all
 candidates advance together, and each candidate's OASPL at its observer, mean lift and drag
-coefficients and penalised objective are computed from the FP64 probe series and wall force.
+coefficients (Eq. (8), computed by the library) and penalised objective are computed from the
+FP64 probe series and wall force.
 """
 from __future__ import annotations
 
@@ -51,12 +52,12 @@ def naca_poll(designs, grid: dict, p: int, steps: int, dt: float, mach: float = 
     sol.reset_accumulators()
     sol.rk_step(ut, dtt, steps, sample_every=sample_every)
     st = sol.probe_oaspl(p_ref=p_ref_pa * fp.p_inf[0] / 101325.0)
-    F = st["mean_force"]                                   # [n_mesh, 3], force on the walls
-    q = 0.5 * np.asarray(fp.rho_inf) * np.linalg.norm(np.asarray(fp.vel_inf), axis=1) ** 2
+    # Eq. (8) in the library: drag along the free stream, lift normal to it in the x-y plane,
+    # reference area chord (1) x span
     ed = np.asarray(fp.vel_inf) / np.linalg.norm(np.asarray(fp.vel_inf), axis=1, keepdims=True)
     el = np.stack([-ed[:, 1], ed[:, 0], np.zeros(nm)], axis=1)
-    cd = (F * ed).sum(1) / (q * span)
-    cl = (F * el).sum(1) / (q * span)
+    c = sol.force_coefficients(np.stack([ed, el], axis=1), np.full(nm, span))
+    cd, cl = c[:, 0], c[:, 1]
     out = {"oaspl": st["oaspl"], "cl": cl, "cd": cd, "n_samples": st["n_samples"],
            "finite": bool(torch.isfinite(ut).all())}
     if cl_base is not None and cd_base is not None:

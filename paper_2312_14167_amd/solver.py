@@ -132,6 +132,23 @@ class Solver:
         return {"prms": prms[:self.n_probe], "oaspl": oaspl[:self.n_probe],
                 "mean_force": force.reshape(self.n_mesh, self.dim), "n_samples": int(n.value)}
 
+    def force_coefficients(self, directions, ref_area, stream=None) -> np.ndarray:
+        """Eq. (8): time-mean wall force of each mesh along each direction over the free-stream
+        dynamic pressure times ref_area.  directions [n_mesh][n_dir][dim] (or [n_dir][dim] for
+        all meshes), ref_area scalar or [n_mesh] -> [n_mesh][n_dir]."""
+        d = np.asarray(directions, dtype=np.float64)
+        if d.ndim == 2:
+            d = np.broadcast_to(d, (self.n_mesh,) + d.shape)
+        d = np.ascontiguousarray(d)
+        if d.shape[0] != self.n_mesh or d.shape[2] != self.dim:
+            raise ValueError("directions must be [n_mesh][n_dir][dim]")
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(ref_area, dtype=np.float64), (self.n_mesh,)))
+        out = np.zeros((self.n_mesh, d.shape[1]))
+        check(lib().fr_force_coefficients(self._h, int(d.shape[1]), d.ctypes.data_as(C.c_void_p),
+                                          a.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p),
+                                          _stream(stream)))
+        return out
+
     def probe_series(self, cap: int, stream=None) -> np.ndarray:
         out = np.zeros((max(self.n_probe, 1), cap))
         n = C.c_int64()
