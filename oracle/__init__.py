@@ -16,6 +16,8 @@ What it computes and where the paper fixes it:
   LDG viscous common fluxes, adiabatic no-slip walls, Riemann-invariant far field;
 * drag coefficient Eq. (8); OASPL, RMS and cumulative mean, Eqs. (9)-(12); the spanwise
   observer average and the Welch spectra of the case sections (``spectra.py``);
+* a solution degree per element (the airfoil case's P0-P4 sponge, ``vardeg.py``), with
+  mixed-degree faces read as mortars on the higher side's flux points;
 * classical RK4 time stepping with a given dt (the paper's own integrator is a
   second-order optimal scheme whose coefficients it does not print).
 
@@ -26,3 +28,4 @@ from .basis import (  # noqa: F401
 )
 from .fr import OracleSystem, airfoil_objective, cumulative_prms, force_coefficients, oaspl_from_series  # noqa: F401
 from .spectra import observer_oaspl, welch_psd  # noqa: F401
+from .vardeg import VarDegreeOracle  # noqa: F401
