@@ -7,7 +7,7 @@ fluxes); both the oracle and the HIP path compute those on their own.
 """
 from .meshes import (  # noqa: F401
     FACE_AUTO, BC_WALL, BC_FARFIELD,
-    MeshDesc, gll_points, periodic_box, o_grid, cavity, c_grid_naca, concat_meshes,
+    MeshDesc, gll_points, periodic_box, o_grid, cavity, c_grid_naca, concat_meshes, sponge_degrees,
 )
 from .fields import (  # noqa: F401
     FlowParams, freestream_params, vortex_params, vortex_state, freestream_state,

@@ -490,3 +490,16 @@ def concat_meshes(meshes) -> MeshDesc:
                     face_bc=np.concatenate(fbs), periodic_vec=pv.copy(),
                     mesh_elem_begin=np.array(begins, dtype=np.int64),
                     info={"kind": "batch", "parts": [m.info for m in meshes]})
+
+
+def sponge_degrees(mesh: MeshDesc, radii=(0.5, 1.0, 2.0, 3.0), p_max: int = 4) -> np.ndarray:
+    """Solution degree per element falling with distance from the chord segment (0, 0)-(1, 0) in
+    the x-y plane: p_max inside radii[0], one less per band, 0 beyond the last radius (the
+    airfoil case's sponge: high degree at the airfoil, degree 0 towards the outer boundaries).
+    The distance is the element centroid's (mean of its nodes) in-plane distance, so on an
+    extruded mesh the degree is constant along the span."""
+    c = mesh.node_xyz[mesh.elem_nodes].mean(axis=1)
+    x, y = c[:, 0], c[:, 1]
+    dist = np.hypot(x - np.clip(x, 0.0, 1.0), y)
+    band = np.searchsorted(np.asarray(radii, float), dist, side="right")
+    return np.clip(p_max - band, 0, p_max).astype(np.int64)

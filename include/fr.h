@@ -271,6 +271,55 @@ fr_status fr_stats_psd_welch(const double *series, int64_t n, int32_t n_windows,
 /* Release everything the handle owns (NULL is a no-op). */
 void fr_destroy(fr_solver *s);
 
+/*
+ * Variable solution degree (the sponge of the airfoil case's computational details: the
+ * degree falls from 4 or 3 near the airfoil to 0 towards the outer boundaries so that outgoing
+ * waves are damped before they reach them).  The paper gives the distribution, not the face
+ * treatment; the one built here:
+ *  - every element is FR of its own degree p_e in 0..4 (Gauss-Legendre points, g_DG
+ *    correction; degree 0 is one point with correction derivative 1/2: a finite-volume cell);
+ *  - faces between equal degrees are treated as in fr_build_operators;
+ *  - a face between degrees p_lo < p_hi is a mortar on the higher side's flux points: the lower
+ *    side's trace polynomial is evaluated there, the LDG common solution and the common flux
+ *    (Rusanov + LDG with each side's own viscous normal flux carried to the mortar, penalty
+ *    tau) are formed there with the higher side's normal and |N|; the higher side takes them at
+ *    its own points, the lower side their L2 projections onto its face polynomials (Gauss
+ *    quadrature on the mortar points), so each face's integrated flux is the same from both
+ *    sides (conservative).  Free-stream preserving where the face normal is a polynomial of
+ *    degree <= p_lo along the face (faces along z of an extruded mesh with in-plane degrees).
+ * Restrictions: Navier-Stokes, one mesh (n_mesh <= 1), probes in that mesh; the adjoint entry
+ * points take single-degree solvers only.
+ *
+ * fr_vdeg_build: mesh as for fr_build_operators (its p is ignored); elem_degree[n_elem] in
+ *   0..4 (host, read during the call); params as for fr_build_operators.  FR_ERR_UNSUPPORTED
+ *   for Euler or several meshes, FR_ERR_MESH for a face between degrees that is not conforming.
+ * State layout (device, precision of params): one buffer holding the degree groups in
+ *   increasing degree; group g starts at value offset[g] and is [n_elem[g]][dim+2][(degree+1)^dim]
+ *   with its elements in increasing element number (fr_vdeg_group_elems); offset[n_group] is the
+ *   buffer length in values (each group starts on a 64-value boundary; the gaps are not read).
+ * fr_vdeg_groups: n_group, degree[g] (-1 past n_group), n_elem[g], offset[0..5], and the number
+ *   of mortar faces.  fr_vdeg_solpt_coords: xyz[n_elem[g]][(degree+1)^dim][dim] of group g.
+ * fr_vdeg_rhs / fr_vdeg_rk_step / fr_vdeg_reset_accumulators: as fr_rhs / fr_rk_step /
+ *   fr_reset_accumulators on the whole buffer (u and r must not alias; dt is one device double).
+ * fr_vdeg_probe_series: as fr_probe_series, probes in the order given at build.
+ * fr_vdeg_mean_force: mean wall force [dim] over the samples since the last reset (forces != 0),
+ *   *n_samples the number of samples; FR_ERR_NONFINITE if a sampled probe pressure was not finite.
+ */
+typedef struct fr_vdeg fr_vdeg;  /* opaque, library-owned */
+fr_status fr_vdeg_build(const fr_mesh_desc *mesh, const int32_t *elem_degree, const fr_params *params,
+                        fr_vdeg **out);
+fr_status fr_vdeg_groups(const fr_vdeg *v, int32_t *n_group, int32_t degree[5], int64_t n_elem[5],
+                         int64_t offset[6], int64_t *n_mortar);
+fr_status fr_vdeg_group_elems(const fr_vdeg *v, int32_t group, int64_t *elems);
+fr_status fr_vdeg_solpt_coords(const fr_vdeg *v, int32_t group, double *xyz);
+fr_status fr_vdeg_rhs(fr_vdeg *v, const void *u, void *r, void *stream);
+fr_status fr_vdeg_rk_step(fr_vdeg *v, void *u, const double *dt, int32_t n_steps, int32_t sample_every,
+                          void *stream);
+fr_status fr_vdeg_reset_accumulators(fr_vdeg *v, void *stream);
+fr_status fr_vdeg_probe_series(fr_vdeg *v, double *series, int64_t cap, int64_t *n, void *stream);
+fr_status fr_vdeg_mean_force(fr_vdeg *v, double *mean_force, int64_t *n_samples, void *stream);
+void fr_vdeg_destroy(fr_vdeg *v);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *fr_last_error(void);
 

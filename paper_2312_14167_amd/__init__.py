@@ -2,3 +2,4 @@
 C ABI declared in include/fr.h).  The binding loads libfrmi.so and fails loudly if it is absent."""
 from ._lib import FrError, LIB_PATH, lib  # noqa: F401
 from .solver import Solver  # noqa: F401
+from .vardeg import VarDegreeSolver  # noqa: F401

@@ -77,6 +77,17 @@ def lib() -> C.CDLL:
     L.fr_stats_psd_welch.argtypes = [vp, i64, i32, dbl, vp, vp, i64, C.POINTER(i64)]
     L.fr_destroy.argtypes = [vp]
     L.fr_destroy.restype = None
+    L.fr_vdeg_build.argtypes = [C.POINTER(fr_mesh_desc), vp, C.POINTER(fr_params), C.POINTER(vp)]
+    L.fr_vdeg_groups.argtypes = [vp, C.POINTER(i32), vp, vp, vp, C.POINTER(i64)]
+    L.fr_vdeg_group_elems.argtypes = [vp, i32, vp]
+    L.fr_vdeg_solpt_coords.argtypes = [vp, i32, vp]
+    L.fr_vdeg_rhs.argtypes = [vp, vp, vp, vp]
+    L.fr_vdeg_rk_step.argtypes = [vp, vp, vp, i32, i32, vp]
+    L.fr_vdeg_reset_accumulators.argtypes = [vp, vp]
+    L.fr_vdeg_probe_series.argtypes = [vp, vp, i64, C.POINTER(i64), vp]
+    L.fr_vdeg_mean_force.argtypes = [vp, vp, C.POINTER(i64), vp]
+    L.fr_vdeg_destroy.argtypes = [vp]
+    L.fr_vdeg_destroy.restype = None
     L.fr_last_error.argtypes = []
     L.fr_last_error.restype = C.c_char_p
     for name in ("fr_build_operators", "fr_state_shape", "fr_solpt_coords", "fr_rhs", "fr_rk_step",
@@ -84,7 +95,9 @@ def lib() -> C.CDLL:
                  "fr_solver_info",
                  "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp",
                  "fr_autotune", "fr_geo_adjoint_begin", "fr_geo_adjoint_end", "fr_stats_prms_cumulative",
-                 "fr_stats_observer_oaspl", "fr_stats_psd_welch"):
+                 "fr_stats_observer_oaspl", "fr_stats_psd_welch", "fr_vdeg_build", "fr_vdeg_groups",
+                 "fr_vdeg_group_elems", "fr_vdeg_solpt_coords", "fr_vdeg_rhs", "fr_vdeg_rk_step",
+                 "fr_vdeg_reset_accumulators", "fr_vdeg_probe_series", "fr_vdeg_mean_force"):
         getattr(L, name).restype = i32
     _lib = L
     return L

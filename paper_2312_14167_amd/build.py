@@ -16,7 +16,7 @@ LIB = os.path.join(PKG, "libfrmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FRMI_ARCH", "gfx950")
 
-SOURCES = ["fr_host.cpp", "fr_stats.cpp", "fr_kernels.hip", "fr_vjp.hip", "fr_geo.hip", "fr_api.hip"]
+SOURCES = ["fr_host.cpp", "fr_stats.cpp", "fr_kernels.hip", "fr_vjp.hip", "fr_geo.hip", "fr_vardeg.hip", "fr_api.hip"]
 CLANG = os.environ.get("FRMI_CLANG", "/opt/rocm/lib/llvm/bin/clang++")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
           "-I", os.path.join(ROOT, "include"),

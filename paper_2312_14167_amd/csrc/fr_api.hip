@@ -159,12 +159,20 @@ extern "C" {
 
 const char *fr_last_error(void) { return g_err.c_str(); }
 
-fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_solver **out) {
+}  // extern "C"
+
+namespace frmi {
+fr_status set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+// One solver.  group: a degree group of a mesh with several solution degrees (degree 0 allowed,
+// BC_MORTAR faces allowed; built by fr_vdeg_build, never returned through fr_build_operators).
+fr_status build_solver(const fr_mesh_desc *mesh, const fr_params *prm, bool group, fr_solver **out) {
   if (!out) return fail(FR_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!mesh || !prm) return fail(FR_ERR_ARG, "mesh or params is NULL");
   if (mesh->dim != 2 && mesh->dim != 3) return fail(FR_ERR_ARG, "dim must be 2 or 3");
-  if (mesh->p < 1 || mesh->p > 4) return fail(FR_ERR_UNSUPPORTED, "p must be in 1..4");
+  if (mesh->p < (group ? 0 : 1) || mesh->p > 4)
+    return fail(FR_ERR_UNSUPPORTED, group ? "degree must be in 0..4" : "p must be in 1..4");
   if (mesh->geom_q < 1 || mesh->geom_q > 4) return fail(FR_ERR_UNSUPPORTED, "geom_q must be in 1..4");
   if (mesh->n_elem <= 0 || mesh->n_node <= 0 || !mesh->node_xyz || !mesh->elem_nodes || !mesh->face_bc)
     return fail(FR_ERR_ARG, "empty mesh or NULL mesh array");
@@ -211,6 +219,7 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     m.n_periodic = mesh->n_periodic;
     m.periodic_vec = mesh->periodic_vec;
     m.n_mesh = n_mesh;
+    m.allow_mortar = group;
     if (mesh->n_mesh > 1 || mesh->mesh_elem_begin) {
       m.mesh_begin.assign(mesh->mesh_elem_begin, mesh->mesh_elem_begin + n_mesh + 1);
       if (m.mesh_begin[0] != 0 || m.mesh_begin[n_mesh] != mesh->n_elem) throw FrError(FR_ERR_ARG, "bad mesh ranges");
@@ -268,6 +277,7 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
     s->npair = (int64_t)c.pairL.size();
     s->nbnd = (int64_t)c.bnd.size();
     s->n_wall = c.n_wall;
+    s->n_bc = c.n_bc;
     s->pairL = (int32_t *)upload(s, c.pairL);
     s->pairR = (int32_t *)upload(s, c.pairR);
     s->bnd = (int32_t *)upload(s, c.bnd);
@@ -313,6 +323,7 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
       s->fvn = dalloc(s, nf * T);
       s->vol = dalloc(s, nsol * T);
     }
+    if (s->nbnd > s->n_bc) s->ifc_uh = dalloc(s, (size_t)(s->nbnd - s->n_bc) * s->NV * T);
     s->h_probe_pinf = pinf;
     s->probe_elem = (int64_t *)upload(s, pe);
     s->probe_w = (double *)upload(s, pw);
@@ -348,6 +359,13 @@ fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_
   *out = s;
   g_err.clear();
   return FR_OK;
+}
+}  // namespace frmi
+
+extern "C" {
+
+fr_status fr_build_operators(const fr_mesh_desc *mesh, const fr_params *prm, fr_solver **out) {
+  return build_solver(mesh, prm, false, out);
 }
 
 fr_status fr_state_shape(const fr_solver *s, int64_t shape[3]) {

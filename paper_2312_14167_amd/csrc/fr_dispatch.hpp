@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
+
+#include "../../include/fr.h"
 
 #include "fr_solver.hpp"
 
@@ -12,6 +15,12 @@ namespace frmi {
 struct Dispatch {
   void (*rhs)(const fr_solver *, const void *, void *, hipStream_t);
   void (*step)(const fr_solver *, void *, const double *, bool, bool, hipStream_t);
+  // pieces of a residual / RK4 stage for degree-group solvers (part: 1 volume and common-flux
+  // kernels, 2 lifting and RK kernel, 3 both)
+  void (*interp)(const fr_solver *, const void *, hipStream_t);
+  void (*sample_probes)(const fr_solver *, const void *, hipStream_t);
+  void (*rhs_part)(const fr_solver *, const void *, void *, int, hipStream_t);
+  void (*stage_k)(const fr_solver *, void *, const double *, int, bool, int, hipStream_t);
   void (*step_record)(const fr_solver *, void *, const double *, int, void *, void *, void *, hipStream_t);
   void (*probe_vjp)(const fr_solver *, const void *, const double *, void *, double *, hipStream_t);
   void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
@@ -22,6 +31,10 @@ struct Dispatch {
   void (*tile_cands)(int kind, int *E);
 };
 bool get_dispatch(int dim, int p, int precision, Dispatch &out);
+// API layer (fr_api.hip): builds one solver (group: a degree group of a variable-degree mesh) and
+// records an error message for fr_last_error
+fr_status build_solver(const fr_mesh_desc *mesh, const fr_params *prm, bool group, fr_solver **out);
+fr_status set_error(int code, const std::string &msg);
 void launch_fill(double *p, int64_t n, double v, hipStream_t st);
 void launch_fill_state(const fr_solver *s, void *p, int64_t n, hipStream_t st);
 void launch_reset_counters(unsigned long long *count, int *nonfinite, hipStream_t st);

@@ -347,7 +347,7 @@ Connectivity build_connectivity(const MeshIn &m, const Ops1D &o, const Geometry 
   for (int64_t e = 0; e < Ne; ++e)
     for (int f = 0; f < nface; ++f) {
       int32_t tag = m.face_bc[e * nface + f];
-      if (tag != FR_FACE_AUTO && tag != FR_BC_WALL && tag != FR_BC_FARFIELD)
+      if (tag != FR_FACE_AUTO && tag != FR_BC_WALL && tag != FR_BC_FARFIELD && !(m.allow_mortar && tag == BC_MORTAR))
         throw FrError(FR_ERR_ARG, "unknown face tag");
       if (tag == FR_FACE_AUTO) grid[quant(&cent[((size_t)e * nface + f) * 3])].push_back(e * nface + f);
     }
@@ -426,9 +426,10 @@ Connectivity build_connectivity(const MeshIn &m, const Ops1D &o, const Geometry 
       c.pair_nrm.push_back(mag);
     }
   }
-  // boundary flux points: walls first, then far field
-  for (int pass = 0; pass < 2; ++pass) {
-    int want = pass == 0 ? FR_BC_WALL : FR_BC_FARFIELD;
+  // boundary flux points: walls, then far field, then (degree-group solvers) mortar points
+  for (int pass = 0; pass < 3; ++pass) {
+    int want = pass == 0 ? FR_BC_WALL : (pass == 1 ? FR_BC_FARFIELD : BC_MORTAR);
+    if (pass == 2) c.n_bc = (int64_t)c.bnd.size();
     if (pass == 0) c.wall_mesh_begin.assign(m.n_mesh + 1, 0);
     for (int64_t e = 0; e < Ne; ++e)
       for (int f = 0; f < nface; ++f) {
@@ -568,6 +569,22 @@ Probe locate_probe(const MeshIn &m, const Ops1D &o, const double *xp, int mesh) 
     }
   }
   throw FrError(FR_ERR_MESH, "probe is outside every element of its mesh");
+}
+
+std::vector<double> ref_flux_points(int dim, const Ops1D &o) { return ref_fpts(dim, o); }
+
+std::vector<double> map_ref_points(const MeshIn &m, int64_t e, const std::vector<double> &ref) {
+  const int d = m.dim;
+  GeoBasis b = geo_basis(d, m.q, ref);
+  std::vector<double> Xe((size_t)b.nn * d);
+  for (int n = 0; n < b.nn; ++n)
+    for (int j = 0; j < d; ++j) Xe[(size_t)n * d + j] = m.node_xyz[m.elem_nodes[e * b.nn + n] * d + j];
+  std::vector<double> x((size_t)b.npts * d);
+  for (int a = 0; a < b.npts; ++a) {
+    double A[9];
+    map_point(d, b, a, Xe.data(), &x[(size_t)a * d], A);
+  }
+  return x;
 }
 
 GeoAdj build_geo_adj(const MeshIn &m, const Ops1D &o) {

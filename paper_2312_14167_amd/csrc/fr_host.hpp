@@ -12,6 +12,11 @@ namespace frmi {
 // this element is the R side of the pair; < 0 -> boundary point -(code + 1)
 constexpr int32_t NBR_R_BIT = 1 << 30;
 
+// Internal face tag of a degree-group solver: a face whose partner has another solution degree.
+// Its flux points are boundary points after the walls and the far field; their common solution
+// comes from a buffer and their common flux from the mortar kernels of the whole mesh.
+constexpr int32_t BC_MORTAR = 3;
+
 // Thrown by host construction; mapped to an fr_status at the ABI.
 struct FrError : std::runtime_error {
   int code;
@@ -42,6 +47,7 @@ struct MeshIn {
   const double *periodic_vec = nullptr;
   int n_mesh = 1;
   std::vector<int64_t> mesh_begin;  // n_mesh + 1
+  bool allow_mortar = false;        // degree-group solver: BC_MORTAR faces allowed
 };
 
 struct Geometry {
@@ -65,6 +71,7 @@ struct Connectivity {
   std::vector<double> bnd_nrm;    // [nbnd][dim + 1]
   std::vector<double> bnd_w;      // face quadrature weight of the flux point (walls: force integral)
   int64_t n_wall = 0;
+  int64_t n_bc = 0;               // walls + far field; mortar points follow
   std::vector<int64_t> wall_mesh_begin;  // [n_mesh + 1] ranges into the wall list
   std::vector<int32_t> elem_mesh;        // [Ne]
   // per element flux point: partner code (bit 30 set on the R side) or -(boundary index + 1)
@@ -89,6 +96,13 @@ struct Probe {
 };
 
 Probe locate_probe(const MeshIn &m, const Ops1D &ops, const double *xp, int mesh);
+
+// reference coordinates [Nf][dim] of the flux points of degree o.P - 1: face f on coordinate f/2 at
+// side -1 (f even) / +1 (f odd), tangential Gauss points lowest coordinate fastest
+std::vector<double> ref_flux_points(int dim, const Ops1D &o);
+
+// physical coordinates [n][dim] of reference points ref [n][dim] in element e
+std::vector<double> map_ref_points(const MeshIn &m, int64_t e, const std::vector<double> &ref);
 
 // Tables of the mesh-node adjoint: element node coordinates, derivatives of the geometry basis
 // at solution and flux points, and the node -> (element, local node) incidence in a fixed order.

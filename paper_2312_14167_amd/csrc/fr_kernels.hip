@@ -166,12 +166,16 @@ struct TileCands {
 //   state); F~_k = S_k . (F_inv - F_vis) at solution points;
 //   vol = sum_k D~_k F~_k with D~ = D - (interior part of the correction), i.e.
 //   vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f}).
-template <int D, int P, typename T, int EE>
+// MORTAR (a degree group of a mesh with several solution degrees): boundary points from n_bc on
+// lie on faces to another degree; their common solution comes from ifc_uh ([point][NV], written by
+// the mortar kernels), their viscous normal flux is stored like a boundary point's, and their
+// common flux is left to the mortar kernels.
+template <int D, int P, typename T, int EE, bool MORTAR = false>
 __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>::MIN_WAVES)) void k_ns_grad(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
     const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, T *__restrict__ fvn,
-    T *__restrict__ fhat, T *__restrict__ vol, int64_t Ne) {
+    T *__restrict__ fhat, T *__restrict__ vol, int64_t Ne, int64_t n_bc = 0, const T *__restrict__ ifc_uh = nullptr) {
   using S = Shape<D, P>;
   using TL = GradTile<D, P, T, EE>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM, NFACE = 2 * D;
@@ -306,12 +310,15 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
       T n[D];
       for (int j = 0; j < D; ++j) n[j] = bnrm[b * (D + 1) + j];
       const bool wall = b < n_wall;
-      if (wall) {
+      const bool mortar = MORTAR && b >= n_bc;
+      if (mortar) {
+        for (int v = 0; v < NV; ++v) uh[v] = ifc_uh[(b - n_bc) * NV + v];
+      } else if (wall) {
         wall_state<D>(uo, uh);
       } else {
         farfield<D>(uo, n, flow[s_mesh[el]], ph.gamma, ph.gm1, uh);
       }
-      if (side != 0) {
+      if (side != 0 && !mortar) {
         // boundary flux, inviscid part: Rusanov against the ghost (wall reflection / far-field state)
         T ug[NV], F[NV];
         if (wall) {
@@ -419,10 +426,14 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
       mag = fnrm_t[(uint32_t)((elf * (D + 1) + D) * Nf + fp)];
       for (int v = 0; v < NV; ++v) fprev[v] = TL::KEEP2D ? lp[(elf * NV + v) * Nf + fp] : fo[v * UL::VS];
     }
-    bool heat = true, wall = false;
+    bool heat = true, wall = false, mortar = false;
     if (code < 0) {
-      wall = (-(int64_t)code - 1) < n_wall;
-      if (wall) {
+      const int64_t b = -(int64_t)code - 1;
+      wall = b < n_wall;
+      mortar = MORTAR && b >= n_bc;
+      if (mortar) {
+        for (int v = 0; v < NV; ++v) st[v] = uo[v];
+      } else if (wall) {
         wall_state<D>(uo, st);
         heat = false;
       } else {
@@ -447,7 +458,8 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     if (side == 0) continue;
     // complete the common flux started in the first phase (same workgroup, ordered by the barriers)
     if (code < 0) {
-      for (int v = 0; v < NV; ++v) fo[v * UL::VS] = fprev[v] - fv[v] * mag;
+      if (!mortar)
+        for (int v = 0; v < NV; ++v) fo[v * UL::VS] = fprev[v] - fv[v] * mag;
     } else {
       const int32_t c = code & (NBR_R_BIT - 1);
       T *fq = fhat + UL::point((int64_t)(c / Nf), c % Nf);
@@ -1076,8 +1088,10 @@ struct Engine {
   }
 
   // one residual evaluation of `u` whose flux-point values are already in s->uf; the epilogue
-  // `rk` decides what is written
-  static void stage(const fr_solver *s, const T *u, const RKArgs<T> &rk, hipStream_t st, bool force_sample) {
+  // `rk` decides what is written.  part: bit 0 the volume / common-flux kernels, bit 1 the lifting
+  // and RK kernel (a degree group runs the mortar kernels of the whole mesh between the two)
+  static void stage(const fr_solver *s, const T *u, const RKArgs<T> &rk, hipStream_t st, bool force_sample,
+                    int part = 3) {
     const OpsDev<T, P> o = ops(s);
     const PhysDev<T> ph = phys(s);
     const int64_t nface = s->npair + s->nbnd;
@@ -1086,31 +1100,41 @@ struct Engine {
     const FlowDev<T> *fl = (const FlowDev<T> *)s->flow;
     if (s->equations == 1) {
       T *fvn = (T *)s->fvn, *vol = (T *)s->vol;
-      {
+      if (part & 1) {
         ProfScope ps(s, 2, st);
-        auto go = [&](auto tag) {
-          constexpr int EE = decltype(tag)::value;
-          using TL = GradTile<D, P, T, EE>;
-          k_ns_grad<D, P, T, EE><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(
+        if (s->n_bc < s->nbnd) {  // mortar points: degree-group solver, default tile
+          using TL = GradTile<D, P, T, 0>;
+          k_ns_grad<D, P, T, 0, true><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(
               u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o,
-              ph, fvn, fhat, vol, s->Ne);
-        };
-        using C = TileCands<GradTile<D, P, T>::E>;
-        pick_tile<C>(s->tune[0], go);
+              ph, fvn, fhat, vol, s->Ne, s->n_bc, (const T *)s->ifc_uh);
+        } else {
+          auto go = [&](auto tag) {
+            constexpr int EE = decltype(tag)::value;
+            using TL = GradTile<D, P, T, EE>;
+            k_ns_grad<D, P, T, EE><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(
+                u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl,
+                o, ph, fvn, fhat, vol, s->Ne);
+          };
+          using C = TileCands<GradTile<D, P, T>::E>;
+          pick_tile<C>(s->tune[0], go);
+        }
       }
-      if (force_sample && s->forces && s->n_wall > 0) {
+      if ((part & 1) && force_sample && s->forces && s->n_wall > 0) {
         ProfScope ps(s, 7, st);
         k_wall_force<D, P, T><<<dim3((unsigned)s->wall_nchunk, (unsigned)s->n_mesh), WALL_CHUNK, 0, st>>>(
             uf, fvn, s->bnd, (const T *)s->bnd_nrm, s->bnd_w, s->wall_mesh_begin, ph, s->wall_nchunk,
             s->wall_partial);
         k_wall_force_sum<D><<<s->n_mesh, 64, 0, st>>>(s->wall_partial, s->wall_nchunk, s->force_acc);
       }
-      if (ph.side == 0) {  // one-sided LDG: the common flux was formed inside k_ns_grad
+      if ((part & 1) && ph.side == 0 && s->npair + s->n_bc > 0) {
+        // two-sided LDG (the one-sided common flux is formed in k_ns_grad)
         ProfScope ps(s, 3, st);
-        k_face_flux<D, P, T, true><<<nblk(nface, 256), 256, 0, st>>>(
+        // mortar points (after the first n_bc boundary points) are left to the mortar kernels
+        k_face_flux<D, P, T, true><<<nblk(s->npair + s->n_bc, 256), 256, 0, st>>>(
             uf, fvn, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
-            s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
+            s->n_wall, s->n_bc, s->elem_mesh, fl, ph, fhat);
       }
+      if (!(part & 2)) return;
       ProfScope ps(s, 4, st);
       auto go = [&](auto tag) {
         constexpr int EE = decltype(tag)::value;
@@ -1143,6 +1167,32 @@ struct Engine {
     RKArgs<T> rk{};
     rk.r_out = r;
     stage(s, u, rk, st, false);
+  }
+
+  // part of the residual of u (flux-point values already in s->uf) into r
+  static void rhs_part(const fr_solver *s, const T *u, T *r, int part, hipStream_t st) {
+    RKArgs<T> rk{};
+    rk.r_out = r;
+    stage(s, u, rk, st, false, part);
+  }
+
+  // part of stage k of a classical RK4 step of u in place (see step)
+  static void stage_k(const fr_solver *s, T *u, const double *dt, int k, bool sample, int part, hipStream_t st) {
+    static const double cA[4] = {0.5, 0.5, 1.0, 0.0};
+    static const double cB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    RKArgs<T> rk{};
+    rk.u0 = u;
+    rk.acc = (T *)s->acc;
+    rk.ustage = (T *)s->ustage;
+    rk.dt = dt;
+    rk.cA = (T)cA[k];
+    rk.cB = (T)cB[k];
+    rk.first = k == 0;
+    rk.last = k == 3;
+    rk.uf_next = (T *)s->uf;
+    rk.uf_faces = s->uf_faces;
+    const T *ust = k == 0 ? u : (const T *)s->ustage;
+    stage(s, ust, rk, st, sample && k == 0, part);
   }
 
   static void probe(const fr_solver *s, const T *u, hipStream_t st) {
@@ -1196,6 +1246,18 @@ Dispatch make_dispatch() {
   d.step = [](const fr_solver *s, void *u, const double *dt, bool sample, bool fresh, hipStream_t st) {
     Engine<D, P, T>::step(s, (T *)u, dt, sample, fresh, st);
   };
+  d.interp = [](const fr_solver *s, const void *u, hipStream_t st) {
+    Engine<D, P, T>::interp(s, (const T *)u, (T *)s->uf, st);
+  };
+  d.sample_probes = [](const fr_solver *s, const void *u, hipStream_t st) {
+    Engine<D, P, T>::probe(s, (const T *)u, st);
+  };
+  d.rhs_part = [](const fr_solver *s, const void *u, void *r, int part, hipStream_t st) {
+    Engine<D, P, T>::rhs_part(s, (const T *)u, (T *)r, part, st);
+  };
+  d.stage_k = [](const fr_solver *s, void *u, const double *dt, int k, bool sample, int part, hipStream_t st) {
+    Engine<D, P, T>::stage_k(s, (T *)u, dt, k, sample, part, st);
+  };
   // n steps recording each step's base state (states, optional), its three stage states and
   // (residuals, optional) the residuals of its four stages;
   // flux-point values carry over between the steps of one call, as in fr_rk_step
@@ -1248,8 +1310,8 @@ bool get_dispatch(int dim, int p, int precision, Dispatch &out) {
     out = precision == 0 ? make_dispatch<DD, PP, double>() : make_dispatch<DD, PP, float>(); \
     return true;                                                                     \
   }
-  FR_CASE(2, 2) FR_CASE(2, 3) FR_CASE(2, 4) FR_CASE(2, 5)
-  FR_CASE(3, 2) FR_CASE(3, 3) FR_CASE(3, 4) FR_CASE(3, 5)
+  FR_CASE(2, 1) FR_CASE(2, 2) FR_CASE(2, 3) FR_CASE(2, 4) FR_CASE(2, 5)
+  FR_CASE(3, 1) FR_CASE(3, 2) FR_CASE(3, 3) FR_CASE(3, 4) FR_CASE(3, 5)
 #undef FR_CASE
   return false;
 }

@@ -106,6 +106,8 @@ struct fr_solver {
   int32_t *pairL = nullptr, *pairR = nullptr, *bnd = nullptr, *elem_mesh = nullptr;
   int32_t *nbr = nullptr;   // [Ne][Nf] neighbour code of every own flux point
   int64_t npair = 0, nbnd = 0, n_wall = 0;
+  int64_t n_bc = 0;         // walls + far field; boundary points from n_bc on are mortar points
+  void *ifc_uh = nullptr;   // [nbnd - n_bc][NV] common solution at mortar points (degree groups)
   double *bnd_w = nullptr;          // FP64 [nbnd]
   int64_t *wall_mesh_begin = nullptr;  // device [n_mesh+1]
 

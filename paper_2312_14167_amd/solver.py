@@ -20,6 +20,43 @@ def _stream(stream=None):
     return C.c_void_p(stream.cuda_stream)
 
 
+def marshal(mesh, p: int, flow, equations: str, precision: str, probes=None, probe_mesh=None,
+            max_samples: int = 0, forces: bool = False):
+    """fr_mesh_desc and fr_params of a mesh and flow; the arrays they point to are returned too and
+    must stay alive during the build call (the first one is the node array)."""
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+        keep.append(a)
+        return a
+    node = arr(mesh.node_xyz, np.float64)
+    en = arr(mesh.elem_nodes, np.int64)
+    fb = arr(mesh.face_bc, np.int32)
+    pv = arr(np.asarray(mesh.periodic_vec).reshape(-1, mesh.dim), np.float64)
+    mb = arr(mesh.mesh_elem_begin, np.int64)
+    md = fr_mesh_desc(dim=mesh.dim, p=p, geom_q=mesh.q, n_periodic=pv.shape[0], n_elem=en.shape[0],
+                      n_node=node.shape[0], node_xyz=_ptr(node), elem_nodes=_ptr(en), face_bc=_ptr(fb),
+                      periodic_vec=_ptr(pv), n_mesh=mesh.n_mesh, reserved0=0, mesh_elem_begin=_ptr(mb))
+    rho = arr(flow.rho_inf, np.float64)
+    vel = arr(flow.vel_inf, np.float64)
+    pin = arr(flow.p_inf, np.float64)
+    mu = arr(flow.mu, np.float64)
+    npb = 0
+    pxyz = pm = None
+    if probes is not None:
+        pxyz = arr(np.atleast_2d(probes), np.float64)
+        npb = pxyz.shape[0]
+        pm = arr(np.zeros(npb) if probe_mesh is None else probe_mesh, np.int32)
+    prm = fr_params(equations=FR_NAVIER_STOKES if equations == "ns" else FR_EULER,
+                    precision=FR_FP64 if precision == "fp64" else FR_FP32,
+                    gamma=flow.gamma, prandtl=flow.prandtl, ldg_beta=flow.ldg_beta, ldg_tau=flow.ldg_tau,
+                    rho_inf=_ptr(rho), vel_inf=_ptr(vel), p_inf=_ptr(pin), mu=_ptr(mu),
+                    n_probe=npb, max_samples=max(int(max_samples), 1 if npb else 0),
+                    probe_xyz=_ptr(pxyz), probe_mesh=_ptr(pm), forces=1 if forces else 0, reserved0=0)
+    return md, prm, keep
+
+
 class Solver:
     """One FR discretisation (one or several concatenated meshes) on the current GPU.
 
@@ -37,36 +74,9 @@ class Solver:
         self.equations = equations
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
-        keep = []
-
-        def arr(a, dt):
-            a = np.ascontiguousarray(np.asarray(a, dtype=dt))
-            keep.append(a)
-            return a
-        node = arr(mesh.node_xyz, np.float64)
-        en = arr(mesh.elem_nodes, np.int64)
-        fb = arr(mesh.face_bc, np.int32)
-        pv = arr(np.asarray(mesh.periodic_vec).reshape(-1, mesh.dim), np.float64)
-        mb = arr(mesh.mesh_elem_begin, np.int64)
-        md = fr_mesh_desc(dim=mesh.dim, p=p, geom_q=mesh.q, n_periodic=pv.shape[0], n_elem=en.shape[0],
-                          n_node=node.shape[0], node_xyz=_ptr(node), elem_nodes=_ptr(en), face_bc=_ptr(fb),
-                          periodic_vec=_ptr(pv), n_mesh=mesh.n_mesh, reserved0=0, mesh_elem_begin=_ptr(mb))
-        rho = arr(flow.rho_inf, np.float64)
-        vel = arr(flow.vel_inf, np.float64)
-        pin = arr(flow.p_inf, np.float64)
-        mu = arr(flow.mu, np.float64)
-        npb = 0
-        pxyz = pm = None
-        if probes is not None:
-            pxyz = arr(np.atleast_2d(probes), np.float64)
-            npb = pxyz.shape[0]
-            pm = arr(np.zeros(npb) if probe_mesh is None else probe_mesh, np.int32)
-        prm = fr_params(equations=FR_NAVIER_STOKES if equations == "ns" else FR_EULER,
-                        precision=FR_FP64 if precision == "fp64" else FR_FP32,
-                        gamma=flow.gamma, prandtl=flow.prandtl, ldg_beta=flow.ldg_beta, ldg_tau=flow.ldg_tau,
-                        rho_inf=_ptr(rho), vel_inf=_ptr(vel), p_inf=_ptr(pin), mu=_ptr(mu),
-                        n_probe=npb, max_samples=max(int(max_samples), 1 if npb else 0),
-                        probe_xyz=_ptr(pxyz), probe_mesh=_ptr(pm), forces=1 if forces else 0, reserved0=0)
+        md, prm, keep = marshal(mesh, p, flow, equations, precision, probes, probe_mesh, max_samples, forces)
+        node = keep[0]
+        npb = int(prm.n_probe)
         self.n_node = int(node.shape[0])
         self.node_xyz = node.copy()
         self.max_samples = int(prm.max_samples)  # capacity of the device series
