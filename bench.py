@@ -263,6 +263,42 @@ def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None
     return out
 
 
+SPONGE_RADII = (2.0, 4.0, 6.0, 8.0)   # chords from the section: P4 inside 2, P0 beyond 8
+
+
+def run_sponge(mesh, fp, precision, steps, warmup, seed=5):
+    """The C-grid with the sponge's degrees (4 near the section falling to 0 towards the outer
+    boundary and the far wake): one solver per degree group, mortar kernels between degrees, the
+    whole RK4 step one graph; FP64 probe and wall-force sampling every step."""
+    import torch
+    import fr_inputs as fi
+    from paper_2312_14167_amd import VarDegreeSolver
+    deg = fi.sponge_degrees(mesh, radii=SPONGE_RADII)
+    t0 = time.perf_counter()
+    sol = VarDegreeSolver(mesh, deg, fp, precision=precision, probes=mesh.info["probe"][None, :],
+                          max_samples=max(steps + warmup, 1), forces=True)
+    log(f"  built {precision} variable-degree solver in {time.perf_counter() - t0:.1f}s: degrees {sol.degrees}, "
+        f"elements {sol.n_elem}, {sol.n_mortar} mortar faces")
+    parts = []
+    for g, x in enumerate(sol.solpt_coords()):
+        u = fi.freestream_state(x, fp)
+        noise = fi.noise_like(u.shape, seed + g, 1e-3)
+        u[..., 1:-1] += noise[..., 1:-1]
+        parts.append(torch.tensor(u).permute(0, 2, 1).contiguous())
+    u = sol.join(parts)
+    dt = torch.full((1,), 5e-7, dtype=torch.float64, device="cuda")
+    t = time_steps(sol, u, dt, steps, warmup)
+    dof = sum(n * 5 * (p + 1) ** 3 for n, p in zip(sol.n_elem, sol.degrees))
+    f, ns = sol.mean_force()
+    out = {"gdofs": dof * 4 * steps / t / 1e9, "ms_per_step": 1e3 * t / steps, "dof": dof,
+           "degrees": sol.degrees, "elements": sol.n_elem, "mortar_faces": sol.n_mortar,
+           "finite": bool(torch.isfinite(u).all()) and bool(np.isfinite(f).all()), "n_samples": ns}
+    sol.close()
+    del u
+    torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_ratio(K=200, C=20):
     """Forward RK4 trajectory with probe sampling vs its checkpointed adjoint (gradient of the
     time-mean square probe-pressure fluctuation w.r.t. the initial state), cylinder O-grid
@@ -388,7 +424,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 192,000 hexes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["adjoint", "drift", "batched", "fp32"],
+    ap.add_argument("--only", choices=["adjoint", "drift", "batched", "fp32", "sponge"],
                     help="run one secondary measurement alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -420,6 +456,9 @@ def main():
                  "kernels": {k: v[0] / v[1] for k, v in r["kernels"].items()}}
         elif args.only == "drift":
             r = cylinder_precision_drift()
+        elif args.only == "sponge":
+            mesh, fp, aoa = naca_workload(scale=args.scale)
+            r = {pr: run_sponge(mesh, fp, pr, K, W) for pr in ("fp64", "fp32")}
         else:
             bm, bfp, bprobes, counts = cavity_batch()
             r = run_variant(bm, bfp, "fp32", K, W, probes=bprobes, probe_mesh=np.arange(16))
@@ -479,6 +518,15 @@ def main():
         log(f"  {r32['gdofs']:.2f} GDoF-stage/s")
         result["variants"] = {"fp32": {"value": r32["gdofs"], "ms_per_step": r32["ms_per_step"],
                                        "speedup_vs_fp64": r32["gdofs"] / r64["gdofs"], "tiles": r32.get("tiles")}}
+        log(f"sponge: degrees 4 -> 0 with distance from the section (radii {SPONGE_RADII} chords)")
+        sp = {}
+        for pr, ref in (("fp64", r64), ("fp32", r32)):
+            rs_ = run_sponge(mesh, fp, pr, K, W)
+            rs_["step_time_vs_uniform_p4"] = rs_["ms_per_step"] / ref["ms_per_step"]
+            sp[pr] = rs_
+            log(f"  {pr}: {rs_['gdofs']:.2f} GDoF-stage/s, {rs_['ms_per_step']:.2f} ms/step "
+                f"({rs_['step_time_vs_uniform_p4']:.2f} of uniform p=4)")
+        result["variants"]["sponge_p4_to_p0"] = {"radii_chords": list(SPONGE_RADII), **sp}
         del mesh
         log("batched poll: 16 cavities, FP32, one launch per kernel over all meshes")
         bm, bfp, bprobes, counts = cavity_batch()
