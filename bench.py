@@ -247,7 +247,9 @@ def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None
     dt = torch.full((mesh.n_mesh,), 5e-7 if mesh.dim == 3 else 1e-5, dtype=torch.float64, device="cuda")
     tiles = sol.autotune(u, dt, reps=3) if autotune else None
     if tiles:
-        log("  autotuned tiles: " + ", ".join(f"{k} E={v['elements_per_workgroup']}" for k, v in tiles.items()))
+        log("  autotuned: " + ", ".join(f"{k} E={v['elements_per_workgroup']} waves={v['waves_per_simd_bound'] or 'default'} "
+                                         f"{v['engine']}{' (remembered)' if v['from_cache'] else ''}"
+                                         for k, v in tiles.items()))
     t = time_steps(sol, u, dt, steps, warmup)
     info = solver_info(sol)
     dof = info[0] * info[1] * info[2]
@@ -296,6 +298,32 @@ def run_sponge(mesh, fp, precision, steps, warmup, seed=5):
     sol.close()
     del u
     torch.cuda.empty_cache()
+    return out
+
+
+def mfma_comparison(mesh, fp, steps, warmup, seed=5):
+    """FP32 headline with the NS volume kernel's divergence on the vector ALU and on the matrix
+    cores (v_mfma_f32_16x16x4f32), at the same tile sizes and register budget: ms per step and
+    the volume kernel's average launch time for each."""
+    import torch
+    from paper_2312_14167_amd import Solver
+    sol = Solver(mesh, 4, fp, equations="ns", precision="fp32", probes=mesh.info["probe"][None, :],
+                 max_samples=max(steps + warmup, 1) * 8, forces=True)
+    u0 = initial_state(sol, fp, mesh, seed).to(device="cuda", dtype=sol.dtype)
+    dt = torch.full((1,), 5e-7, dtype=torch.float64, device="cuda")
+    cands = sol.tune_candidates(0)
+    out = {}
+    for c, (E, Wb, eng) in enumerate(cands):
+        if Wb != 0 or E == cands[2][0] and c == 2:
+            continue
+        sol.tune_select(0, c)
+        u = u0.clone()
+        t = time_steps(sol, u, dt, steps, warmup)
+        kern = kernel_profile(sol, u, dt, max(2, min(steps, 5)))
+        name = f"{'mfma' if eng else 'valu'}_E{E}"
+        out[name] = {"ms_per_step": 1e3 * t / steps, "ns_grad_avg_ms": kern["ns_grad"][0] / kern["ns_grad"][1]}
+        log(f"  {name}: {out[name]['ms_per_step']:.3f} ms/step, volume kernel {out[name]['ns_grad_avg_ms']:.4f} ms")
+    sol.close()
     return out
 
 
@@ -424,7 +452,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 192,000 hexes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["adjoint", "drift", "batched", "fp32", "sponge"],
+    ap.add_argument("--only", choices=["adjoint", "drift", "batched", "fp32", "sponge", "mfma"],
                     help="run one secondary measurement alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -456,6 +484,9 @@ def main():
                  "kernels": {k: v[0] / v[1] for k, v in r["kernels"].items()}}
         elif args.only == "drift":
             r = cylinder_precision_drift()
+        elif args.only == "mfma":
+            mesh, fp, aoa = naca_workload(scale=args.scale)
+            r = mfma_comparison(mesh, fp, K, W)
         elif args.only == "sponge":
             mesh, fp, aoa = naca_workload(scale=args.scale)
             r = {pr: run_sponge(mesh, fp, pr, K, W) for pr in ("fp64", "fp32")}

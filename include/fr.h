@@ -233,16 +233,29 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
 fr_status fr_geo_adjoint_begin(fr_solver *s, void *stream);
 fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream);
 
-/* Tile-shape autotuner.  For each volume kernel of the solver's equations (Navier-Stokes: the
- * volume kernel and the lifting + RK kernel; Euler: the volume + RK kernel) it times the candidate
- * tile sizes (elements per workgroup: the default, its half and its quarter) with `reps` RK4 steps
- * each on a device copy of u (u is not modified), keeps the fastest, and drops the captured step
- * graphs so that the next fr_rk_step re-captures them.  Synchronises `stream`; allocates and frees
- * one state-sized scratch copy.  tiles[3] (host, nullable): chosen elements per workgroup for
- * kinds {NS volume, NS lifting + RK, Euler volume + RK}; ms[3][3] (host, nullable): measured ms
- * per RK4 step of each candidate (0 where not tried).  FR_ERR_ARG for reps < 1. */
-fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *tiles, double *ms,
+/* Autotuner.  For each volume kernel of the solver's equations (kind 0: NS volume kernel, 1: NS
+ * lifting + RK kernel, 2: Euler volume + RK kernel) the candidates are the tile sizes (elements
+ * per workgroup: the default, its half and its quarter) times two register budgets (the default
+ * and one alternative waves-per-SIMD launch bound), and for kind 0 in FP32 3-D p = 4 the volume
+ * divergence on the matrix cores; degree-0 groups have the default only.  fr_autotune times each
+ * candidate with `reps` RK4 steps on a device copy of u (u is not modified), keeps the fastest,
+ * remembers it for the rest of the process under (dim, p, precision, equations, LDG form, kind,
+ * floor(log2 n_elem)) -- a later solver with the same key takes the remembered choice without
+ * timing -- and drops the captured step graphs so that the next fr_rk_step re-captures them.
+ * Synchronises `stream`; allocates and frees one state-sized scratch copy when it times.
+ * choice[3][4] (host, nullable): per kind (elements per workgroup, waves-per-SIMD bound or 0 for
+ * the compiler's default, engine 0 vector ALU / 1 matrix cores, 1 if taken from the remembered
+ * choices); ms[3][FR_TUNE_MAX] (host, nullable): ms per RK4 step of each candidate (0 where not
+ * timed).  FR_ERR_ARG for reps < 1.
+ * fr_tune_candidates: the candidates of `kind`, cand[FR_TUNE_MAX][3] as in choice, *n of them.
+ * fr_tune_select: use candidate `index` of `kind` from now on (drops the step graphs).
+ * fr_tune_cache_clear: forget the remembered choices. */
+#define FR_TUNE_MAX 8
+fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *choice, double *ms,
                       void *stream);
+fr_status fr_tune_candidates(const fr_solver *s, int32_t kind, int32_t *cand, int32_t *n);
+fr_status fr_tune_select(fr_solver *s, int32_t kind, int32_t index);
+void fr_tune_cache_clear(void);
 
 /* Host statistics of FP64 probe pressure series (no solver, no device; plain host arrays).
  *

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(_PKG, "libfrmi.so")
 
 FR_OK, FR_ERR_ARG, FR_ERR_MESH, FR_ERR_UNSUPPORTED, FR_ERR_HIP, FR_ERR_NONFINITE, FR_ERR_OOM = 0, -1, -2, -3, -4, -5, -6
 FR_NOALLOC_SCRATCH_BYTES = 32 << 20   # include/fr.h
+FR_TUNE_MAX = 8                       # include/fr.h
 FR_EULER, FR_NAVIER_STOKES = 0, 1
 FR_FP64, FR_FP32 = 0, 1
 
@@ -70,6 +71,10 @@ def lib() -> C.CDLL:
     L.fr_rk_step_stages.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.fr_autotune.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.fr_tune_candidates.argtypes = [vp, i32, vp, C.POINTER(i32)]
+    L.fr_tune_select.argtypes = [vp, i32, i32]
+    L.fr_tune_cache_clear.argtypes = []
+    L.fr_tune_cache_clear.restype = None
     L.fr_geo_adjoint_begin.argtypes = [vp, vp]
     L.fr_geo_adjoint_end.argtypes = [vp, vp, vp]
     L.fr_stats_prms_cumulative.argtypes = [vp, i64, vp]
@@ -94,7 +99,7 @@ def lib() -> C.CDLL:
                  "fr_probe_oaspl", "fr_probe_series", "fr_force_coefficients", "fr_reset_accumulators", "fr_rhs_vjp", "fr_rhs_vjp_noalloc",
                  "fr_solver_info",
                  "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp",
-                 "fr_autotune", "fr_geo_adjoint_begin", "fr_geo_adjoint_end", "fr_stats_prms_cumulative",
+                 "fr_autotune", "fr_tune_candidates", "fr_tune_select", "fr_geo_adjoint_begin", "fr_geo_adjoint_end", "fr_stats_prms_cumulative",
                  "fr_stats_observer_oaspl", "fr_stats_psd_welch", "fr_vdeg_build", "fr_vdeg_groups",
                  "fr_vdeg_group_elems", "fr_vdeg_solpt_coords", "fr_vdeg_rhs", "fr_vdeg_rk_step",
                  "fr_vdeg_reset_accumulators", "fr_vdeg_probe_series", "fr_vdeg_mean_force"):

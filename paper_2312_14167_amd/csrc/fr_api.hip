@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -56,6 +57,32 @@ void acquire_scratch(int dev) {
 void *scratch_of(int dev) {
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   return (dev >= 0 && dev < MAX_DEVICES) ? g_scratch_ptr[dev] : nullptr;
+}
+
+// Autotuner choices of this process, keyed by what decides them: dimension, degree, precision,
+// equations, LDG form, kernel kind and the mesh size's power of two
+struct TuneKey {
+  int dim, p, precision, equations, side, kind, bucket;
+  bool operator<(const TuneKey &o) const {
+    const int a[7] = {dim, p, precision, equations, side, kind, bucket};
+    const int b[7] = {o.dim, o.p, o.precision, o.equations, o.side, o.kind, o.bucket};
+    for (int i = 0; i < 7; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return false;
+  }
+};
+struct TuneEntry {
+  int choice = 0;
+  double ms[FR_TUNE_MAX] = {};
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune_cache;
+
+TuneKey tune_key(const fr_solver *s, int kind) {
+  int bucket = 0;
+  while (((int64_t)1 << (bucket + 1)) <= s->Ne) ++bucket;
+  const int side = s->precision == FR_FP64 ? ldg_side_of<double>(s->beta) : ldg_side_of<float>(s->beta);
+  return TuneKey{s->dim, s->p, s->precision, s->equations, side, kind, bucket};
 }
 
 void *dalloc(fr_solver *s, size_t bytes) {
@@ -723,7 +750,7 @@ fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream) {
   return FR_OK;
 }
 
-fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *tiles, double *ms,
+fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *choice, double *ms,
                       void *stream) {
   if (!s || !u || !dt) return fail(FR_ERR_ARG, "NULL argument");
   if (reps < 1) return fail(FR_ERR_ARG, "reps must be >= 1");
@@ -733,25 +760,41 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
   try {
     Dispatch d = dispatch_of(s);
     const size_t nb = (size_t)s->Ne * s->NV * s->Ns * s->tsize;
-    HIP_OK(hipMalloc(&tmp, nb));
-    HIP_OK(hipEventCreate(&a));
-    HIP_OK(hipEventCreate(&b));
     const int kinds_ns[2] = {0, 1}, kinds_eu[1] = {2};
     const int *kinds = s->equations == FR_NAVIER_STOKES ? kinds_ns : kinds_eu;
     const int nk = s->equations == FR_NAVIER_STOKES ? 2 : 1;
-    double times[3][3];
-    for (int k = 0; k < 3; ++k)
-      for (int c = 0; c < 3; ++c) times[k][c] = 0.0;
+    double times[3][FR_TUNE_MAX] = {};
+    int cached[3] = {0, 0, 0};
     const int prof = s->profiling;
     s->profiling = 0;
     for (int q = 0; q < nk; ++q) {
       const int kind = kinds[q];
-      int E[3];
-      d.tile_cands(kind, E);
+      int32_t cand[FR_TUNE_MAX * 3];
+      const int nc = d.tune_cands(kind, cand);
+      const TuneKey key = tune_key(s, kind);
+      {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+          s->tune[kind] = it->second.choice;
+          for (int c = 0; c < FR_TUNE_MAX; ++c) times[kind][c] = it->second.ms[c];
+          cached[kind] = 1;
+          continue;
+        }
+      }
+      if (!tmp) {
+        HIP_OK(hipMalloc(&tmp, nb));
+        HIP_OK(hipEventCreate(&a));
+        HIP_OK(hipEventCreate(&b));
+      }
       double best = 1e300;
       int best_c = 0;
-      for (int c = 0; c < 3; ++c) {
-        if (c > 0 && (E[c] == E[c - 1] || (c == 2 && E[2] == E[0]))) continue;
+      for (int c = 0; c < nc; ++c) {
+        bool dup = false;  // tile halves and quarters coincide for small defaults
+        for (int c2 = 0; c2 < c; ++c2)
+          dup = dup || (cand[3 * c] == cand[3 * c2] && cand[3 * c + 1] == cand[3 * c2 + 1] &&
+                        cand[3 * c + 2] == cand[3 * c2 + 2]);
+        if (dup) continue;
         s->tune[kind] = c;
         HIP_OK(hipMemcpyAsync(tmp, u, nb, hipMemcpyDeviceToDevice, st));
         d.step(s, tmp, dt, false, true, st);  // warm-up (first launch of this variant)
@@ -768,21 +811,29 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
         }
       }
       s->tune[kind] = best_c;
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      TuneEntry &en = g_tune_cache[key];
+      en.choice = best_c;
+      for (int c = 0; c < FR_TUNE_MAX; ++c) en.ms[c] = times[kind][c];
     }
     s->profiling = prof;
-    free_graphs(s);  // captured steps must use the chosen tiles
-    if (tiles)
+    free_graphs(s);  // captured steps must use the chosen candidates
+    if (choice)
       for (int k = 0; k < 3; ++k) {
-        int E[3];
-        d.tile_cands(k, E);
-        tiles[k] = E[s->tune[k]];
+        int32_t cand[FR_TUNE_MAX * 3];
+        const int nc = d.tune_cands(k, cand);
+        const int c = s->tune[k] < nc ? s->tune[k] : 0;
+        choice[4 * k] = cand[3 * c];
+        choice[4 * k + 1] = cand[3 * c + 1];
+        choice[4 * k + 2] = cand[3 * c + 2];
+        choice[4 * k + 3] = cached[k];
       }
     if (ms)
       for (int k = 0; k < 3; ++k)
-        for (int c = 0; c < 3; ++c) ms[k * 3 + c] = times[k][c];
-    HIP_OK(hipEventDestroy(a));
-    HIP_OK(hipEventDestroy(b));
-    HIP_OK(hipFree(tmp));
+        for (int c = 0; c < FR_TUNE_MAX; ++c) ms[k * FR_TUNE_MAX + c] = times[k][c];
+    if (a) HIP_OK(hipEventDestroy(a));
+    if (b) HIP_OK(hipEventDestroy(b));
+    if (tmp) HIP_OK(hipFree(tmp));
   } catch (const FrError &e) {
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
@@ -790,6 +841,38 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
     return fail(e.code, e.what());
   }
   return FR_OK;
+}
+
+fr_status fr_tune_candidates(const fr_solver *s, int32_t kind, int32_t *cand, int32_t *n) {
+  if (!s || !cand || !n) return fail(FR_ERR_ARG, "NULL argument");
+  if (kind < 0 || kind > 2) return fail(FR_ERR_ARG, "kind must be 0, 1 or 2");
+  try {
+    Dispatch d = dispatch_of(s);
+    *n = d.tune_cands(kind, cand);
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_tune_select(fr_solver *s, int32_t kind, int32_t index) {
+  if (!s) return fail(FR_ERR_ARG, "NULL solver");
+  if (kind < 0 || kind > 2) return fail(FR_ERR_ARG, "kind must be 0, 1 or 2");
+  try {
+    Dispatch d = dispatch_of(s);
+    int32_t cand[FR_TUNE_MAX * 3];
+    if (index < 0 || index >= d.tune_cands(kind, cand)) return fail(FR_ERR_ARG, "candidate index out of range");
+    s->tune[kind] = index;
+    free_graphs(s);
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
+void fr_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache.clear();
 }
 
 fr_status fr_solver_info(const fr_solver *s, int64_t info[8]) {

@@ -26,9 +26,10 @@ struct Dispatch {
   void (*rk_adj_combine)(const fr_solver *, void *, void *, void *, void *, void *, double, double,
                          const double *, hipStream_t);
   void (*zero)(const fr_solver *, void *, hipStream_t);
-  // elements per workgroup of the autotuner candidates of volume kernel `kind`
-  // (0: NS volume, 1: NS lifting + RK, 2: Euler volume + RK)
-  void (*tile_cands)(int kind, int *E);
+  // autotuner candidates of volume kernel `kind` (0: NS volume, 1: NS lifting + RK, 2: Euler
+  // volume + RK): cand[c][3] = (elements per workgroup, waves-per-SIMD bound or 0 for the
+  // default, engine: 0 vector ALU, 1 matrix cores); returns the count (<= FR_TUNE_MAX)
+  int (*tune_cands)(int kind, int32_t *cand);
 };
 bool get_dispatch(int dim, int p, int precision, Dispatch &out);
 // API layer (fr_api.hip): builds one solver (group: a degree group of a variable-degree mesh) and

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
 
 // tile sizes (elements per workgroup E) of the LDS-staged volume kernels: EE = 0 gives the
 // default; the autotuner also tries the default's halves and quarters (TileCands)
-template <int D, int P, typename T, int EE = 0>
+template <int D, int P, typename T, int EE = 0, int WW = 0>
 struct GradTile {
   using S = Shape<D, P>;
   // per element: the state [NV][Ns], kept to the flux-point viscous phase, then one region that
@@ -123,7 +123,8 @@ struct GradTile {
   static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
   static constexpr int BS = round64(E * S::Ns);
   // register budget (launch bound, waves per SIMD): 4 (128 VGPRs) in FP64, 7 (72 VGPRs) in FP32
-  static constexpr int MIN_WAVES = sizeof(T) == 4 ? 7 : 4;
+  // by default; WW > 0 (an autotuner candidate) sets it
+  static constexpr int MIN_WAVES = WW > 0 ? WW : (sizeof(T) == 4 ? 7 : 4);
 };
 
 // index of a thread's flux point in pass `pass` over a face-list-ordered tile: odd passes walk the
@@ -158,6 +159,52 @@ struct TileCands {
   static constexpr int c0 = E0, c1 = cmax(1, E0 / 2), c2 = cmax(1, E0 / 4);
 };
 
+// Volume divergence vol = sum_k Dt_k F~_k on the matrix cores (FP32, 3-D): for each element and
+// direction k, the line operator Dt (P x P, zero-padded to 16 rows x 8) times the tile's line
+// values (columns = (variable, line), 16 per tile) in v_mfma_f32_16x16x4f32 steps (two K steps of
+// 4 line points).  One wave per (element, column tile); the directions are summed in LDS (acc,
+// [E][NV][Ns]) in the order 0, 1, 2 with a barrier between them, so the result is deterministic.
+// lw holds F~ as [E][D][NV][Ns].  Lane layout of the 16x16x4 FP32 step: A[r][q] from lane r + 16 q,
+// B[q][c] from lane c + 16 q, D[r][c] in lane c + 16 (r / 4), component r % 4.
+template <int D, int P, int BS>
+__device__ __forceinline__ void mfma_divergence(const float *lw, float *acc, const float *Dt, int ne, int E) {
+  static_assert(D == 3 && P <= 8, "matrix-core divergence: 3-D, at most 8 points per line");
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns, NL = Ns / P, NCOL = NV * NL, NT = (NCOL + 15) / 16, NW = BS / 64;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const int r = lane % 16, q = lane / 16, c = lane % 16;
+  // this lane's A entries of the two K steps (rows beyond P and points beyond P are zero)
+  const float a0 = (r < P && q < P) ? Dt[r * P + q] : 0.f;
+  const float a1 = (r < P && q + 4 < P) ? Dt[r * P + q + 4] : 0.f;
+  for (int k = 0; k < D; ++k) {
+    const int stride = k == 0 ? 1 : (k == 1 ? P : P * P);
+    for (int item = wave; item < E * NT; item += NW) {
+      const int el = item / NT, tile = item % NT;
+      if (el >= ne) break;  // items are element-major: the rest of this wave's items are empty too
+      const int col = tile * 16 + c;
+      const bool cv = col < NCOL;
+      const int v = cv ? col / NL : 0, line = cv ? col % NL : 0;
+      const int base = k == 0 ? P * line : (k == 1 ? (line % P) + P * P * (line / P) : line);
+      const float *src = lw + ((el * D + k) * NV + v) * Ns + base;
+      const float b0 = (cv && q < P) ? src[q * stride] : 0.f;
+      const float b1 = (cv && q + 4 < P) ? src[(q + 4) * stride] : 0.f;
+      f4 d = {0.f, 0.f, 0.f, 0.f};
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, d, 0, 0, 0);
+      if (cv) {
+        float *dst = acc + (el * NV + v) * Ns + base;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = 4 * q + j;
+          if (row < P) dst[row * stride] = (k == 0) ? d[j] : dst[row * stride] + d[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // NS volume kernel.  Per element tile:
 //   own u_f = M0 u; LDG common solution from the neighbour's u_f (or the boundary state);
 //   corrected gradient grad_xi u = D_k u + s_f g_R'(s_f xi)(u^ - u_f); grad_x u = J^-1 S^T grad_xi u;
@@ -170,8 +217,10 @@ struct TileCands {
 // lie on faces to another degree; their common solution comes from ifc_uh ([point][NV], written by
 // the mortar kernels), their viscous normal flux is stored like a boundary point's, and their
 // common flux is left to the mortar kernels.
-template <int D, int P, typename T, int EE, bool MORTAR = false>
-__global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>::MIN_WAVES)) void k_ns_grad(
+// WW: waves-per-SIMD launch bound (0: the precision's default); MFMA_DIV: the volume divergence on
+// the matrix cores (FP32, 3-D; an autotuner candidate)
+template <int D, int P, typename T, int EE, bool MORTAR = false, int WW = 0, bool MFMA_DIV = false>
+__global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE, WW>::MIN_WAVES)) void k_ns_grad(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
     const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, T *__restrict__ fvn,
@@ -502,6 +551,12 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE>
     for (int k = 0; k < D; ++k)
       for (int v = 0; v < NV; ++v) lw[((el * D + k) * NV + v) * Ns + i] = ft[k][v];
   __syncthreads();
+  if constexpr (MFMA_DIV) {
+    mfma_divergence<D, P, TL::BS>(lw, lu, ops.Dt, ne, E);
+    if (act)
+      for (int v = 0; v < NV; ++v) vol_t[(uint32_t)((el * NV + v) * Ns + i)] = lu[(el * NV + v) * Ns + i];
+    return;
+  }
   if (act) {
     T accv[NV];
     for (int v = 0; v < NV; ++v) accv[v] = T(0);
@@ -657,10 +712,9 @@ __global__ __launch_bounds__((DivTile<D, P, T>::BS)) void k_interp(const T *__re
 
 // NS: R = -(1/J)(vol + Lift F^), RK update, u_f of the new stage state
 template <int D, int P, typename T, int EE>
-__global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *__restrict__ vol, const T *__restrict__ fhat,
-                                                                const T *__restrict__ metric,
-                                                                const int32_t *__restrict__ elem_mesh,
-                                                                OpsDev<T, P> ops_arg, RKArgs<T> rk, int64_t Ne) {
+__device__ __forceinline__ void div_rk_body(const T *__restrict__ vol, const T *__restrict__ fhat,
+                                            const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
+                                            const OpsDev<T, P> &ops_arg, const RKArgs<T> &rk, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = DivTile<D, P, T, EE>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
@@ -712,13 +766,34 @@ __global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *
   }
 }
 
+// the lifting + RK kernel with the compiler's register budget, and with a waves-per-SIMD launch
+// bound WW (an autotuner candidate); same body
+template <int D, int P, typename T, int EE>
+__global__ __launch_bounds__((DivTile<D, P, T, EE>::BS)) void k_div_rk(const T *__restrict__ vol,
+                                                                const T *__restrict__ fhat,
+                                                                const T *__restrict__ metric,
+                                                                const int32_t *__restrict__ elem_mesh,
+                                                                OpsDev<T, P> ops_arg, RKArgs<T> rk, int64_t Ne) {
+  div_rk_body<D, P, T, EE>(vol, fhat, metric, elem_mesh, ops_arg, rk, Ne);
+}
+template <int D, int P, typename T, int EE, int WW>
+__global__ __launch_bounds__((DivTile<D, P, T, EE>::BS), WW) void k_div_rk_w(const T *__restrict__ vol,
+                                                                      const T *__restrict__ fhat,
+                                                                      const T *__restrict__ metric,
+                                                                      const int32_t *__restrict__ elem_mesh,
+                                                                      OpsDev<T, P> ops_arg, RKArgs<T> rk,
+                                                                      int64_t Ne) {
+  div_rk_body<D, P, T, EE>(vol, fhat, metric, elem_mesh, ops_arg, rk, Ne);
+}
+
 // Euler: F~ at solution points, volume divergence with interior correction, lifting of the
 // common flux, RK update and u_f of the new stage state, in one kernel
 template <int D, int P, typename T, int EE>
-__global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
+__device__ __forceinline__ void euler_vol_rk_body(
     const T *u,  // may alias rk.ustage: every thread reads its own point before writing it
     const T *__restrict__ fhat, const T *__restrict__ metric,
-    const int32_t *__restrict__ elem_mesh, OpsDev<T, P> ops_arg, PhysDev<T> ph, RKArgs<T> rk, int64_t Ne) {
+    const int32_t *__restrict__ elem_mesh, const OpsDev<T, P> &ops_arg, const PhysDev<T> &ph, const RKArgs<T> &rk,
+    int64_t Ne) {
   using S = Shape<D, P>;
   using TL = EulerTile<D, P, T, EE>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
@@ -785,6 +860,19 @@ __global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
     __syncthreads();
     tile_interp<D, P>(lds, ne, ops, rk.uf_next + e0 * UfLayout<D, P, T>::EB, s_faces);
   }
+}
+
+template <int D, int P, typename T, int EE>
+__global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS)) void k_euler_vol_rk(
+    const T *u, const T *__restrict__ fhat, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
+    OpsDev<T, P> ops_arg, PhysDev<T> ph, RKArgs<T> rk, int64_t Ne) {
+  euler_vol_rk_body<D, P, T, EE>(u, fhat, metric, elem_mesh, ops_arg, ph, rk, Ne);
+}
+template <int D, int P, typename T, int EE, int WW>
+__global__ __launch_bounds__((EulerTile<D, P, T, EE>::BS), WW) void k_euler_vol_rk_w(
+    const T *u, const T *__restrict__ fhat, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
+    OpsDev<T, P> ops_arg, PhysDev<T> ph, RKArgs<T> rk, int64_t Ne) {
+  euler_vol_rk_body<D, P, T, EE>(u, fhat, metric, elem_mesh, ops_arg, ph, rk, Ne);
 }
 
 // probe pressure samples (FP64): one workgroup per probe, the weighted sum over the element's
@@ -1055,15 +1143,62 @@ struct ProfScope {
 };
 
 // launch the candidate tile chosen by the autotuner (index 0: default, 1: half, 2: quarter)
-template <class C, class F>
-static inline void pick_tile(int which, F &&go) {
-  if (which == 1)
-    go(std::integral_constant<int, C::c1>{});
-  else if (which == 2)
-    go(std::integral_constant<int, C::c2>{});
-  else
-    go(std::integral_constant<int, C::c0>{});
-}
+// Autotuner candidates of a volume kernel (kind 0: NS volume, 1: NS lifting + RK, 2: Euler volume
+// + RK): index c = (tile size c % 3: the default E, its half, its quarter) x (launch bound c / 3:
+// the default and one alternative waves-per-SIMD bound), plus for kind 0 in FP32 3-D p = 4 the
+// matrix-core divergence (index 6: default tile, 7: half tile; default bound).  Degree 0 has the
+// default only.
+template <int V>
+using IC = std::integral_constant<int, V>;
+template <bool V>
+using BC = std::integral_constant<bool, V>;
+
+template <int D, int P, typename T, int KIND>
+struct Cands {
+  static constexpr int E0 = KIND == 0 ? GradTile<D, P, T>::E : (KIND == 1 ? DivTile<D, P, T>::E : EulerTile<D, P, T>::E);
+  using C = TileCands<E0>;
+  // waves per SIMD of the alternative bound: the NS volume kernel one wave below its default
+  // (more registers per thread), the lifting kernels 8 (at most 64 VGPRs)
+  static constexpr int W1 = KIND == 0 ? GradTile<D, P, T>::MIN_WAVES - 1 : 8;
+  static constexpr bool HAS_MFMA = KIND == 0 && D == 3 && P == 5 && sizeof(T) == 4;
+  static constexpr int N = P == 1 ? 1 : 6 + (HAS_MFMA ? 2 : 0);
+  // (elements per workgroup, waves-per-SIMD bound (0: default), engine (1: matrix cores))
+  static void list(int32_t *out) {
+    const int E[3] = {C::c0, C::c1, C::c2};
+    for (int c = 0; c < N; ++c) {
+      out[3 * c] = c == 6 ? C::c0 : (c == 7 ? C::c1 : E[c % 3]);
+      out[3 * c + 1] = (c >= 3 && c < 6) ? W1 : 0;
+      out[3 * c + 2] = c >= 6 ? 1 : 0;
+    }
+  }
+  template <class F>
+  static void pick(int c, F &&go) {
+    if constexpr (P == 1) {
+      go(IC<C::c0>{}, IC<0>{}, BC<false>{});
+    } else {
+      switch (c) {
+        case 1: go(IC<C::c1>{}, IC<0>{}, BC<false>{}); break;
+        case 2: go(IC<C::c2>{}, IC<0>{}, BC<false>{}); break;
+        case 3: go(IC<C::c0>{}, IC<W1>{}, BC<false>{}); break;
+        case 4: go(IC<C::c1>{}, IC<W1>{}, BC<false>{}); break;
+        case 5: go(IC<C::c2>{}, IC<W1>{}, BC<false>{}); break;
+        case 6:
+          if constexpr (HAS_MFMA) {
+            go(IC<C::c0>{}, IC<0>{}, BC<true>{});
+            break;
+          }
+          [[fallthrough]];
+        case 7:
+          if constexpr (HAS_MFMA) {
+            go(IC<C::c1>{}, IC<0>{}, BC<true>{});
+            break;
+          }
+          [[fallthrough]];
+        default: go(IC<C::c0>{}, IC<0>{}, BC<false>{}); break;
+      }
+    }
+  }
+};
 
 template <int D, int P, typename T>
 struct Engine {
@@ -1108,15 +1243,15 @@ struct Engine {
               u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o,
               ph, fvn, fhat, vol, s->Ne, s->n_bc, (const T *)s->ifc_uh);
         } else {
-          auto go = [&](auto tag) {
-            constexpr int EE = decltype(tag)::value;
+          auto go = [&](auto te, auto tw, auto tm) {
+            constexpr int EE = decltype(te)::value, WW = decltype(tw)::value;
+            constexpr bool MF = decltype(tm)::value;
             using TL = GradTile<D, P, T, EE>;
-            k_ns_grad<D, P, T, EE><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(
+            k_ns_grad<D, P, T, EE, false, WW, MF><<<nblk(s->Ne, TL::E), TL::BS, 0, st>>>(
                 u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl,
                 o, ph, fvn, fhat, vol, s->Ne);
           };
-          using C = TileCands<GradTile<D, P, T>::E>;
-          pick_tile<C>(s->tune[0], go);
+          Cands<D, P, T, 0>::pick(s->tune[0], go);
         }
       }
       if ((part & 1) && force_sample && s->forces && s->n_wall > 0) {
@@ -1136,13 +1271,16 @@ struct Engine {
       }
       if (!(part & 2)) return;
       ProfScope ps(s, 4, st);
-      auto go = [&](auto tag) {
-        constexpr int EE = decltype(tag)::value;
+      auto go = [&](auto te, auto tw, auto) {
+        constexpr int EE = decltype(te)::value, WW = decltype(tw)::value;
         using TD = DivTile<D, P, T, EE>;
-        k_div_rk<D, P, T, EE><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk, s->Ne);
+        if constexpr (WW == 0)
+          k_div_rk<D, P, T, EE><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk, s->Ne);
+        else
+          k_div_rk_w<D, P, T, EE, WW><<<nblk(s->Ne, TD::E), TD::BS, 0, st>>>(vol, fhat, metric, s->elem_mesh, o, rk,
+                                                                             s->Ne);
       };
-      using C = TileCands<DivTile<D, P, T>::E>;
-      pick_tile<C>(s->tune[1], go);
+      Cands<D, P, T, 1>::pick(s->tune[1], go);
     } else {
       {
         ProfScope ps(s, 3, st);
@@ -1151,14 +1289,17 @@ struct Engine {
             s->n_wall, s->nbnd, s->elem_mesh, fl, ph, fhat);
       }
       ProfScope ps(s, 5, st);
-      auto go = [&](auto tag) {
-        constexpr int EE = decltype(tag)::value;
+      auto go = [&](auto te, auto tw, auto) {
+        constexpr int EE = decltype(te)::value, WW = decltype(tw)::value;
         using TE = EulerTile<D, P, T, EE>;
-        k_euler_vol_rk<D, P, T, EE><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh, o, ph,
-                                                                            rk, s->Ne);
+        if constexpr (WW == 0)
+          k_euler_vol_rk<D, P, T, EE><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh, o, ph,
+                                                                              rk, s->Ne);
+        else
+          k_euler_vol_rk_w<D, P, T, EE, WW><<<nblk(s->Ne, TE::E), TE::BS, 0, st>>>(u, fhat, metric, s->elem_mesh,
+                                                                                   o, ph, rk, s->Ne);
       };
-      using C = TileCands<EulerTile<D, P, T>::E>;
-      pick_tile<C>(s->tune[2], go);
+      Cands<D, P, T, 2>::pick(s->tune[2], go);
     }
   }
 
@@ -1284,17 +1425,16 @@ Dispatch make_dispatch() {
     k_rk_adj_combine<T><<<nblk(n, 256), 256, 0, st>>>((T *)a, (T *)z, (T *)kb, (T *)ub, (T *)zz, ca, cz, dt,
                                                        s->elem_mesh, per, n);
   };
-  d.tile_cands = [](int kind, int *E) {
+  d.tune_cands = [](int kind, int32_t *cand) {
     if (kind == 0) {
-      using C = TileCands<GradTile<D, P, T>::E>;
-      E[0] = C::c0; E[1] = C::c1; E[2] = C::c2;
+      Cands<D, P, T, 0>::list(cand);
+      return Cands<D, P, T, 0>::N;
     } else if (kind == 1) {
-      using C = TileCands<DivTile<D, P, T>::E>;
-      E[0] = C::c0; E[1] = C::c1; E[2] = C::c2;
-    } else {
-      using C = TileCands<EulerTile<D, P, T>::E>;
-      E[0] = C::c0; E[1] = C::c1; E[2] = C::c2;
+      Cands<D, P, T, 1>::list(cand);
+      return Cands<D, P, T, 1>::N;
     }
+    Cands<D, P, T, 2>::list(cand);
+    return Cands<D, P, T, 2>::N;
   };
   d.zero = [](const fr_solver *s, void *p, hipStream_t st) {
     using S = Shape<D, P>;

@@ -7,7 +7,7 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import FR_EULER, FR_FP32, FR_FP64, FR_NAVIER_STOKES, check, fr_mesh_desc, fr_params, lib
+from ._lib import FR_EULER, FR_FP32, FR_FP64, FR_NAVIER_STOKES, FR_TUNE_MAX, check, fr_mesh_desc, fr_params, lib
 
 
 def _ptr(a: np.ndarray):
@@ -165,19 +165,39 @@ class Solver:
         check(lib().fr_probe_series(self._h, out.ctypes.data_as(C.c_void_p), int(cap), C.byref(n), _stream(stream)))
         return out[:self.n_probe, :min(int(n.value), cap, self.max_samples)]
 
+    TUNE_KINDS = ["ns_volume", "ns_lift_rk", "euler_volume_rk"]
+
     def autotune(self, u: torch.Tensor, dt: torch.Tensor, reps: int = 3, stream=None) -> dict:
-        """Time the candidate tile sizes of the volume kernels on this mesh (u is not modified) and
-        keep the fastest; returns the chosen elements per workgroup and the measured ms per step."""
+        """Time the candidates of the volume kernels on this mesh (tile size x waves-per-SIMD bound,
+        and the matrix-core divergence where compiled; u is not modified), keep the fastest (or the
+        choice remembered for this shape); returns per kernel the chosen candidate and the ms per
+        step of every candidate."""
         self._check_state(u, "u")
         self._check_dt(dt)
-        tiles = np.zeros(3, dtype=np.int32)
-        ms = np.zeros(9)
+        choice = np.zeros(12, dtype=np.int32)
+        ms = np.zeros(3 * FR_TUNE_MAX)
         check(lib().fr_autotune(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), int(reps),
-                                tiles.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), _stream(stream)))
-        names = ["ns_volume", "ns_lift_rk", "euler_volume_rk"]
+                                choice.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), _stream(stream)))
         kinds = [0, 1] if self.equations == "ns" else [2]
-        return {names[k]: {"elements_per_workgroup": int(tiles[k]),
-                           "ms_per_step": [float(x) for x in ms[3 * k:3 * k + 3]]} for k in kinds}
+        out = {}
+        for k in kinds:
+            cands = self.tune_candidates(k)
+            out[self.TUNE_KINDS[k]] = {
+                "elements_per_workgroup": int(choice[4 * k]), "waves_per_simd_bound": int(choice[4 * k + 1]),
+                "engine": "mfma" if choice[4 * k + 2] else "valu", "from_cache": bool(choice[4 * k + 3]),
+                "candidates": [{"E": c[0], "waves": c[1], "engine": "mfma" if c[2] else "valu",
+                                "ms_per_step": float(ms[k * FR_TUNE_MAX + i])} for i, c in enumerate(cands)]}
+        return out
+
+    def tune_candidates(self, kind: int):
+        """[(elements per workgroup, waves-per-SIMD bound (0: default), engine (1: matrix cores))]"""
+        cand = np.zeros(3 * FR_TUNE_MAX, dtype=np.int32)
+        n = C.c_int32()
+        check(lib().fr_tune_candidates(self._h, int(kind), cand.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return [tuple(int(x) for x in cand[3 * i:3 * i + 3]) for i in range(n.value)]
+
+    def tune_select(self, kind: int, index: int):
+        check(lib().fr_tune_select(self._h, int(kind), int(index)))
 
     def probe_statistics(self, p_ref: float, groups=None, n_windows: int = 6, sample_dt: float | None = None,
                          cap: int | None = None) -> dict:

@@ -188,22 +188,55 @@ def test_ragged_tiles_3d_p4_channel(shape, probes, gpu):
     np.testing.assert_allclose(st["mean_force"], Fm, rtol=0, atol=1e-10 * max(float(np.abs(Fm).max()), 1e-3))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["ns_ogrid", "euler_vortex", "ns_cgrid_p4"])
-def test_autotuned_tiles_give_the_same_step(name, gpu):
-    """Every candidate tile size of the autotuner computes the same RK4 step (the tile only
-    regroups elements into workgroups), and the tuner leaves u untouched and re-captures graphs."""
-    s, sol, u0, dt = _solver(name)
+def test_every_tuner_candidate_gives_the_same_step(name, precision, gpu):
+    """Every vector-ALU candidate of the autotuner (tile size x waves-per-SIMD bound) computes a
+    bit-identical RK4 step (the tile only regroups elements into workgroups, the bound only the
+    register allocation); the matrix-core divergence (FP32 3-D p = 4) rounds differently and is
+    held to the FP32 bar against the oracle.  The tuner leaves u untouched, re-captures graphs,
+    and a second solver of the same shape takes the remembered choice."""
+    from paper_2312_14167_amd import Solver
+    from paper_2312_14167_amd._lib import lib
+    s, m, p, fp, eq, u0, dt, probes, pm = oracle_for(name, with_probes=False)
+    sol = Solver(m, p, fp, equations=eq, precision=precision)
     dtt = torch.tensor(dt, dtype=torch.float64, device=gpu)
-    ug = u0.to(gpu)
+    ug = u0.to(device=gpu, dtype=sol.dtype)
     ref = ug.clone()
     sol.rk_step(ref, dtt, 2)
+    uref, _, _ = s.run(u0, torch.tensor(dt), 2, sample_every=0)
+    kinds = [0, 1] if eq == "ns" else [2]
+    n_mfma = 0
+    for k in kinds:
+        cands = sol.tune_candidates(k)
+        assert len(cands) >= 6
+        for c, (E, W, engine) in enumerate(cands):
+            sol.tune_select(k, c)
+            u = ug.clone()
+            sol.rk_step(u, dtt, 2)
+            if engine == 0:
+                assert torch.equal(u, ref), (k, c, E, W)
+            else:
+                n_mfma += 1
+                e = rel_l2(u, uref)
+                print(f"{name} {precision}: matrix-core divergence, 2 steps rel L2 vs oracle {e:.3e}")
+                assert e <= 1e-5
+        sol.tune_select(k, 0)
+    assert n_mfma == (2 if (precision == "fp32" and m.dim == 3 and p == 4) else 0)
+    lib().fr_tune_cache_clear()
     keep = ug.clone()
     choice = sol.autotune(ug, dtt, reps=1)
     assert torch.equal(ug, keep)
-    print(f"{name}: autotuned {choice}")
+    print(f"{name} {precision}: autotuned { {k: (v['elements_per_workgroup'], v['waves_per_simd_bound'], v['engine']) for k, v in choice.items()} }")
+    assert not any(v["from_cache"] for v in choice.values())
     u = ug.clone()
     sol.rk_step(u, dtt, 2)
-    assert rel_l2(u, ref) <= 1e-14
+    assert rel_l2(u, uref) <= (1e-12 if precision == "fp64" else 1e-5)
+    again = Solver(m, p, fp, equations=eq, precision=precision)
+    choice2 = again.autotune(ug, dtt, reps=1)
+    assert all(v["from_cache"] for v in choice2.values())
+    assert {k: v["elements_per_workgroup"] for k, v in choice2.items()} == \
+        {k: v["elements_per_workgroup"] for k, v in choice.items()}
 
 
 @pytest.mark.parametrize("p,dim,eq,bc", [(1, 2, "ns", "channel"), (1, 3, "ns", "channel"), (1, 2, "euler", "periodic"),
