@@ -224,6 +224,22 @@ fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_s
 fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const void *stages, const void *residuals,
                          void *u_bar, double *x_bar, void *stream);
 
+/* Reverse of n_steps consecutive RK4 steps with their probe samples, the inner loop of a
+ * checkpointed trajectory adjoint in one call: for j = n_steps-1 .. 0,
+ *   u_bar <- (d u_{j+1} / d u_j)^T u_bar     (as fr_rk_step_vjp with states[j], stages[j]) and
+ *   u_bar += sum_a p_bar[j][a] d p_a / d u_j (as fr_probe_vjp with states[j]).
+ * states [n_steps][Ne][NV][Ns] (each step's base state), stages [n_steps][3][Ne][NV][Ns] and
+ * residuals [n_steps][4][Ne][NV][Ns] (nullable; required with x_bar) as written by
+ * fr_rk_step_stages; p_bar [n_steps][n_probe] FP64 (device); dt one device double per mesh.
+ * x_bar (FP64 [n_node][dim], nullable): the mesh-node adjoint, only inside fr_geo_adjoint_begin /
+ * _end (FR_ERR_ARG otherwise).  The sequence is captured into a HIP graph on first use and
+ * replayed while the pointer arguments and n_steps repeat (a few such graphs are kept); the
+ * solver's adjoint work areas are allocated on first use, before any capture.  u_bar must not
+ * alias the inputs. */
+fr_status fr_rk_segment_vjp(fr_solver *s, const void *states, const double *dt, const void *stages,
+                            const void *residuals, const double *p_bar, int32_t n_steps, void *u_bar, double *x_bar,
+                            void *stream);
+
 /* Deferred mesh-node adjoint for reverse sweeps over many steps (the node mapping is linear, so
  * it can run once): after fr_geo_adjoint_begin, fr_rk_step_vjp calls with a non-NULL x_bar add
  * their metric and normal adjoints to the handle's accumulators without touching x_bar (their
@@ -234,19 +250,22 @@ fr_status fr_geo_adjoint_begin(fr_solver *s, void *stream);
 fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream);
 
 /* Autotuner.  For each volume kernel of the solver's equations (kind 0: NS volume kernel, 1: NS
- * lifting + RK kernel, 2: Euler volume + RK kernel) the candidates are the tile sizes (elements
- * per workgroup: the default, its half and its quarter) times two register budgets (the default
- * and one alternative waves-per-SIMD launch bound), and for kind 0 in FP32 3-D p = 4 the volume
- * divergence on the matrix cores; degree-0 groups have the default only.  fr_autotune times each
- * candidate with `reps` RK4 steps on a device copy of u (u is not modified), keeps the fastest,
- * remembers it for the rest of the process under (dim, p, precision, equations, LDG form, kind,
- * floor(log2 n_elem)) -- a later solver with the same key takes the remembered choice without
- * timing -- and drops the captured step graphs so that the next fr_rk_step re-captures them.
- * Synchronises `stream`; allocates and frees one state-sized scratch copy when it times.
- * choice[3][4] (host, nullable): per kind (elements per workgroup, waves-per-SIMD bound or 0 for
+ * lifting + RK kernel, 2: Euler volume + RK kernel, 3: NS volume adjoint kernel) the candidates
+ * are the tile sizes (elements per workgroup: the default, its half and its quarter) times two
+ * register budgets (the default and one alternative waves-per-SIMD launch bound), and for kind 0
+ * in FP32 3-D p = 4 the volume divergence on the matrix cores; kind 3: default tile, half tile,
+ * default tile with a launch bound; degree-0 groups have the default only.  fr_autotune times
+ * each candidate on device copies of u (u is not modified) -- `reps` RK4 steps, or for kind 3
+ * 4 x reps residual adjoints --, keeps the fastest, remembers it for the rest of the process under
+ * (dim, p, precision, equations, LDG form, kind, floor(log2 n_elem)) -- a later solver with the
+ * same key takes the remembered choice without timing -- and drops the captured step graphs so
+ * that the next fr_rk_step re-captures them.  Synchronises `stream`; allocates and frees
+ * state-sized scratch copies (and the adjoint's work area) when it times.
+ * choice[4][4] (host, nullable): per kind (elements per workgroup, waves-per-SIMD bound or 0 for
  * the compiler's default, engine 0 vector ALU / 1 matrix cores, 1 if taken from the remembered
- * choices); ms[3][FR_TUNE_MAX] (host, nullable): ms per RK4 step of each candidate (0 where not
- * timed).  FR_ERR_ARG for reps < 1.
+ * choices; zeros for kinds the solver does not run).  ms[4][FR_TUNE_MAX] (host, nullable): ms per
+ * RK4 step (kind 3: per 4 residual adjoints) of each candidate, 0 where not timed.  FR_ERR_ARG for
+ * reps < 1.
  * fr_tune_candidates: the candidates of `kind`, cand[FR_TUNE_MAX][3] as in choice, *n of them.
  * fr_tune_select: use candidate `index` of `kind` from now on (drops the step graphs).
  * fr_tune_cache_clear: forget the remembered choices. */

@@ -70,6 +70,7 @@ def lib() -> C.CDLL:
     L.fr_probe_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fr_rk_step_stages.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.fr_rk_segment_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
     L.fr_autotune.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.fr_tune_candidates.argtypes = [vp, i32, vp, C.POINTER(i32)]
     L.fr_tune_select.argtypes = [vp, i32, i32]
@@ -98,7 +99,7 @@ def lib() -> C.CDLL:
     for name in ("fr_build_operators", "fr_state_shape", "fr_solpt_coords", "fr_rhs", "fr_rk_step",
                  "fr_probe_oaspl", "fr_probe_series", "fr_force_coefficients", "fr_reset_accumulators", "fr_rhs_vjp", "fr_rhs_vjp_noalloc",
                  "fr_solver_info",
-                 "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp",
+                 "fr_profile_enable", "fr_profile_read", "fr_probe_vjp", "fr_rk_step_stages", "fr_rk_step_vjp", "fr_rk_segment_vjp",
                  "fr_autotune", "fr_tune_candidates", "fr_tune_select", "fr_geo_adjoint_begin", "fr_geo_adjoint_end", "fr_stats_prms_cumulative",
                  "fr_stats_observer_oaspl", "fr_stats_psd_welch", "fr_vdeg_build", "fr_vdeg_groups",
                  "fr_vdeg_group_elems", "fr_vdeg_solpt_coords", "fr_vdeg_rhs", "fr_vdeg_rk_step",

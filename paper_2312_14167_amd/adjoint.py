@@ -33,8 +33,20 @@ def _record_slots(sol, C, nslot, with_res, dev):
         cache[key] = [{"u": torch.empty(sol.shape, dtype=sol.dtype, device=dev),
                        "states": torch.empty((C,) + sol.shape, dtype=sol.dtype, device=dev),
                        "stages": torch.empty((C, 3) + sol.shape, dtype=sol.dtype, device=dev),
-                       "res": torch.empty((C, 4) + sol.shape, dtype=sol.dtype, device=dev) if with_res else None}
+                       "res": torch.empty((C, 4) + sol.shape, dtype=sol.dtype, device=dev) if with_res else None,
+                       "pbar": torch.empty((C, sol.n_probe), dtype=torch.float64, device=dev)}
                       for _ in range(nslot)]
+    return cache[key]
+
+
+def _adjoint_accumulators(sol, with_nodes, dev):
+    """u_bar (and x_bar) buffers of the reverse sweep, kept on the solver so that the captured
+    reverse-segment graphs see the same addresses on every backward pass."""
+    key = (with_nodes, str(dev))
+    cache = sol.__dict__.setdefault("_adjoint_acc", {})
+    if key not in cache:
+        cache[key] = (torch.empty(sol.shape, dtype=sol.dtype, device=dev),
+                      torch.empty((sol.n_node, sol.dim), dtype=torch.float64, device=dev) if with_nodes else None)
     return cache[key]
 
 
@@ -72,10 +84,11 @@ class FRTrajectory(torch.autograd.Function):
         sol, dt, K, C = ctx.solver, ctx.dt, ctx.K, ctx.C
         p_bar = p_bar.detach().to(torch.float64).contiguous()
         dev = p_bar.device
-        ub = torch.zeros(sol.shape, dtype=sol.dtype, device=dev)   # dJ/du_K = 0
-        xb = None
-        if ctx.with_nodes and ctx.needs_input_grad[5]:
-            xb = torch.zeros((sol.n_node, sol.dim), dtype=torch.float64, device=dev)
+        with_nodes = bool(ctx.with_nodes and ctx.needs_input_grad[5])
+        ub, xb = _adjoint_accumulators(sol, with_nodes, dev)
+        ub.zero_()                                                 # dJ/du_K = 0
+        if xb is not None:
+            xb.zero_()
         # Segments in reverse order.  The recompute of a segment needs only its checkpoint, so it
         # runs on a second stream while the previous (later-in-time) segment is being reversed;
         # two record slots alternate, and a slot is refilled only after the reverse sweep that
@@ -108,18 +121,19 @@ class FRTrajectory(torch.autograd.Function):
         for i, (s0, s1) in enumerate(segs):
             sl = slots[i % nslot]
             main.wait_event(recorded[i])
-            for n in reversed(range(s0, s1)):
-                j = n - s0
-                sol.rk_step_vjp(sl["states"][j], dt, ub, sl["stages"][j], x_bar=xb,
-                                residuals=None if sl["res"] is None else sl["res"][j], stream=main)
-                sol.probe_vjp(sl["states"][j], p_bar[n], ub, x_bar=xb, stream=main)
+            with torch.cuda.stream(main):
+                sl["pbar"][:s1 - s0].copy_(p_bar[s0:s1])
+            # the segment's steps in reverse, each followed by its probe sample's adjoint (one
+            # graph replay per segment)
+            sol.rk_segment_vjp(sl["states"], dt, ub, sl["stages"], sl["pbar"], s1 - s0, x_bar=xb,
+                               residuals=sl["res"], stream=main)
             reversed_[i].record(main)
             if i + nslot < len(segs):
                 record(i + nslot)
         main.wait_stream(side)
         if xb is not None:
             sol.geo_adjoint_end(xb, stream=main)
-        return ub, None, None, None, None, xb
+        return ub.clone(), None, None, None, None, (xb.clone() if xb is not None else None)
 
 
 def probe_variance_gradient(solver, u0, dt, n_steps: int, checkpoint_every: int = 20, with_nodes: bool = False):

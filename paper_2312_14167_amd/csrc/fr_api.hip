@@ -130,6 +130,9 @@ void free_graphs(fr_solver *s) {
     s->graph_u[k] = nullptr;
     s->graph_dt[k] = nullptr;
   }
+  for (auto &g : s->seg_graphs)
+    if (g.ex) (void)hipGraphExecDestroy(g.ex);
+  s->seg_graphs.clear();
 }
 
 void destroy(fr_solver *s) {
@@ -723,6 +726,91 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
   return FR_OK;
 }
 
+fr_status fr_rk_segment_vjp(fr_solver *s, const void *states, const double *dt, const void *stages,
+                            const void *residuals, const double *p_bar, int32_t n_steps, void *u_bar, double *x_bar,
+                            void *stream) {
+  if (!s || !states || !dt || !stages || !u_bar || (s->n_probe > 0 && !p_bar))
+    return fail(FR_ERR_ARG, "NULL argument");
+  if (n_steps < 1) return fail(FR_ERR_ARG, "n_steps must be >= 1");
+  if (x_bar && (!residuals || !s->geo_deferred))
+    return fail(FR_ERR_ARG, "x_bar needs the stage residuals and fr_geo_adjoint_begin");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Dispatch d = dispatch_of(s);
+    const size_t nb = (size_t)s->Ne * s->NV * s->Ns * s->tsize;
+    // work areas exist before any capture
+    if (!s->adj_work) s->adj_work = (char *)dalloc(s, nb * 11);
+    if (!s->vjp_work) {
+      s->vjp_bytes = vjp_work_elems(s) * s->tsize;
+      s->vjp_work = dalloc(s, s->vjp_bytes);
+    }
+    if (x_bar) ensure_geo(s);
+    auto body = [&](hipStream_t q) {
+      const char *X = (const char *)states, *Y = (const char *)stages, *R = (const char *)residuals;
+      for (int j = n_steps - 1; j >= 0; --j) {
+        const char *yj = Y + (size_t)j * 3 * nb;
+        const void *ys[4] = {X + (size_t)j * nb, yj, yj + nb, yj + 2 * nb};
+        const void *rs[4] = {nullptr, nullptr, nullptr, nullptr};
+        if (x_bar)
+          for (int k = 0; k < 4; ++k) rs[k] = R + ((size_t)j * 4 + k) * nb;
+        if (!launch_vjp_rk_step(s, ys, u_bar, s->adj_work, dt, x_bar ? rs : nullptr, x_bar ? s->geo_Gm : nullptr,
+                                x_bar ? s->geo_Gn : nullptr, s->vjp_work, q))
+          throw FrError(FR_ERR_UNSUPPORTED, "unsupported (dim, p)");
+        d.probe_vjp(s, ys[0], p_bar ? p_bar + (size_t)j * s->n_probe : nullptr, u_bar, x_bar, q);
+      }
+    };
+    if (!s->use_graphs || s->profiling) {
+      body(st);
+      HIP_OK(hipGetLastError());
+      return FR_OK;
+    }
+    fr_solver::SegGraph *g = nullptr;
+    for (auto &c : s->seg_graphs)
+      if (c.states == states && c.stages == stages && c.res == residuals && c.pbar == p_bar && c.ubar == u_bar &&
+          c.dt == dt && c.xbar == x_bar && c.n == n_steps)
+        g = &c;
+    if (!g) {
+      if (s->seg_graphs.size() >= 8) {  // keep a handful (two record slots x full and tail segments)
+        (void)hipGraphExecDestroy(s->seg_graphs.front().ex);
+        s->seg_graphs.erase(s->seg_graphs.begin());
+      }
+      hipGraph_t gr = nullptr;
+      HIP_OK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+      try {
+        body(s->cap_stream);
+      } catch (...) {
+        (void)hipStreamEndCapture(s->cap_stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      const hipError_t le = hipGetLastError();
+      const hipError_t ce = hipStreamEndCapture(s->cap_stream, &gr);
+      if (le != hipSuccess) throw FrError(FR_ERR_HIP, std::string("launch during capture: ") + hipGetErrorString(le));
+      HIP_OK(ce);
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      HIP_OK(ie);
+      fr_solver::SegGraph c;
+      c.ex = ex;
+      c.states = states;
+      c.stages = stages;
+      c.res = residuals;
+      c.pbar = p_bar;
+      c.ubar = u_bar;
+      c.dt = dt;
+      c.xbar = x_bar;
+      c.n = n_steps;
+      s->seg_graphs.push_back(c);
+      g = &s->seg_graphs.back();
+    }
+    HIP_OK(hipGraphLaunch(g->ex, st));
+  } catch (const FrError &e) {
+    return fail(e.code, e.what());
+  }
+  return FR_OK;
+}
+
 fr_status fr_geo_adjoint_begin(fr_solver *s, void *stream) {
   if (!s) return fail(FR_ERR_ARG, "NULL solver");
   try {
@@ -756,21 +844,23 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
   if (reps < 1) return fail(FR_ERR_ARG, "reps must be >= 1");
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t a = nullptr, b = nullptr;
-  void *tmp = nullptr;
+  void *tmp = nullptr, *work = nullptr, *tmp2 = nullptr;
   try {
     Dispatch d = dispatch_of(s);
     const size_t nb = (size_t)s->Ne * s->NV * s->Ns * s->tsize;
-    const int kinds_ns[2] = {0, 1}, kinds_eu[1] = {2};
+    const int kinds_ns[3] = {0, 1, 3}, kinds_eu[1] = {2};
     const int *kinds = s->equations == FR_NAVIER_STOKES ? kinds_ns : kinds_eu;
-    const int nk = s->equations == FR_NAVIER_STOKES ? 2 : 1;
-    double times[3][FR_TUNE_MAX] = {};
-    int cached[3] = {0, 0, 0};
+    int32_t vc[FR_TUNE_MAX * 3];
+    const int nk = s->equations == FR_NAVIER_STOKES ? (vjp_tune_cands(s, vc) > 0 ? 3 : 2) : 1;
+    double times[4][FR_TUNE_MAX] = {};
+    int cached[4] = {0, 0, 0, 0};
+    auto cands_of = [&](int kind, int32_t *cand) { return kind == 3 ? vjp_tune_cands(s, cand) : d.tune_cands(kind, cand); };
     const int prof = s->profiling;
     s->profiling = 0;
     for (int q = 0; q < nk; ++q) {
       const int kind = kinds[q];
       int32_t cand[FR_TUNE_MAX * 3];
-      const int nc = d.tune_cands(kind, cand);
+      const int nc = cands_of(kind, cand);
       const TuneKey key = tune_key(s, kind);
       {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -797,10 +887,26 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
         if (dup) continue;
         s->tune[kind] = c;
         HIP_OK(hipMemcpyAsync(tmp, u, nb, hipMemcpyDeviceToDevice, st));
-        d.step(s, tmp, dt, false, true, st);  // warm-up (first launch of this variant)
-        HIP_OK(hipEventRecord(a, st));
-        for (int r = 0; r < reps; ++r) d.step(s, tmp, dt, false, r == 0, st);
-        HIP_OK(hipEventRecord(b, st));
+        if (kind == 3) {  // the residual adjoint at u with r_bar = u (values do not matter for timing)
+          if (!work) {
+            HIP_OK(hipMalloc(&work, vjp_work_elems(s) * s->tsize));
+            HIP_OK(hipMalloc(&tmp2, nb));
+          }
+          const GeoVjpArgs geo{};
+          auto vjp = [&]() {
+            if (!launch_vjp(s, u, tmp, tmp2, work, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, geo, st))
+              throw FrError(FR_ERR_UNSUPPORTED, "adjoint not compiled for this degree");
+          };
+          vjp();  // warm-up
+          HIP_OK(hipEventRecord(a, st));
+          for (int r = 0; r < reps * 4; ++r) vjp();  // as many residual adjoints as forward stages
+          HIP_OK(hipEventRecord(b, st));
+        } else {
+          d.step(s, tmp, dt, false, true, st);  // warm-up (first launch of this variant)
+          HIP_OK(hipEventRecord(a, st));
+          for (int r = 0; r < reps; ++r) d.step(s, tmp, dt, false, r == 0, st);
+          HIP_OK(hipEventRecord(b, st));
+        }
         HIP_OK(hipEventSynchronize(b));
         float t = 0.0f;
         HIP_OK(hipEventElapsedTime(&t, a, b));
@@ -819,25 +925,29 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
     s->profiling = prof;
     free_graphs(s);  // captured steps must use the chosen candidates
     if (choice)
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 4; ++k) {
         int32_t cand[FR_TUNE_MAX * 3];
-        const int nc = d.tune_cands(k, cand);
+        const int nc = cands_of(k, cand);
         const int c = s->tune[k] < nc ? s->tune[k] : 0;
-        choice[4 * k] = cand[3 * c];
-        choice[4 * k + 1] = cand[3 * c + 1];
-        choice[4 * k + 2] = cand[3 * c + 2];
+        choice[4 * k] = nc > 0 ? cand[3 * c] : 0;
+        choice[4 * k + 1] = nc > 0 ? cand[3 * c + 1] : 0;
+        choice[4 * k + 2] = nc > 0 ? cand[3 * c + 2] : 0;
         choice[4 * k + 3] = cached[k];
       }
     if (ms)
-      for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < 4; ++k)
         for (int c = 0; c < FR_TUNE_MAX; ++c) ms[k * FR_TUNE_MAX + c] = times[k][c];
     if (a) HIP_OK(hipEventDestroy(a));
     if (b) HIP_OK(hipEventDestroy(b));
     if (tmp) HIP_OK(hipFree(tmp));
+    if (work) HIP_OK(hipFree(work));
+    if (tmp2) HIP_OK(hipFree(tmp2));
   } catch (const FrError &e) {
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     if (tmp) (void)hipFree(tmp);
+    if (work) (void)hipFree(work);
+    if (tmp2) (void)hipFree(tmp2);
     return fail(e.code, e.what());
   }
   return FR_OK;
@@ -845,10 +955,10 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
 
 fr_status fr_tune_candidates(const fr_solver *s, int32_t kind, int32_t *cand, int32_t *n) {
   if (!s || !cand || !n) return fail(FR_ERR_ARG, "NULL argument");
-  if (kind < 0 || kind > 2) return fail(FR_ERR_ARG, "kind must be 0, 1 or 2");
+  if (kind < 0 || kind > 3) return fail(FR_ERR_ARG, "kind must be in 0..3");
   try {
     Dispatch d = dispatch_of(s);
-    *n = d.tune_cands(kind, cand);
+    *n = kind == 3 ? vjp_tune_cands(s, cand) : d.tune_cands(kind, cand);
   } catch (const FrError &e) {
     return fail(e.code, e.what());
   }
@@ -857,11 +967,12 @@ fr_status fr_tune_candidates(const fr_solver *s, int32_t kind, int32_t *cand, in
 
 fr_status fr_tune_select(fr_solver *s, int32_t kind, int32_t index) {
   if (!s) return fail(FR_ERR_ARG, "NULL solver");
-  if (kind < 0 || kind > 2) return fail(FR_ERR_ARG, "kind must be 0, 1 or 2");
+  if (kind < 0 || kind > 3) return fail(FR_ERR_ARG, "kind must be in 0..3");
   try {
     Dispatch d = dispatch_of(s);
     int32_t cand[FR_TUNE_MAX * 3];
-    if (index < 0 || index >= d.tune_cands(kind, cand)) return fail(FR_ERR_ARG, "candidate index out of range");
+    const int nc = kind == 3 ? vjp_tune_cands(s, cand) : d.tune_cands(kind, cand);
+    if (index < 0 || index >= nc) return fail(FR_ERR_ARG, "candidate index out of range");
     s->tune[kind] = index;
     free_graphs(s);
   } catch (const FrError &e) {

@@ -55,6 +55,10 @@ bool launch_vjp(const fr_solver *s, const void *u, const void *rbar, void *ubar,
 bool launch_vjp_rk_step(const fr_solver *s, const void *const ys[4], void *u_bar, void *A, const double *dt,
                         const void *const Rs[4], void *Gm, void *Gn, void *work, hipStream_t st);
 
+// autotuner candidates of the NS volume adjoint (kind 3), as Dispatch::tune_cands; 0 if the
+// adjoint is not compiled for the solver's degree
+int vjp_tune_cands(const fr_solver *s, int32_t *cand);
+
 // mesh-node adjoint (fr_geo.hip): x_bar += (d metrics / d X)^T (Gm, Gn)
 bool launch_geo_nodes(const fr_solver *s, double *x_bar, hipStream_t st);
 

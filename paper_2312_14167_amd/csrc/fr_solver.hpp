@@ -129,12 +129,23 @@ struct fr_solver {
   // time stepping / graphs
   int64_t steps_since_reset = 0;
   hipStream_t cap_stream = nullptr;
+  // reverse segments of the trajectory adjoint captured as graphs, keyed by their arguments
+  struct SegGraph {
+    hipGraphExec_t ex = nullptr;
+    const void *states = nullptr, *stages = nullptr, *res = nullptr, *pbar = nullptr, *ubar = nullptr;
+    const double *dt = nullptr;
+    double *xbar = nullptr;
+    int n = 0;
+  };
+  std::vector<SegGraph> seg_graphs;
   hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // (sample, fresh u_f) variants
   void *graph_u[4] = {nullptr, nullptr, nullptr, nullptr};
   const double *graph_dt[4] = {nullptr, nullptr, nullptr, nullptr};
   int use_graphs = 1;
   // autotuner choice per volume kernel (0: default tile, 1: half, 2: quarter)
-  int tune[3] = {0, 0, 0};
+  // autotuner candidate per kernel kind: NS volume, NS lifting + RK, Euler volume + RK, NS volume
+  // adjoint
+  int tune[4] = {0, 0, 0, 0};
 
   // per-kernel event timing (FR_K_* ids)
   int profiling = 0;

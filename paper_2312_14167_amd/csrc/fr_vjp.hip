@@ -575,15 +575,46 @@ __global__ __launch_bounds__(256) void k_vjp_face(const T *__restrict__ uf, cons
   }
 }
 
-template <int D, int P, typename T>
+template <int D, int P, typename T, int EE = 0>
 struct VjpVolTile {
   using S = Shape<D, P>;
   // A: u + (u^ - u_f) | gradient | flux-point gradient adjoint | reference-gradient adjoint
   static constexpr int LA = cmax(cmax(S::NV * S::Ns + S::NV * S::Nf, D * S::NV * S::Ns), D * S::NV * S::Nf);
   // + own u_f + vol_bar + own u_f adjoint
   static constexpr int LE = LA + S::NV * S::Nf + S::NV * S::Ns + S::NV * S::Nf;
-  static constexpr int E = tile_elems<S::Ns>(LE, sizeof(T));
+  static constexpr int E = EE > 0 ? EE : tile_elems<S::Ns>(LE, sizeof(T));
   static constexpr int BS = round64(cmax(E * S::Ns, E * S::Nf));
+};
+
+// Autotuner candidates of the NS volume adjoint (kind 3): (default tile, compiler's register
+// budget), (half tile, compiler's budget), (default tile, a waves-per-SIMD launch bound one above
+// the compiler's choice); degree 1 has the default only
+template <int D, int P, typename T>
+struct VCands {
+  static constexpr int E0 = VjpVolTile<D, P, T>::E, E1 = E0 / 2 > 0 ? E0 / 2 : 1;
+  static constexpr int W1 = sizeof(T) == 8 ? (D == 2 ? 3 : 2) : (D == 2 ? 5 : 3);
+  static constexpr int N = P >= 3 ? 3 : 1;
+  static void list(int32_t *out) {
+    const int E[3] = {E0, E1, E0}, W[3] = {0, 0, W1};
+    for (int c = 0; c < N; ++c) {
+      out[3 * c] = E[c];
+      out[3 * c + 1] = W[c];
+      out[3 * c + 2] = 0;
+    }
+  }
+  template <class F>
+  static void pick(int c, F &&go) {
+    if constexpr (N == 1) {
+      go(std::integral_constant<int, E0>{}, std::integral_constant<int, 0>{});
+    } else {
+      if (c == 1)
+        go(std::integral_constant<int, E1>{}, std::integral_constant<int, 0>{});
+      else if (c == 2)
+        go(std::integral_constant<int, E0>{}, std::integral_constant<int, W1>{});
+      else
+        go(std::integral_constant<int, E0>{}, std::integral_constant<int, 0>{});
+    }
+  }
 };
 
 // NS volume adjoint (see the file header), including the adjoint of the common flux at its own
@@ -596,15 +627,15 @@ struct VjpVolTile {
 // 1/J from the gradient transform) into Gm, and the unit-normal and |N| adjoints of the common
 // flux (at the L point of a pair and at boundary points), of the viscous normal flux and of the
 // far-field states at own flux points into Gn
-template <int D, int P, typename T, bool GEO>
-__global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
+template <int D, int P, typename T, bool GEO, int EE>
+__device__ __forceinline__ void vjp_ns_vol_body(
     const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
     const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
-    const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, const T *volbar,
+    const FlowDev<T> *__restrict__ flow, const OpsDev<T, P> &ops_arg, const PhysDev<T> &ph, const T *volbar,
     const T *__restrict__ fhatbar, T *ubvol, T *__restrict__ ufb_own, T *__restrict__ ufb_nbr,
     T *__restrict__ Gm, T *__restrict__ Gn, int64_t Ne) {
   using S = Shape<D, P>;
-  using TL = VjpVolTile<D, P, T>;
+  using TL = VjpVolTile<D, P, T, EE>;
   constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
@@ -961,6 +992,48 @@ __global__ __launch_bounds__((VjpVolTile<D, P, T>::BS)) void k_vjp_ns_vol(
   }
 }
 
+// the NS volume adjoint with the compiler's register budget, and with a waves-per-SIMD launch
+// bound WW (an autotuner candidate); same body
+template <int D, int P, typename T, bool GEO, int EE = 0>
+__global__ __launch_bounds__((VjpVolTile<D, P, T, EE>::BS)) void k_vjp_ns_vol(
+    const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
+    const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
+    const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, const T *volbar,
+    const T *__restrict__ fhatbar, T *ubvol, T *__restrict__ ufb_own, T *__restrict__ ufb_nbr,
+    T *__restrict__ Gm, T *__restrict__ Gn, int64_t Ne) {
+  vjp_ns_vol_body<D, P, T, GEO, EE>(u, uf, nbr, fnrm, bnrm, n_wall, metric, elem_mesh, flow, ops_arg, ph, volbar,
+                                    fhatbar, ubvol, ufb_own, ufb_nbr, Gm, Gn, Ne);
+}
+template <int D, int P, typename T, bool GEO, int EE, int WW>
+__global__ __launch_bounds__((VjpVolTile<D, P, T, EE>::BS), WW) void k_vjp_ns_vol_w(
+    const T *__restrict__ u, const T *__restrict__ uf, const int32_t *__restrict__ nbr, const T *__restrict__ fnrm,
+    const T *__restrict__ bnrm, int64_t n_wall, const T *__restrict__ metric, const int32_t *__restrict__ elem_mesh,
+    const FlowDev<T> *__restrict__ flow, OpsDev<T, P> ops_arg, PhysDev<T> ph, const T *volbar,
+    const T *__restrict__ fhatbar, T *ubvol, T *__restrict__ ufb_own, T *__restrict__ ufb_nbr,
+    T *__restrict__ Gm, T *__restrict__ Gn, int64_t Ne) {
+  vjp_ns_vol_body<D, P, T, GEO, EE>(u, uf, nbr, fnrm, bnrm, n_wall, metric, elem_mesh, flow, ops_arg, ph, volbar,
+                                    fhatbar, ubvol, ufb_own, ufb_nbr, Gm, Gn, Ne);
+}
+
+// launches the NS volume adjoint with the solver's chosen candidate
+template <int D, int P, typename T, bool GEO>
+void launch_vjp_ns_vol(const fr_solver *s, hipStream_t st, const T *u, const T *uf, const T *metric,
+                       const FlowDev<T> *fl, const OpsDev<T, P> &o, const PhysDev<T> &ph, const T *volbar,
+                       const T *fhatbar, T *ubvol, T *ufb_own, T *ufb_nbr, T *Gm, T *Gn) {
+  VCands<D, P, T>::pick(s->tune[3], [&](auto te, auto tw) {
+    constexpr int EE = decltype(te)::value, WW = decltype(tw)::value;
+    using TV = VjpVolTile<D, P, T, EE>;
+    const unsigned nb = (unsigned)((s->Ne + TV::E - 1) / TV::E);
+    if constexpr (WW == 0)
+      k_vjp_ns_vol<D, P, T, GEO, EE><<<nb, TV::BS, 0, st>>>(
+          u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
+          volbar, fhatbar, ubvol, ufb_own, ufb_nbr, Gm, Gn, s->Ne);
+    else
+      k_vjp_ns_vol_w<D, P, T, GEO, EE, WW><<<nb, TV::BS, 0, st>>>(
+          u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
+          volbar, fhatbar, ubvol, ufb_own, ufb_nbr, Gm, Gn, s->Ne);
+  });
+}
 // Euler volume adjoint: F~_bar from vol_bar, pointwise inviscid-flux adjoint
 template <int D, int P, typename T, bool GEO>
 __global__ __launch_bounds__((VjpDivTile<D, P, T>::BS)) void k_vjp_euler_vol(const T *__restrict__ u,
@@ -1219,10 +1292,8 @@ struct VjpEngine {
     k_vjp_div<D, P, T, GEO><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(rbar, u, metric, o, volbar, fhatbar, uf, Rf, Gm, Ne);
     const int64_t nface = s->npair + s->nbnd;
     if (s->equations == 1) {
-      using TV = VjpVolTile<D, P, T>;
-      k_vjp_ns_vol<D, P, T, GEO><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
-          u, uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o, ph,
-          volbar, fhatbar, volbar, ufbface, ufbnbr, Gm, Gn, Ne);
+      launch_vjp_ns_vol<D, P, T, GEO>(s, st, u, uf, metric, fl, o, ph, volbar, fhatbar, volbar, ufbface, ufbnbr,
+                                      Gm, Gn);
       k_vjp_final<D, P, T><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(volbar, ufbface, ufbnbr, o, ubar, rk, Ne);
     } else {
       k_vjp_face<D, P, T, false, GEO><<<vblk(nface, 256), 256, 0, st>>>(
@@ -1260,7 +1331,6 @@ struct VjpStepEngine {
     static const double cA[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     static const double cZ[4] = {0.5, 0.5, 1.0, 0.0};
     using TD = VjpDivTile<D, P, T>;
-    using TV = VjpVolTile<D, P, T>;
     const bool ns = s->equations == 1;
     k_vjp_div<D, P, T, GEO, true><<<vblk(Ne, TD::E), TD::BS, 0, st>>>(
         ub, ys[3], metric, o, volbar, fhatbar, uf, GEO ? Rs[3] : nullptr, Gm, Ne, A, dt, s->elem_mesh, (T)cA[3]);
@@ -1269,9 +1339,8 @@ struct VjpStepEngine {
       T *own = ufbface;  // own flux-point adjoint (NS volume adjoint, or the Euler face adjoint)
       T *nbr = ns ? ufbnbr : nullptr;
       if (ns) {
-        k_vjp_ns_vol<D, P, T, GEO><<<vblk(Ne, TV::E), TV::BS, 0, st>>>(
-            ys[k], uf, s->nbr, (const T *)s->fnrm, (const T *)s->bnd_nrm, s->n_wall, metric, s->elem_mesh, fl, o,
-            ph, volbar, fhatbar, volbar, ufbface, ufbnbr, Gm, Gn, Ne);
+        launch_vjp_ns_vol<D, P, T, GEO>(s, st, ys[k], uf, metric, fl, o, ph, volbar, fhatbar, volbar, ufbface,
+                                        ufbnbr, Gm, Gn);
       } else {
         k_vjp_face<D, P, T, false, GEO><<<vblk(nface, 256), 256, 0, st>>>(
             uf, fhatbar, s->pairL, s->pairR, (const T *)s->pair_nrm, s->npair, s->bnd, (const T *)s->bnd_nrm,
@@ -1351,6 +1420,22 @@ bool launch_vjp_rk_step(const fr_solver *s, const void *const ys[4], void *u_bar
   FR_SCASE(3, 2) FR_SCASE(3, 3) FR_SCASE(3, 4) FR_SCASE(3, 5)
 #undef FR_SCASE
   return false;
+}
+
+int vjp_tune_cands(const fr_solver *s, int32_t *cand) {
+#define FR_TCASE(DD, PP)                                            \
+  if (s->dim == DD && s->p + 1 == PP) {                             \
+    if (s->precision == 0) {                                        \
+      VCands<DD, PP, double>::list(cand);                           \
+      return VCands<DD, PP, double>::N;                             \
+    }                                                               \
+    VCands<DD, PP, float>::list(cand);                              \
+    return VCands<DD, PP, float>::N;                                \
+  }
+  FR_TCASE(2, 2) FR_TCASE(2, 3) FR_TCASE(2, 4) FR_TCASE(2, 5)
+  FR_TCASE(3, 2) FR_TCASE(3, 3) FR_TCASE(3, 4) FR_TCASE(3, 5)
+#undef FR_TCASE
+  return 0;
 }
 
 }  // namespace frmi

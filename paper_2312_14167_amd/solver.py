@@ -165,7 +165,7 @@ class Solver:
         check(lib().fr_probe_series(self._h, out.ctypes.data_as(C.c_void_p), int(cap), C.byref(n), _stream(stream)))
         return out[:self.n_probe, :min(int(n.value), cap, self.max_samples)]
 
-    TUNE_KINDS = ["ns_volume", "ns_lift_rk", "euler_volume_rk"]
+    TUNE_KINDS = ["ns_volume", "ns_lift_rk", "euler_volume_rk", "ns_volume_adjoint"]
 
     def autotune(self, u: torch.Tensor, dt: torch.Tensor, reps: int = 3, stream=None) -> dict:
         """Time the candidates of the volume kernels on this mesh (tile size x waves-per-SIMD bound,
@@ -174,14 +174,16 @@ class Solver:
         step of every candidate."""
         self._check_state(u, "u")
         self._check_dt(dt)
-        choice = np.zeros(12, dtype=np.int32)
-        ms = np.zeros(3 * FR_TUNE_MAX)
+        choice = np.zeros(16, dtype=np.int32)
+        ms = np.zeros(4 * FR_TUNE_MAX)
         check(lib().fr_autotune(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), int(reps),
                                 choice.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), _stream(stream)))
-        kinds = [0, 1] if self.equations == "ns" else [2]
+        kinds = [0, 1, 3] if self.equations == "ns" else [2]
         out = {}
         for k in kinds:
             cands = self.tune_candidates(k)
+            if not cands:
+                continue
             out[self.TUNE_KINDS[k]] = {
                 "elements_per_workgroup": int(choice[4 * k]), "waves_per_simd_bound": int(choice[4 * k + 1]),
                 "engine": "mfma" if choice[4 * k + 2] else "valu", "from_cache": bool(choice[4 * k + 3]),
@@ -302,6 +304,30 @@ class Solver:
         rp = C.c_void_p(residuals.data_ptr()) if residuals is not None else None
         check(lib().fr_rk_step_vjp(self._h, C.c_void_p(u_n.data_ptr()), C.c_void_p(dt.data_ptr()), sp, rp,
                                    C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
+        return u_bar
+
+    def rk_segment_vjp(self, states: torch.Tensor, dt: torch.Tensor, u_bar: torch.Tensor, stages: torch.Tensor,
+                       p_bar: torch.Tensor, n_steps: int, x_bar=None, residuals=None, stream=None):
+        """Reverse of n_steps RK4 steps with their probe samples (see fr_rk_segment_vjp): states
+        [>= n, *shape], stages [>= n, 3, *shape], residuals [>= n, 4, *shape] or None, p_bar
+        float64 CUDA [>= n, n_probe]; replayed from a captured graph while the tensors repeat."""
+        self._check_state(u_bar, "u_bar")
+        self._check_dt(dt)
+        n = int(n_steps)
+        for t, name, shp in ((states, "states", (self.shape,)), (stages, "stages", ((3,) + self.shape,))):
+            if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and t.shape[0] >= n
+                    and tuple(t.shape[1:]) == shp[0]):
+                raise ValueError(f"{name} has the wrong shape, dtype or layout")
+        if residuals is not None and not (residuals.is_contiguous() and tuple(residuals.shape[1:]) == (4,) + self.shape
+                                          and residuals.shape[0] >= n and residuals.dtype == self.dtype):
+            raise ValueError("residuals has the wrong shape, dtype or layout")
+        if not (p_bar.is_cuda and p_bar.dtype == torch.float64 and p_bar.is_contiguous()
+                and tuple(p_bar.shape[1:]) == (self.n_probe,) and p_bar.shape[0] >= n):
+            raise ValueError("p_bar must be a contiguous float64 CUDA tensor [n_steps, n_probe]")
+        rp = C.c_void_p(residuals.data_ptr()) if residuals is not None else None
+        check(lib().fr_rk_segment_vjp(self._h, C.c_void_p(states.data_ptr()), C.c_void_p(dt.data_ptr()),
+                                      C.c_void_p(stages.data_ptr()), rp, C.c_void_p(p_bar.data_ptr()), n,
+                                      C.c_void_p(u_bar.data_ptr()), self._xbar_ptr(x_bar), _stream(stream)))
         return u_bar
 
     def geo_adjoint_begin(self, stream=None):
