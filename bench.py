@@ -250,6 +250,9 @@ def cpu_baseline(budget_s: float = 20.0):
 
 
 # ------------------------------------------------------------------------------------ main
+FORWARD_KINDS = ("ns_volume", "ns_lift_rk", "euler_volume_rk")
+
+
 def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None, seed=5, profile=False,
                 autotune=True):
     import torch
@@ -261,7 +264,7 @@ def run_variant(mesh, fp, precision, steps, warmup, probes=None, probe_mesh=None
     u = initial_state(sol, fp, mesh, seed).to(device="cuda", dtype=sol.dtype)
     # stable explicit dt: the trailing-edge cells of the C-grid are ~7e-4 chords long
     dt = torch.full((mesh.n_mesh,), 5e-7 if mesh.dim == 3 else 1e-5, dtype=torch.float64, device="cuda")
-    tiles = sol.autotune(u, dt, reps=3) if autotune else None
+    tiles = sol.autotune(u, dt, reps=3, kinds=FORWARD_KINDS) if autotune else None
     if tiles:
         log("  autotuned: " + ", ".join(f"{k} E={v['elements_per_workgroup']} waves={v['waves_per_simd_bound'] or 'default'} "
                                          f"{v['engine']}{' (remembered)' if v['from_cache'] else ''}"
@@ -449,7 +452,7 @@ def sequential_cavities(bm, bfp, counts, steps, precision="fp32"):
                      max_samples=steps + 4, forces=True)
         u = initial_state(sol, fpk, mk, 5).to(device="cuda", dtype=sol.dtype)
         dt = torch.full((1,), 1e-5, dtype=torch.float64, device="cuda")
-        sol.autotune(u, dt, reps=2)
+        sol.autotune(u, dt, reps=2, kinds=FORWARD_KINDS)
         total += time_steps(sol, u, dt, steps, 2)
         info = solver_info(sol)
         dof += info[0] * info[1] * info[2]

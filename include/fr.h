@@ -254,7 +254,9 @@ fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream);
  * are the tile sizes (elements per workgroup: the default, its half and its quarter) times two
  * register budgets (the default and one alternative waves-per-SIMD launch bound), and for kind 0
  * in FP32 3-D p = 4 the volume divergence on the matrix cores; kind 3: default tile, half tile,
- * default tile with a launch bound; degree-0 groups have the default only.  fr_autotune times
+ * default tile with a launch bound; degree-0 groups have the default only.  kinds_mask: bit k
+ * selects kind k (0: every kind of the solver's equations); the others keep their candidate and
+ * report zero times.  fr_autotune times
  * each candidate on device copies of u (u is not modified) -- `reps` RK4 steps, or for kind 3
  * 4 x reps residual adjoints --, keeps the fastest, remembers it for the rest of the process under
  * (dim, p, precision, equations, LDG form, kind, floor(log2 n_elem)) -- a later solver with the
@@ -270,8 +272,8 @@ fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream);
  * fr_tune_select: use candidate `index` of `kind` from now on (drops the step graphs).
  * fr_tune_cache_clear: forget the remembered choices. */
 #define FR_TUNE_MAX 8
-fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *choice, double *ms,
-                      void *stream);
+fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t kinds_mask,
+                      int32_t *choice, double *ms, void *stream);
 fr_status fr_tune_candidates(const fr_solver *s, int32_t kind, int32_t *cand, int32_t *n);
 fr_status fr_tune_select(fr_solver *s, int32_t kind, int32_t index);
 void fr_tune_cache_clear(void);

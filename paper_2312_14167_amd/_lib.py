@@ -71,7 +71,7 @@ def lib() -> C.CDLL:
     L.fr_rk_step_stages.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     L.fr_rk_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.fr_rk_segment_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
-    L.fr_autotune.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.fr_autotune.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
     L.fr_tune_candidates.argtypes = [vp, i32, vp, C.POINTER(i32)]
     L.fr_tune_select.argtypes = [vp, i32, i32]
     L.fr_tune_cache_clear.argtypes = []

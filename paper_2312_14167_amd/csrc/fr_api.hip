@@ -838,10 +838,11 @@ fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream) {
   return FR_OK;
 }
 
-fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t *choice, double *ms,
-                      void *stream) {
+fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t reps, int32_t kinds_mask,
+                      int32_t *choice, double *ms, void *stream) {
   if (!s || !u || !dt) return fail(FR_ERR_ARG, "NULL argument");
   if (reps < 1) return fail(FR_ERR_ARG, "reps must be >= 1");
+  if (kinds_mask < 0 || kinds_mask > 15) return fail(FR_ERR_ARG, "kinds_mask must be in 0..15");
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t a = nullptr, b = nullptr;
   void *tmp = nullptr, *work = nullptr, *tmp2 = nullptr;
@@ -859,6 +860,7 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
     s->profiling = 0;
     for (int q = 0; q < nk; ++q) {
       const int kind = kinds[q];
+      if (kinds_mask != 0 && !(kinds_mask & (1 << kind))) continue;
       int32_t cand[FR_TUNE_MAX * 3];
       const int nc = cands_of(kind, cand);
       const TuneKey key = tune_key(s, kind);

@@ -167,18 +167,21 @@ class Solver:
 
     TUNE_KINDS = ["ns_volume", "ns_lift_rk", "euler_volume_rk", "ns_volume_adjoint"]
 
-    def autotune(self, u: torch.Tensor, dt: torch.Tensor, reps: int = 3, stream=None) -> dict:
+    def autotune(self, u: torch.Tensor, dt: torch.Tensor, reps: int = 3, kinds=None, stream=None) -> dict:
         """Time the candidates of the volume kernels on this mesh (tile size x waves-per-SIMD bound,
         and the matrix-core divergence where compiled; u is not modified), keep the fastest (or the
         choice remembered for this shape); returns per kernel the chosen candidate and the ms per
-        step of every candidate."""
+        step of every candidate.  kinds: names from TUNE_KINDS to tune (default: all of the
+        solver's)."""
         self._check_state(u, "u")
         self._check_dt(dt)
         choice = np.zeros(16, dtype=np.int32)
         ms = np.zeros(4 * FR_TUNE_MAX)
-        check(lib().fr_autotune(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), int(reps),
+        mask = 0 if kinds is None else sum(1 << self.TUNE_KINDS.index(k) for k in kinds)
+        check(lib().fr_autotune(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(dt.data_ptr()), int(reps), int(mask),
                                 choice.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), _stream(stream)))
-        kinds = [0, 1, 3] if self.equations == "ns" else [2]
+        kinds = [k for k in ([0, 1, 3] if self.equations == "ns" else [2])
+                 if kinds is None or self.TUNE_KINDS[k] in kinds]
         out = {}
         for k in kinds:
             cands = self.tune_candidates(k)
