@@ -172,3 +172,31 @@ def test_conservation_across_degree_jumps_on_gpu(gpu):
     scale = v.integrate([r.abs() for r in R])
     print("relative integral", (tot.abs() / scale).numpy())
     assert float((tot.abs() / scale).max()) < 1e-13
+
+
+@pytest.mark.parametrize("beta", [0.5, 0.0])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_isolated_elements_of_another_degree(dim, beta, gpu):
+    """One element of degree 0 and one of degree 4 inside a periodic box of degree 3 (2-D) or 2
+    (3-D): groups of a single element whose every face is a face between degrees (no pairs and
+    no wall or far-field points of their own), both LDG forms."""
+    from oracle.vardeg import VarDegreeOracle
+    from paper_2312_14167_amd.vardeg import VarDegreeSolver
+    m = fi.periodic_box(dim, 4 if dim == 2 else 3, q=2, curv=0.15, seed=9)
+    deg = np.full(m.n_elem, 3 if dim == 2 else 2)
+    deg[1], deg[m.n_elem - 2] = 0, 4
+    fp = fi.freestream_params(dim, 0.2, 150.0, aoa_deg=30.0)
+    fp.ldg_beta = beta
+    v = VarDegreeOracle(m, deg, fp, equations="ns")
+    u0 = [torch.tensor(fi.developed_state(x, fp, 8, amp=0.05)).permute(0, 2, 1).contiguous()
+          for x in v.solpt_coords()]
+    sol = VarDegreeSolver(m, deg, fp)
+    assert sol.n_elem[0] == 1 and sol.n_elem[-1] == 1 and sol.n_mortar == 4 * dim
+    eR = _err(sol.split(sol.rhs(sol.join(u0))), v.residual(u0))
+    u = sol.join(u0)
+    dt = 1e-3
+    sol.rk_step(u, torch.tensor([dt], dtype=torch.float64, device=gpu), 3)
+    uref, _, _ = v.run(u0, torch.tensor([dt], dtype=torch.float64), 3, sample_every=0, forces=False)
+    e3 = _err(sol.split(u), uref)
+    print(f"dim {dim} beta {beta}: rhs {eR:.3e}, 3 steps {e3:.3e}")
+    assert eR <= 1e-11 and e3 <= 1e-12, (eR, e3)

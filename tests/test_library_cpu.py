@@ -216,3 +216,46 @@ def test_algorithmic_bytes_follow_the_face_flags():
     info2 = (Ne, 4, 25, 20, 5, 30, 0, 1)
     b2 = bench.algorithmic_bytes(info2, 2, 4, "ns", 0.5)
     assert b2["interp"] == Ne * 4 * 25 * 4 + Ne * 20 * 4 * 4 + Ne
+
+
+def _vdeg_build(m, deg, eq="ns", probes=None, n_mesh_override=None):
+    from paper_2312_14167_amd.solver import marshal
+    lb = _lib()
+    L = lb.lib()
+    fp = fi.freestream_params(m.dim, 0.2, 100.0 if eq == "ns" else None)
+    md, prm, keep = marshal(m, 0, fp, eq, "fp64", probes, None, 4 if probes is not None else 0, False)
+    if n_mesh_override:
+        md.n_mesh = n_mesh_override
+    d = np.ascontiguousarray(np.asarray(deg, dtype=np.int32))
+    h = C.c_void_p()
+    st = L.fr_vdeg_build(C.byref(md), d.ctypes.data_as(C.c_void_p), C.byref(prm), C.byref(h))
+    return st, L.fr_last_error().decode(), h
+
+
+def test_variable_degree_host_validation_without_gpu():
+    """fr_vdeg_build refuses bad arguments before any device work: NULL pointers, degrees outside
+    0..4, the Euler equations and several meshes (not built), the internal mortar face tag given
+    as input, and a probe outside the mesh."""
+    lb = _lib()
+    L = lb.lib()
+    assert L.fr_vdeg_build(None, None, None, None) == lb.FR_ERR_ARG
+    h = C.c_void_p()
+    assert L.fr_vdeg_build(None, None, None, C.byref(h)) == lb.FR_ERR_ARG
+    m = fi.periodic_box(2, 3, q=1, bc="farfield")
+    deg = np.full(m.n_elem, 2)
+    deg[0] = 5
+    st, msg, _ = _vdeg_build(m, deg)
+    assert st == lb.FR_ERR_ARG and "degree" in msg
+    st, msg, _ = _vdeg_build(m, np.full(m.n_elem, 2), eq="euler")
+    assert st == lb.FR_ERR_UNSUPPORTED
+    st, msg, _ = _vdeg_build(m, np.full(m.n_elem, 2), n_mesh_override=2)
+    assert st == lb.FR_ERR_UNSUPPORTED
+    m2 = fi.periodic_box(2, 3, q=1, bc="farfield")
+    m2.face_bc[0, 0] = 3
+    st, msg, _ = _vdeg_build(m2, np.full(m2.n_elem, 2))
+    assert st == lb.FR_ERR_ARG and "tag" in msg
+    st, msg, _ = _vdeg_build(m, np.full(m.n_elem, 2), probes=np.array([[50.0, 0.0]]))
+    assert st == lb.FR_ERR_MESH and "probe" in msg
+    assert L.fr_vdeg_rhs(None, None, None, None) == lb.FR_ERR_ARG
+    assert L.fr_vdeg_rk_step(None, None, None, 1, 0, None) == lb.FR_ERR_ARG
+    L.fr_vdeg_destroy(None)
