@@ -120,7 +120,10 @@ struct GradTile {
   static constexpr int LG = cmax(S::NV * S::Nf + LC, D * S::NV * S::Ns);
   static constexpr int LS = KEEP2D ? D * D * S::Ns + S::NV * S::Nf : 0;
   static constexpr int LE = LU + LG + LS;
-  static constexpr int E = EE > 0 ? EE : cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
+  // degree 0 (a degree group of a variable-degree mesh): at most 16 elements, so that a group of
+  // ten thousand elements still spreads over every CU
+  static constexpr int E0 = cmax(1, cmin(512 / S::Ns, (40 * 1024 - 640) / (LE * (int)sizeof(T))));
+  static constexpr int E = EE > 0 ? EE : (P == 1 ? cmin(E0, 16) : E0);
   static constexpr int BS = round64(E * S::Ns);
   // register budget (launch bound, waves per SIMD): 4 (128 VGPRs) in FP64, 7 (72 VGPRs) in FP32
   // by default; WW > 0 (an autotuner candidate) sets it
@@ -141,7 +144,9 @@ template <int D, int P, typename T, int EE = 0>
 struct DivTile {
   using S = Shape<D, P>;
   static constexpr int LE = cmax(UfLayout<D, P, T>::EB, S::NV * S::Ns);  // common-flux tile, then state
-  static constexpr int E = EE > 0 ? EE : tile_elems<S::Ns>(LE, sizeof(T));
+  // degree 0: at most 32 elements per workgroup (see GradTile)
+  static constexpr int E = EE > 0 ? EE : (P == 1 ? cmin(tile_elems<S::Ns>(LE, sizeof(T)), 32)
+                                                  : tile_elems<S::Ns>(LE, sizeof(T)));
   static constexpr int BS = round64(E * S::Ns);
 };
 
