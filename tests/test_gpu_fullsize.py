@@ -199,3 +199,68 @@ def test_vortex_full_size_20_steps(gpu):
     eo = float((uref - ue).abs().max())
     print(f"vortex: |GPU - exact| {eg:.3e}, |oracle - exact| {eo:.3e}")
     assert abs(eg - eo) <= 1e-12 and eg < 1e-4
+
+
+def test_naca_sponge_full_size_sampled_residual(gpu):
+    """The variable-degree solver on the full C-grid with the bench's sponge degrees (4 near the
+    section to 0 beyond 8 chords): sampled elements next to degree jumps, at the wall and at the
+    outer boundary against the variable-degree oracle on the index-space patch around them (the
+    degrees of the patch's elements kept)."""
+    import bench
+    from oracle.vardeg import VarDegreeOracle
+    from paper_2312_14167_amd.vardeg import VarDegreeSolver
+    mesh, fp, _ = bench.naca_workload(scale=1.0)
+    deg = fi.sponge_degrees(mesh, radii=bench.SPONGE_RADII)
+    sol = VarDegreeSolver(mesh, deg, fp, precision="fp64")
+    parts = []
+    for g, x in enumerate(sol.solpt_coords()):
+        ug = fi.freestream_state(x, fp)
+        ug[..., 1:-1] += fi.noise_like(ug.shape, 5 + g, 1e-3)[..., 1:-1]
+        parts.append(torch.tensor(ug).permute(0, 2, 1).contiguous())
+    R = [r.cpu() for r in sol.split(sol.rhs(sol.join(parts)))]
+    where = {}  # element -> (group, local index)
+    for g, el in enumerate(sol.elems):
+        for l, e in enumerate(el):
+            where[int(e)] = (g, l)
+    gi = mesh.info["grid_index"]
+    na, nn, nz = gi[:, 0].max() + 1, gi[:, 1].max() + 1, gi[:, 2].max() + 1
+    index = {tuple(int(v) for v in gi[e]): e for e in range(mesh.n_elem)}
+
+    def jump(e, lo, hi):
+        i, j, k = (int(v) for v in gi[e])
+        if deg[e] != hi:
+            return False
+        for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            n = index.get((i + di, j + dj, k))
+            if n is not None and deg[n] == lo:
+                return True
+        return False
+    picks = []
+    for lo, hi in ((3, 4), (2, 3), (1, 2), (0, 1)):
+        picks.append(next(e for e in range(0, mesh.n_elem, 7) if jump(e, lo, hi)))
+    picks.append(index[(100, 0, 4)])                                  # wall at the leading edge
+    picks.append(next(e for e in range(mesh.n_elem) if gi[e, 1] == nn - 1 and gi[e, 2] == 7))  # outer boundary
+    for e in picks:
+        i, j, k = (int(v) for v in gi[e])
+        ib = [x for x in range(i - 2, i + 3) if 0 <= x < na]
+        jb = [x for x in range(j - 2, j + 3) if 0 <= x < nn]
+        kb = [x % nz for x in range(k - 2, k + 3)]
+        boxes = [[ib, jb, kb]]
+        if j <= 2:  # across the wake cut
+            boxes.append([[na - 1 - x for x in ib if 0 <= na - 1 - x < na], [0, 1, 2], kb])
+        sel, sub = _patch(mesh, e, boxes)
+        v = _close_patch(sub, lambda m_, p_, f_, equations: VarDegreeOracle(m_, deg[sel], f_, equations=equations),
+                         None, fp)
+        # the patch's state, group by group in the oracle's order
+        up = []
+        for G in v.groups:
+            rows = [parts[where[int(sel[le])][0]][where[int(sel[le])][1]] for le in G.elems]
+            up.append(torch.stack(rows))
+        Rp = v.residual(up)
+        le = int(np.nonzero(sel == e)[0][0])
+        gp, lp = int(v.gidx[le]), int(v.lidx[le])
+        g, l = where[e]
+        err = _rel(R[g][l].numpy(), Rp[gp][lp].numpy())
+        print(f"sponge element {e} grid {(i, j, k)} degree {deg[e]}: patch of {len(sel)} "
+              f"(degrees {sorted(set(deg[sel].tolist()))}); residual rel L2 {err:.3e}")
+        assert err <= FULL_SIZE_TOL, err
