@@ -715,16 +715,17 @@ fr_status fr_vdeg_probe_series(fr_vdeg *v, double *series, int64_t cap, int64_t 
   *n = 0;
   for (int g = 0; g < v->n_group; ++g) {
     const fr_solver *c = v->child[g];
-    std::vector<double> buf((size_t)std::max(1, c->n_probe) * std::max<int64_t>(cap, 1));
+    // the group's series, strided by what it keeps (not by the caller's capacity)
+    const int64_t cc = c->n_probe ? std::min<int64_t>(cap, c->cap) : 0;
+    std::vector<double> buf((size_t)std::max(1, c->n_probe) * std::max<int64_t>(cc, 1));
     int64_t ng = 0;
-    const fr_status st = fr_probe_series(v->child[g], c->n_probe ? buf.data() : nullptr, c->n_probe ? cap : 0, &ng,
-                                         stream);
+    const fr_status st = fr_probe_series(v->child[g], cc ? buf.data() : nullptr, cc, &ng, stream);
     if (st != FR_OK) return st;
     *n = ng;
-    const int64_t k = std::min<int64_t>(ng, std::min<int64_t>(cap, c->cap));
+    const int64_t k = std::min<int64_t>(ng, cc);
     for (int a = 0; a < v->n_probe; ++a)
       if (v->probe_group[a] == g)
-        for (int64_t j = 0; j < k; ++j) series[a * cap + j] = buf[(size_t)v->probe_slot[a] * cap + j];
+        for (int64_t j = 0; j < k; ++j) series[a * cap + j] = buf[(size_t)v->probe_slot[a] * cc + j];
   }
   return FR_OK;
 }
