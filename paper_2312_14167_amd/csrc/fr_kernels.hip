@@ -306,6 +306,12 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE,
     if (idx >= ne * Nf) break;
     const int fc0 = s_face[idx / Nfp];
     const int el = fc0 / NFACE, fp = (fc0 % NFACE) * Nfp + idx % Nfp;
+    if (side != 0 && idx >= s_nface * Nfp) {
+      // one-sided LDG, the side that provides u^: u^ is its own u_f (weight exactly 1, the
+      // neighbour's 0), so u^ - u_f is zero and neither the value nor the gather is needed
+      for (int v = 0; v < NV; ++v) lw[(el * NV + v) * Nf + fp] = T(0);
+      continue;
+    }
     int base, stride, fs;
     line_of_fpt<D, P>(fp, base, stride, fs);
     const T *lv = fs ? ops.lp : ops.lm;
