@@ -43,6 +43,7 @@ namespace {
 constexpr int MAX_GROUPS = 5;         // degrees 0..4
 constexpr int MORTAR_BS = 64;         // one workgroup (one wave) per mortar face
 constexpr int MAX_MORTAR_PTS = 25;    // (p_hi + 1)^(dim - 1)
+constexpr int MAX_LO_PTS = 16;        // (p_lo + 1)^(dim - 1), p_lo < p_hi
 constexpr int64_t STATE_ALIGN = 64;   // values: group states start on 256-byte boundaries
 
 #define VD_HIP_OK(expr)                                                                      \
@@ -81,13 +82,28 @@ __device__ __forceinline__ int64_t gpt(const GroupDev<T> &g, int64_t e, int fp) 
   return g.skip ? e * g.EB + (int64_t)(fp / g.Nfp) * g.FST + fp % g.Nfp : e * g.EB + fp;
 }
 
-// value of variable-major array `a` (u_f layout) of both sides at mortar point i: the higher
-// side's own value and the lower side's trace polynomial there
+// the lower side's u_f and (lo_f != nullptr) its viscous normal flux at its face points, in
+// canonical order, into LDS: the workgroup loads each value once, one per lane
 template <int D, typename T>
-__device__ __forceinline__ void mortar_pair(const MortarFace &mf, const GroupDev<T> &H, const GroupDev<T> &L,
-                                            const T *ah, const T *al, const T *I, int i, T *vh, T *vl) {
+__device__ __forceinline__ void stage_lower(const MortarFace &mf, const int8_t *perm, const GroupDev<T> &L,
+                                            T (*lo_u)[D + 2], T (*lo_f)[D + 2]) {
   constexpr int NV = D + 2;
-  const int Nm = H.Nfp, Nlo = L.Nfp;
+  const int Nlo = L.Nfp;
+  for (int k = (int)threadIdx.x; k < Nlo * NV; k += MORTAR_BS) {
+    const int v = k / Nlo, j = k % Nlo;
+    const int fp = mf.f_lo * Nlo + perm[j];
+    lo_u[j][v] = L.uf[gpt(L, mf.e_lo, fp) + v * L.VS];
+    if (lo_f) lo_f[j][v] = L.fvn[((int64_t)mf.e_lo * NV + v) * L.Nf + fp];
+  }
+}
+
+// at mortar point i: the higher side's own value of variable-major array `ah` (u_f layout) and the
+// lower side's trace polynomial there, from its staged face values lo
+template <int D, typename T>
+__device__ __forceinline__ void mortar_pair(const MortarFace &mf, const GroupDev<T> &H, const T *ah,
+                                            const T (*lo)[D + 2], int Nlo, const T *I, int i, T *vh, T *vl) {
+  constexpr int NV = D + 2;
+  const int Nm = H.Nfp;
   const int64_t ph = gpt(H, mf.e_hi, mf.f_hi * Nm + i);
   for (int v = 0; v < NV; ++v) {
     vh[v] = ah[ph + v * H.VS];
@@ -95,8 +111,7 @@ __device__ __forceinline__ void mortar_pair(const MortarFace &mf, const GroupDev
   }
   for (int j = 0; j < Nlo; ++j) {
     const T c = I[i * Nlo + j];
-    const int64_t pl = gpt(L, mf.e_lo, mf.f_lo * Nlo + mf.perm[j]);
-    for (int v = 0; v < NV; ++v) vl[v] += c * al[pl + v * L.VS];
+    for (int v = 0; v < NV; ++v) vl[v] += c * lo[j][v];
   }
 }
 
@@ -108,14 +123,18 @@ __global__ __launch_bounds__(MORTAR_BS) void k_mortar_sol(const MortarFace *__re
                                                           const T *__restrict__ tabs, T wl, T wr) {
   constexpr int NV = D + 2;
   __shared__ T lu[MAX_MORTAR_PTS][NV];
+  __shared__ T llo[MAX_LO_PTS][NV];
   const MortarFace mf = faces[blockIdx.x];
+  const int8_t *perm = faces[blockIdx.x].perm;
   const GroupDev<T> H = grp[mf.g_hi], L = grp[mf.g_lo];
   const int Nm = H.Nfp, Nlo = L.Nfp;
   const T *I = tabs + mf.tab, *Pi = I + Nm * Nlo;
   const int i = threadIdx.x;
+  stage_lower<D, T>(mf, perm, L, llo, nullptr);
+  __syncthreads();
   if (i < Nm) {
     T uh[NV], ul[NV];
-    mortar_pair<D, T>(mf, H, L, H.uf, L.uf, I, i, uh, ul);
+    mortar_pair<D, T>(mf, H, H.uf, llo, Nlo, I, i, uh, ul);
     for (int v = 0; v < NV; ++v) {
       const T w = mf.hi_is_L ? wl * uh[v] + wr * ul[v] : wl * ul[v] + wr * uh[v];
       lu[i][v] = w;
@@ -130,7 +149,7 @@ __global__ __launch_bounds__(MORTAR_BS) void k_mortar_sol(const MortarFace *__re
       const T c = Pi[i * Nm + m];
       for (int v = 0; v < NV; ++v) s[v] += c * lu[m][v];
     }
-    for (int v = 0; v < NV; ++v) L.ifc_uh[(int64_t)(mf.q_lo + mf.perm[i]) * NV + v] = s[v];
+    for (int v = 0; v < NV; ++v) L.ifc_uh[(int64_t)(mf.q_lo + perm[i]) * NV + v] = s[v];
   }
 }
 
@@ -144,15 +163,19 @@ __global__ __launch_bounds__(MORTAR_BS) void k_mortar_flux(const MortarFace *__r
                                                            const T *__restrict__ tabs, PhysDev<T> ph) {
   constexpr int NV = D + 2;
   __shared__ T lf[MAX_MORTAR_PTS][NV];
+  __shared__ T llo[MAX_LO_PTS][NV], llf[MAX_LO_PTS][NV];
   const MortarFace mf = faces[blockIdx.x];
+  const int8_t *perm = faces[blockIdx.x].perm;
   const GroupDev<T> H = grp[mf.g_hi], L = grp[mf.g_lo];
   const int Nm = H.Nfp, Nlo = L.Nfp;
   const T *I = tabs + mf.tab, *Pi = I + Nm * Nlo;
   const T sh = mf.hi_is_L ? T(1) : T(-1);
   const int i = threadIdx.x;
+  stage_lower<D, T>(mf, perm, L, llo, llf);
+  __syncthreads();
   if (i < Nm) {
     T uh[NV], ul[NV], fh[NV], fl[NV];
-    mortar_pair<D, T>(mf, H, L, H.uf, L.uf, I, i, uh, ul);
+    mortar_pair<D, T>(mf, H, H.uf, llo, Nlo, I, i, uh, ul);
     {
       const int fph = mf.f_hi * Nm + i;
       for (int v = 0; v < NV; ++v) {
@@ -161,8 +184,7 @@ __global__ __launch_bounds__(MORTAR_BS) void k_mortar_flux(const MortarFace *__r
       }
       for (int j = 0; j < Nlo; ++j) {
         const T c = I[i * Nlo + j];
-        const int fpl = mf.f_lo * Nlo + mf.perm[j];
-        for (int v = 0; v < NV; ++v) fl[v] += c * L.fvn[((int64_t)mf.e_lo * NV + v) * L.Nf + fpl];
+        for (int v = 0; v < NV; ++v) fl[v] += c * llf[j][v];
       }
     }
     const T *bn = H.bnd_nrm + (H.n_bc + mf.q_hi + i) * (D + 1);
@@ -194,7 +216,7 @@ __global__ __launch_bounds__(MORTAR_BS) void k_mortar_flux(const MortarFace *__r
       const T c = Pi[i * Nm + m];
       for (int v = 0; v < NV; ++v) s[v] += c * lf[m][v];
     }
-    const int64_t po = gpt(L, mf.e_lo, mf.f_lo * Nlo + mf.perm[i]);
+    const int64_t po = gpt(L, mf.e_lo, mf.f_lo * Nlo + perm[i]);
     for (int v = 0; v < NV; ++v) L.fhat[po + v * L.VS] = -sh * s[v];
   }
 }
