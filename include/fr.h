@@ -43,7 +43,7 @@ typedef int32_t fr_status;
 #define FR_ERR_UNSUPPORTED  -3  /* (dim, p) combination not compiled                    */
 #define FR_ERR_HIP          -4  /* HIP runtime error (launch, copy, device fault)       */
 #define FR_ERR_NONFINITE    -5  /* a sampled probe pressure was NaN / Inf               */
-#define FR_ERR_OOM          -6  /* device allocation failed                             */
+#define FR_ERR_OOM          -6  /* device or host allocation failed                     */
 
 /* face tags (per element face) */
 #define FR_FACE_AUTO     0   /* matched geometrically with another face (conforming or periodic) */

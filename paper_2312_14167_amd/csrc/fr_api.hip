@@ -421,6 +421,8 @@ fr_status fr_rhs(fr_solver *s, const void *u, void *r, void *stream) {
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -463,6 +465,8 @@ fr_status fr_rk_step(fr_solver *s, void *u, const double *dt, int32_t n_steps, i
     }
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -479,6 +483,8 @@ fr_status fr_reset_accumulators(fr_solver *s, void *stream) {
     s->steps_since_reset = 0;
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -510,6 +516,8 @@ fr_status fr_force_coefficients(fr_solver *s, int32_t n_dir, const double *dirs,
     }
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -531,6 +539,8 @@ fr_status fr_probe_series(fr_solver *s, double *series, int64_t cap, int64_t *n,
     }
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -579,6 +589,8 @@ fr_status fr_probe_oaspl(fr_solver *s, double p_ref, double *prms, double *oaspl
     if (nf) return fail(FR_ERR_NONFINITE, "a sampled probe pressure is not finite");
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -599,6 +611,8 @@ fr_status fr_rhs_vjp_noalloc(fr_solver *s, const void *u, const void *r_bar, voi
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -627,6 +641,8 @@ fr_status fr_rhs_vjp(fr_solver *s, const void *u, const void *r_bar, void *u_bar
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -639,6 +655,8 @@ fr_status fr_probe_vjp(fr_solver *s, const void *u, const double *p_bar, void *u
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -654,6 +672,8 @@ fr_status fr_rk_step_stages(fr_solver *s, void *u, const double *dt, int32_t n_s
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -722,6 +742,8 @@ fr_status fr_rk_step_vjp(fr_solver *s, const void *u_n, const double *dt, const 
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -807,6 +829,8 @@ fr_status fr_rk_segment_vjp(fr_solver *s, const void *states, const double *dt, 
     HIP_OK(hipGraphLaunch(g->ex, st));
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -820,6 +844,8 @@ fr_status fr_geo_adjoint_begin(fr_solver *s, void *stream) {
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -834,6 +860,8 @@ fr_status fr_geo_adjoint_end(fr_solver *s, double *x_bar, void *stream) {
     HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -846,6 +874,10 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t a = nullptr, b = nullptr;
   void *tmp = nullptr, *work = nullptr, *tmp2 = nullptr;
+  // restored if timing fails part way, so the solver keeps the candidates it had
+  const int prof = s->profiling;
+  int tune0[4];
+  for (int k = 0; k < 4; ++k) tune0[k] = s->tune[k];
   try {
     Dispatch d = dispatch_of(s);
     const size_t nb = (size_t)s->Ne * s->NV * s->Ns * s->tsize;
@@ -856,7 +888,6 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
     double times[4][FR_TUNE_MAX] = {};
     int cached[4] = {0, 0, 0, 0};
     auto cands_of = [&](int kind, int32_t *cand) { return kind == 3 ? vjp_tune_cands(s, cand) : d.tune_cands(kind, cand); };
-    const int prof = s->profiling;
     s->profiling = 0;
     for (int q = 0; q < nk; ++q) {
       const int kind = kinds[q];
@@ -893,6 +924,7 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
           if (!work) {
             HIP_OK(hipMalloc(&work, vjp_work_elems(s) * s->tsize));
             HIP_OK(hipMalloc(&tmp2, nb));
+            HIP_OK(hipMemsetAsync(tmp2, 0, nb, st));  // u_bar accumulates: start from finite values
           }
           const GeoVjpArgs geo{};
           auto vjp = [&]() {
@@ -939,18 +971,25 @@ fr_status fr_autotune(fr_solver *s, const void *u, const double *dt, int32_t rep
     if (ms)
       for (int k = 0; k < 4; ++k)
         for (int c = 0; c < FR_TUNE_MAX; ++c) ms[k * FR_TUNE_MAX + c] = times[k][c];
-    if (a) HIP_OK(hipEventDestroy(a));
-    if (b) HIP_OK(hipEventDestroy(b));
-    if (tmp) HIP_OK(hipFree(tmp));
-    if (work) HIP_OK(hipFree(work));
-    if (tmp2) HIP_OK(hipFree(tmp2));
-  } catch (const FrError &e) {
+    // every candidate run has ended (the last event was waited for); release the work areas
+    const hipError_t rel[5] = {a ? hipEventDestroy(a) : hipSuccess, b ? hipEventDestroy(b) : hipSuccess,
+                               tmp ? hipFree(tmp) : hipSuccess, work ? hipFree(work) : hipSuccess,
+                               tmp2 ? hipFree(tmp2) : hipSuccess};
+    a = b = nullptr;
+    tmp = work = tmp2 = nullptr;
+    for (const hipError_t r : rel) HIP_OK(r);
+  } catch (const std::exception &ex) {
+    (void)hipStreamSynchronize(st);  // no candidate run may still use the work areas
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     if (tmp) (void)hipFree(tmp);
     if (work) (void)hipFree(work);
     if (tmp2) (void)hipFree(tmp2);
-    return fail(e.code, e.what());
+    s->profiling = prof;
+    for (int k = 0; k < 4; ++k) s->tune[k] = tune0[k];
+    free_graphs(s);
+    const FrError *fe = dynamic_cast<const FrError *>(&ex);
+    return fail(fe ? fe->code : FR_ERR_OOM, ex.what());
   }
   return FR_OK;
 }
@@ -963,6 +1002,8 @@ fr_status fr_tune_candidates(const fr_solver *s, int32_t kind, int32_t *cand, in
     *n = kind == 3 ? vjp_tune_cands(s, cand) : d.tune_cands(kind, cand);
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -979,6 +1020,8 @@ fr_status fr_tune_select(fr_solver *s, int32_t kind, int32_t index) {
     free_graphs(s);
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -1030,6 +1073,8 @@ fr_status fr_profile_read(fr_solver *s, double *total_ms, int64_t *launches, voi
     }
   } catch (const FrError &e) {
     return fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }

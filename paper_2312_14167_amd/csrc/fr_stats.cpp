@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <vector>
+#include <new>
 
 #include "../../include/fr.h"
 
@@ -60,19 +61,23 @@ fr_status fr_stats_observer_oaspl(const double *series, int32_t n_probe, int64_t
                                   int32_t n_group, double p_ref, double *prms, double *oaspl) {
   if (!series || !group || !prms || !oaspl || n_probe < 1 || n < 1 || n_group < 1 || !(p_ref > 0.0))
     return FR_ERR_ARG;
-  std::vector<double> sum(n_group, 0.0), tmp(n);
-  std::vector<int> cnt(n_group, 0);
-  for (int32_t a = 0; a < n_probe; ++a) {
-    const int32_t g = group[a];
-    if (g < 0 || g >= n_group) return FR_ERR_ARG;
-    cumulative_rms(series + (int64_t)a * n, n, tmp.data());
-    sum[g] += tmp[n - 1];
-    cnt[g] += 1;
-  }
-  for (int32_t g = 0; g < n_group; ++g) {
-    if (cnt[g] == 0) return FR_ERR_ARG;
-    prms[g] = sum[g] / cnt[g];
-    oaspl[g] = prms[g] > 0.0 ? 20.0 * std::log10(prms[g] / p_ref) : -INFINITY;
+  try {
+    std::vector<double> sum(n_group, 0.0), tmp(n);
+    std::vector<int> cnt(n_group, 0);
+    for (int32_t a = 0; a < n_probe; ++a) {
+      const int32_t g = group[a];
+      if (g < 0 || g >= n_group) return FR_ERR_ARG;
+      cumulative_rms(series + (int64_t)a * n, n, tmp.data());
+      sum[g] += tmp[n - 1];
+      cnt[g] += 1;
+    }
+    for (int32_t g = 0; g < n_group; ++g) {
+      if (cnt[g] == 0) return FR_ERR_ARG;
+      prms[g] = sum[g] / cnt[g];
+      oaspl[g] = prms[g] > 0.0 ? 20.0 * std::log10(prms[g] / p_ref) : -INFINITY;
+    }
+  } catch (const std::bad_alloc &) {
+    return FR_ERR_OOM;
   }
   return FR_OK;
 }
@@ -87,28 +92,37 @@ fr_status fr_stats_psd_welch(const double *series, int64_t n, int32_t n_windows,
   const int64_t hop = L / 2, nf = L / 2 + 1;
   *n_freq = nf;
   if (cap < nf) return FR_ERR_ARG;
-  std::vector<double> w(L);
+  std::vector<double> w;
+  try {
+    w.resize(L);
+  } catch (const std::bad_alloc &) {
+    return FR_ERR_OOM;
+  }
   double w2 = 0.0;
   for (int64_t t = 0; t < L; ++t) {  // periodic Hann window
     w[t] = 0.5 - 0.5 * std::cos(2.0 * M_PI * (double)t / (double)L);
     w2 += w[t] * w[t];
   }
   const double fs = 1.0 / sample_dt;
-  std::vector<double> acc(nf, 0.0), x(L), pw;
-  for (int32_t k = 0; k < n_windows; ++k) {
-    const double *seg = series + (int64_t)k * hop;
-    double mean = 0.0;
-    for (int64_t t = 0; t < L; ++t) mean += seg[t];
-    mean /= (double)L;
-    for (int64_t t = 0; t < L; ++t) x[t] = (seg[t] - mean) * w[t];  // pressure perturbation per segment
-    dft_power(x, pw);
-    for (int64_t f = 0; f < nf; ++f) acc[f] += pw[f];
-  }
-  for (int64_t f = 0; f < nf; ++f) {
-    // one-sided density: double every bin except DC and (even L) Nyquist
-    const bool edge = f == 0 || (L % 2 == 0 && f == L / 2);
-    psd[f] = acc[f] / n_windows / (fs * w2) * (edge ? 1.0 : 2.0);
-    freq[f] = (double)f * fs / (double)L;
+  try {
+    std::vector<double> acc(nf, 0.0), x(L), pw;
+    for (int32_t k = 0; k < n_windows; ++k) {
+      const double *seg = series + (int64_t)k * hop;
+      double mean = 0.0;
+      for (int64_t t = 0; t < L; ++t) mean += seg[t];
+      mean /= (double)L;
+      for (int64_t t = 0; t < L; ++t) x[t] = (seg[t] - mean) * w[t];  // pressure perturbation per segment
+      dft_power(x, pw);
+      for (int64_t f = 0; f < nf; ++f) acc[f] += pw[f];
+    }
+    for (int64_t f = 0; f < nf; ++f) {
+      // one-sided density: double every bin except DC and (even L) Nyquist
+      const bool edge = f == 0 || (L % 2 == 0 && f == L / 2);
+      psd[f] = acc[f] / n_windows / (fs * w2) * (edge ? 1.0 : 2.0);
+      freq[f] = (double)f * fs / (double)L;
+    }
+  } catch (const std::bad_alloc &) {
+    return FR_ERR_OOM;
   }
   return FR_OK;
 }

@@ -674,6 +674,8 @@ fr_status fr_vdeg_rhs(fr_vdeg *v, const void *u, void *r, void *stream) {
     VD_HIP_OK(hipGetLastError());
   } catch (const FrError &e) {
     return vd_fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return vd_fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
@@ -717,6 +719,8 @@ fr_status fr_vdeg_rk_step(fr_vdeg *v, void *u, const double *dt, int32_t n_steps
     }
   } catch (const FrError &e) {
     return vd_fail(e.code, e.what());
+  } catch (const std::exception &e) {  // host allocation
+    return vd_fail(FR_ERR_OOM, e.what());
   }
   return FR_OK;
 }
