@@ -6,7 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <vector>
-#include <new>
+#include <exception>
 
 #include "../../include/fr.h"
 
@@ -76,7 +76,7 @@ fr_status fr_stats_observer_oaspl(const double *series, int32_t n_probe, int64_t
       prms[g] = sum[g] / cnt[g];
       oaspl[g] = prms[g] > 0.0 ? 20.0 * std::log10(prms[g] / p_ref) : -INFINITY;
     }
-  } catch (const std::bad_alloc &) {
+  } catch (const std::exception &) {  // allocation (bad_alloc, or a size beyond max_size)
     return FR_ERR_OOM;
   }
   return FR_OK;
@@ -95,7 +95,7 @@ fr_status fr_stats_psd_welch(const double *series, int64_t n, int32_t n_windows,
   std::vector<double> w;
   try {
     w.resize(L);
-  } catch (const std::bad_alloc &) {
+  } catch (const std::exception &) {  // allocation (bad_alloc, or a size beyond max_size)
     return FR_ERR_OOM;
   }
   double w2 = 0.0;
@@ -121,7 +121,7 @@ fr_status fr_stats_psd_welch(const double *series, int64_t n, int32_t n_windows,
       psd[f] = acc[f] / n_windows / (fs * w2) * (edge ? 1.0 : 2.0);
       freq[f] = (double)f * fs / (double)L;
     }
-  } catch (const std::bad_alloc &) {
+  } catch (const std::exception &) {  // allocation (bad_alloc, or a size beyond max_size)
     return FR_ERR_OOM;
   }
   return FR_OK;

@@ -163,6 +163,12 @@ def test_host_statistics_argument_errors():
     grp = np.array([0, 2], dtype=np.int32)
     two = np.ones((2, 10))
     assert L.fr_stats_observer_oaspl(_dp(two), 2, 10, _dp(grp), 2, 1.0, _dp(out), _dp(out)) == -1
+    # a work area no host can hold is refused with FR_ERR_OOM before any sample is read (the
+    # exception stays inside the library)
+    huge = 1 << 62
+    assert L.fr_stats_psd_welch(_dp(y), huge, 1, 0.1, _dp(out), _dp(out), huge, C.byref(nf)) == -6
+    assert L.fr_stats_observer_oaspl(_dp(two), 2, huge, _dp(np.zeros(2, dtype=np.int32)), 1, 1.0, _dp(out),
+                                     _dp(out)) == -6
 
 
 def test_bench_refuses_more_than_one_gpu():
