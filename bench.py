@@ -346,6 +346,40 @@ def mfma_comparison(mesh, fp, steps, warmup, seed=5):
     return out
 
 
+def interface_forms(mesh, fp, steps, warmup, seed=5):
+    """The headline C-grid (FP64) in the two forms that run the standalone interface kernel
+    `k_face_flux` (left/right flux-point states gathered per pair): the two-sided LDG flux (beta = 0,
+    every flux point supplies a viscous normal flux) and the Euler equations.  Per-kernel average
+    launch times and fractions of the HBM roofline on each kernel's algorithmic bytes."""
+    import dataclasses
+
+    import torch
+    from paper_2312_14167_amd import Solver
+    out = {}
+    for name, eq, beta in (("ns_two_sided_ldg", "ns", 0.0), ("euler", "euler", fp.ldg_beta)):
+        f2 = dataclasses.replace(fp, ldg_beta=beta)
+        sol = Solver(mesh, 4, f2, equations=eq, precision="fp64", probes=mesh.info["probe"][None, :],
+                     max_samples=max(steps + warmup, 1) * 8, forces=(eq == "ns"))
+        u = initial_state(sol, f2, mesh, seed).to(device="cuda", dtype=sol.dtype)
+        dt = torch.full((1,), 5e-7, dtype=torch.float64, device="cuda")
+        t = time_steps(sol, u, dt, steps, warmup)
+        kern = kernel_profile(sol, u, dt, max(2, min(steps, 10)))
+        info = solver_info(sol)
+        ab = algorithmic_bytes(info, 3, 8, eq, beta)
+        r = {"ms_per_step": 1e3 * t / steps, "gdofs": info[0] * info[1] * info[2] * 4 * steps / t / 1e9, "kernels": {}}
+        for k, (ms, n) in kern.items():
+            e = {"avg_ms": ms / n}
+            if ab.get(k, 0) > 0:
+                e["algorithmic_GB"] = ab[k] / 1e9
+                e["frac"] = ab[k] / (ms / n * 1e-3) / 1e9 / HBM_PEAK_GBS
+            r["kernels"][k] = e
+        out[name] = r
+        sol.close()
+        del u
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_ratio(K=200, C=20):
     """Forward RK4 trajectory with probe sampling vs its checkpointed adjoint (gradient of the
     time-mean square probe-pressure fluctuation w.r.t. the initial state), cylinder O-grid
@@ -471,7 +505,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 192,000 hexes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["adjoint", "drift", "batched", "fp32", "sponge", "mfma"],
+    ap.add_argument("--only", choices=["adjoint", "drift", "batched", "fp32", "sponge", "mfma", "interface"],
                     help="run one secondary measurement alone (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -509,6 +543,9 @@ def main():
         elif args.only == "sponge":
             mesh, fp, aoa = naca_workload(scale=args.scale)
             r = {pr: run_sponge(mesh, fp, pr, K, W) for pr in ("fp64", "fp32")}
+        elif args.only == "interface":
+            mesh, fp, aoa = naca_workload(scale=args.scale)
+            r = interface_forms(mesh, fp, K, W)
         else:
             bm, bfp, bprobes, counts = cavity_batch()
             r = run_variant(bm, bfp, "fp32", K, W, probes=bprobes, probe_mesh=np.arange(16))

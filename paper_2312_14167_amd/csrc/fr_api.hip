@@ -350,7 +350,7 @@ fr_status build_solver(const fr_mesh_desc *mesh, const fr_params *prm, bool grou
     s->acc = dalloc(s, nsol * T);
     s->ustage = dalloc(s, nsol * T);
     if (s->equations == FR_NAVIER_STOKES) {
-      s->fvn = dalloc(s, nf * T);
+      s->fvn = dalloc(s, (size_t)s->Ne * 2 * s->dim * (size_t)uf_face_stride(s->NV * s->Nfp, (int)T) * T);
       s->vol = dalloc(s, nsol * T);
     }
     if (s->nbnd > s->n_bc) s->ifc_uh = dalloc(s, (size_t)(s->nbnd - s->n_bc) * s->NV * T);

@@ -64,13 +64,13 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
       const T wl = T(0.5) - ph.beta, wr = T(0.5) + ph.beta;
       // a side with zero weight (one-sided LDG) never had its fvn computed: not read
       if (wl == T(0)) {
-        for (int v = 0; v < NV; ++v) F[v] -= -wr * fvn[(eR * NV + v) * Nf + fR] - ph.tau * (uL[v] - uR[v]);
+        for (int v = 0; v < NV; ++v) F[v] -= -wr * fvn[UfLayout<D, P, T>::at(eR, v, fR)] - ph.tau * (uL[v] - uR[v]);
       } else if (wr == T(0)) {
-        for (int v = 0; v < NV; ++v) F[v] -= wl * fvn[(eL * NV + v) * Nf + fL] - ph.tau * (uL[v] - uR[v]);
+        for (int v = 0; v < NV; ++v) F[v] -= wl * fvn[UfLayout<D, P, T>::at(eL, v, fL)] - ph.tau * (uL[v] - uR[v]);
       } else {
         for (int v = 0; v < NV; ++v) {
-          const T fl = fvn[(eL * NV + v) * Nf + fL];
-          const T fr = fvn[(eR * NV + v) * Nf + fR];
+          const T fl = fvn[UfLayout<D, P, T>::at(eL, v, fL)];
+          const T fr = fvn[UfLayout<D, P, T>::at(eR, v, fR)];
           F[v] -= wl * fl - wr * fr - ph.tau * (uL[v] - uR[v]);
         }
       }
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256, 6) void k_face_flux(const T *__restrict__ uf, 
     }
     rusanov<D>(uB, ug, n, ph.gamma, ph.gm1, F);
     if (NS)
-      for (int v = 0; v < NV; ++v) F[v] -= fvn[(e * NV + v) * Nf + fp];
+      for (int v = 0; v < NV; ++v) F[v] -= fvn[UfLayout<D, P, T>::at(e, v, fp)];
     for (int v = 0; v < NV; ++v) fhat[UfLayout<D, P, T>::at(e, v, fp)] = F[v] * mag;
   }
 }
@@ -244,7 +244,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE,
   const int32_t *nbr_t = nbr + e0 * Nf;
   const T *fnrm_t = fnrm + e0 * (D + 1) * Nf, *metric_t = metric + e0 * NM * Ns;
   using UL = UfLayout<D, P, T>;  // layout of fhat (and u_f)
-  T *fvn_t = fvn + e0 * NV * Nf, *fhat_t = fhat + e0 * UL::EB, *vol_t = vol + e0 * NV * Ns;
+  T *fvn_t = fvn + e0 * UL::EB, *fhat_t = fhat + e0 * UL::EB, *vol_t = vol + e0 * NV * Ns;
   T *lu = lds;                // [E][NV][Ns]
   T *lw = lds + E * TL::LU;   // [E][NV][Nf] u^ - u_f; then [E][Ns][D][NV] gradient; [E][D][NV][Ns] F~
   int32_t *lcode = reinterpret_cast<int32_t *>(lw + E * NV * Nf);  // [E][Nf], until the gradient phase
@@ -514,7 +514,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE,
     T fv[NV];
     fvis_normal_stream<D>(st, gdir, n, fl.mu, ph, heat, fv);
     if (side == 0 || code < 0)
-      for (int v = 0; v < NV; ++v) fvn_t[(uint32_t)((elf * NV + v) * Nf + fp)] = fv[v];
+      for (int v = 0; v < NV; ++v) fvn_t[(uint32_t)UL::point(elf, fp) + v * UL::VS] = fv[v];
     if (side == 0) continue;
     // complete the common flux started in the first phase (same workgroup, ordered by the barriers)
     if (code < 0) {
@@ -960,7 +960,7 @@ __global__ __launch_bounds__(WALL_CHUNK) void k_wall_force(const T *__restrict__
     primitives<D>(uB, ph.gm1, rho, vel, p);
     const double wm = bw[b] * (double)bnrm[b * (D + 1) + D];
     for (int j = 0; j < D; ++j)
-      f[j] = wm * ((double)p * (double)bnrm[b * (D + 1) + j] - (double)fvn[(e * NV + 1 + j) * Nf + fp]);
+      f[j] = wm * ((double)p * (double)bnrm[b * (D + 1) + j] - (double)fvn[UfLayout<D, P, T>::at(e, 1 + j, fp)]);
   }
   for (int j = 0; j < D; ++j) red[threadIdx.x][j] = f[j];
   __syncthreads();

@@ -94,7 +94,7 @@ struct fr_solver {
   void *uf = nullptr;       // u_f: [Ne][2 dim][face stride] by face where faces fill two lines
                             // (uf_face_skip), else [Ne][NV][Nf]
   uint8_t *uf_faces = nullptr;  // [Ne] faces (bit f) whose u_f the stage kernels write
-  void *fvn = nullptr;      // [Ne][NV][Nf]   viscous normal flux at own flux points (NS)
+  void *fvn = nullptr;      // viscous normal flux at own flux points (NS), in the layout of uf
   void *vol = nullptr;      // [Ne][NV][Ns]   volume divergence (NS)
   void *fnrm = nullptr;     // [Ne][dim+1][Nf] outward unit normal at own flux points, then |N|
   void *fhat = nullptr;     // common flux x |N|, in the layout of uf

@@ -58,7 +58,7 @@ constexpr int64_t STATE_ALIGN = 64;   // values: group states start on 256-byte 
 template <typename T>
 struct GroupDev {
   const T *uf;        // own flux-point states (the degree's u_f layout)
-  const T *fvn;       // [Ne][NV][Nf] own viscous normal flux
+  const T *fvn;       // own viscous normal flux (u_f layout)
   T *fhat;            // transformed common normal flux (u_f layout)
   T *ifc_uh;          // [mortar point][NV] common solution at the mortar points
   const T *bnd_nrm;   // [boundary point][dim + 1] outward unit normal, |N|
@@ -93,7 +93,7 @@ __device__ __forceinline__ void stage_lower(const MortarFace &mf, const int8_t *
     const int v = k / Nlo, j = k % Nlo;
     const int fp = mf.f_lo * Nlo + perm[j];
     lo_u[j][v] = L.uf[gpt(L, mf.e_lo, fp) + v * L.VS];
-    if (lo_f) lo_f[j][v] = L.fvn[((int64_t)mf.e_lo * NV + v) * L.Nf + fp];
+    if (lo_f) lo_f[j][v] = L.fvn[gpt(L, mf.e_lo, fp) + v * L.VS];
   }
 }
 
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(MORTAR_BS) void k_mortar_flux(const MortarFace *__r
     {
       const int fph = mf.f_hi * Nm + i;
       for (int v = 0; v < NV; ++v) {
-        fh[v] = H.fvn[((int64_t)mf.e_hi * NV + v) * H.Nf + fph];
+        fh[v] = H.fvn[gpt(H, mf.e_hi, fph) + v * H.VS];
         fl[v] = T(0);
       }
       for (int j = 0; j < Nlo; ++j) {
