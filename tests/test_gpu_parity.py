@@ -114,6 +114,28 @@ def test_fp32_vs_fp64_oracle(name, gpu):
     assert eR <= 5e-4, eR
 
 
+@pytest.mark.parametrize("name", ["ns_ogrid", "ns_cgrid_p4"])
+def test_fp32_two_sided_ldg(name, gpu):
+    """FP32 with the two-sided LDG flux (beta = 0): every flux point's viscous normal flux is stored
+    (3-D p = 4: in the face-blocked layout) and the face kernel forms each pair's common flux."""
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    m, p, fp, eq, init, dt, probes = make_case(name)
+    fp.ldg_beta = 0.0
+    s = OracleSystem(m, p, fp, equations=eq)
+    u0 = torch.tensor(init(s.solpt_coords())).permute(0, 2, 1).contiguous()
+    sol = Solver(m, p, fp, equations=eq, precision="fp32")
+    eR = rel_l2(sol.rhs(u0.float().to(gpu)), s.residual(u0))
+    u = u0.float().to(gpu).clone()
+    sol.rk_step(u, torch.tensor(dt, dtype=torch.float64, device=gpu), 1)
+    uref, _, _ = s.run(u0, torch.tensor(dt), 1, sample_every=0)
+    torch.cuda.synchronize()
+    e1 = rel_l2(u, uref)
+    print(f"{name} beta 0 fp32: rhs rel L2 {eR:.3e}, 1 step {e1:.3e}")
+    assert e1 <= 1e-5, e1
+    assert eR <= 5e-4, eR
+
+
 def test_graph_replay_matches_direct_launches(gpu, monkeypatch):
     """Steps replayed from the captured graph equal the same steps launched directly, bit for bit,
     and two identical runs are bitwise identical (no atomics in the reductions)."""
