@@ -514,7 +514,7 @@ __global__ __launch_bounds__((GradTile<D, P, T, EE>::BS), (GradTile<D, P, T, EE,
     T fv[NV];
     fvis_normal_stream<D>(st, gdir, n, fl.mu, ph, heat, fv);
     if (side == 0 || code < 0)
-      for (int v = 0; v < NV; ++v) fvn_t[(uint32_t)UL::point(elf, fp) + v * UL::VS] = fv[v];
+      for (int v = 0; v < NV; ++v) fvn_t[(fo - fhat_t) + v * UL::VS] = fv[v];  // same offset as fo
     if (side == 0) continue;
     // complete the common flux started in the first phase (same workgroup, ordered by the barriers)
     if (code < 0) {
