@@ -2,26 +2,31 @@
 //
 // Data layout (element-major, per-element blocks are contiguous so a workgroup's tile of
 // elements is one contiguous range of HBM):
-//   state / residual      [Ne][NV][Ns]
-//   flux-point arrays     [Ne][NV][Nf]          (u_f, u^ - u_f, common flux)
-//   flux-point gradients  [Ne][dim][NV][Nf]
-//   metrics               [Ne][dim*dim + 1][Ns] (S = adj(dx/dxi) row-major, then 1/J)
+//   state, residual, RK arrays, volume term   [Ne][NV][Ns]
+//   u_f, common flux, viscous normal flux     UfLayout: [Ne][2 dim][face block], each face block
+//                                             [NV][Nfp] padded to whole 128-byte lines, where a
+//                                             face fills two lines; else [Ne][NV][Nf]
+//   metrics                                   [Ne][dim*dim + 1][Ns] (S = adj(dx/dxi) row-major, 1/J)
+//   neighbour codes [Ne][Nf] (int32), outward unit normals and |N| [Ne][dim + 1][Nf]
 // Element operators are applied in sum-factorised (tensor-product) form along the P points of
 // each reference line: every operator is a P x P contraction per line, so the whole stage is
-// bound by HBM traffic, not by arithmetic.  Volume kernels stage their element tile in LDS
-// once and read all line operands from LDS.
+// bound by HBM traffic and on-chip latency, not by arithmetic.  Volume kernels stage their
+// element tile in LDS once and read all line operands from LDS.
 //
 // Stage pipeline (Navier-Stokes), one launch each:
-//   interp      u_f = M0 u                                  (only before the first stage of a call;
-//                                                            later stages get u_f from div_rk)
-//   common_sol  u^ - u_f on both sides of every flux point (LDG u^ = (1/2+b) u_L + (1/2-b) u_R,
-//               boundary states for walls / far field)
-//   ns_grad     corrected gradient grad_xi u = D_k u + s_f g_R'(s_f xi) (u^ - u_f); grad_x u =
-//               J^-1 S^T grad_xi u; grad u_f = M0 grad_x u; F = F_inv - F_vis; F~_k = S_k . F;
-//               vol = sum_k D_k F~_k - Lift (s_f M0 F~_{k_f})
-//   face_flux   common normal flux (Rusanov - LDG viscous + penalty) x |N|, + on L, - on R
+//   interp      u_f = M0 u (only before the first stage of a call; later stages get u_f from
+//               div_rk)
+//   ns_grad     per element tile: own u_f = M0 u; LDG common solution u^ from the neighbour's u_f
+//               or the boundary state; corrected gradient grad_xi u = D_k u + s_f g_R'(s_f xi)
+//               (u^ - u_f); grad_x u = J^-1 S^T grad_xi u; viscous normal flux at the flux points
+//               whose value the common flux uses; with the one-sided LDG flux (beta = +-1/2) the
+//               flux side also forms its pair's whole common flux (Rusanov - LDG viscous +
+//               penalty) x |N|; F~_k = S_k . (F_inv - F_vis); vol = sum_k D~_k F~_k (the
+//               correction's interior part folded into D~)
+//   face_flux   two-sided LDG (beta != +-1/2): common normal flux per pair and boundary point
 //   div_rk      R = -(1/J) (vol + Lift F^_n); RK4 stage update; u_f of the new stage state
-// Euler drops common_sol / ns_grad and computes F~ and vol inside div_rk (euler_vol_rk).
+// Euler: face_flux, then euler_vol_rk (F~, vol, lifting and the RK update in one kernel).
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
