@@ -321,7 +321,7 @@ fr_status build_solver(const fr_mesh_desc *mesh, const fr_params *prm, bool grou
     s->wall_mesh_begin = (int64_t *)upload(s, c.wall_mesh_begin);
     s->flow = s->precision == FR_FP64 ? upload_flow<double>(s) : upload_flow<float>(s);
     const size_t T = s->tsize;
-    const size_t nsol = (size_t)s->Ne * s->NV * s->Ns, nf = (size_t)s->Ne * s->NV * s->Nf;
+    const size_t nsol = (size_t)s->Ne * s->NV * s->Ns;
     // u_f by face; where face blocks are line-sized (uf_face_skip) the stage kernels write only
     // the faces something reads later: with the one-sided LDG the side whose values the flux side
     // takes, and boundary faces (wall force); otherwise (small blocks, two-sided LDG, Euler: the

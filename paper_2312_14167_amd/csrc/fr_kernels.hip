@@ -733,7 +733,7 @@ __device__ __forceinline__ void div_rk_body(const T *__restrict__ vol, const T *
                                             const OpsDev<T, P> &ops_arg, const RKArgs<T> &rk, int64_t Ne) {
   using S = Shape<D, P>;
   using TL = DivTile<D, P, T, EE>;
-  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  constexpr int E = TL::E, Ns = S::Ns, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
   __shared__ uint8_t s_faces[E];
@@ -812,7 +812,7 @@ __device__ __forceinline__ void euler_vol_rk_body(
     int64_t Ne) {
   using S = Shape<D, P>;
   using TL = EulerTile<D, P, T, EE>;
-  constexpr int E = TL::E, Ns = S::Ns, Nf = S::Nf, Nfp = S::Nfp, NV = S::NV, NM = S::NM;
+  constexpr int E = TL::E, Ns = S::Ns, NV = S::NV, NM = S::NM;
   __shared__ __attribute__((aligned(16))) T lds[E * TL::LE];
   __shared__ OpsDev<T, P> ops;
   __shared__ uint8_t s_faces[E];
