@@ -264,3 +264,123 @@ def test_naca_sponge_full_size_sampled_residual(gpu):
         print(f"sponge element {e} grid {(i, j, k)} degree {deg[e]}: patch of {len(sel)} "
               f"(degrees {sorted(set(deg[sel].tolist()))}); residual rel L2 {err:.3e}")
         assert err <= FULL_SIZE_TOL, err
+
+
+def _face_centres(node_xyz, elem_nodes, d, q):
+    """[n_elem][2 d][d] face centres (mean of each face's corner nodes)."""
+    import itertools
+    cents = np.zeros((elem_nodes.shape[0], 2 * d, d))
+    for f in range(2 * d):
+        k, side = f // 2, f % 2
+        corners = []
+        for bits in itertools.product([0, q], repeat=d - 1):
+            idx, b = [0] * d, 0
+            for m in range(d):
+                if m == k:
+                    idx[m] = q * side
+                else:
+                    idx[m] = bits[b]
+                    b += 1
+            corners.append(sum(idx[m] * (q + 1) ** m for m in range(d)))
+        cents[:, f] = node_xyz[elem_nodes[:, corners]].mean(axis=1)
+    return cents
+
+
+def _neighbours(mesh, b0, b1):
+    """Face neighbours (global element indices) of the elements of one mesh of a batch
+    (elements b0..b1-1; faces pair only inside their own mesh)."""
+    from scipy.spatial import cKDTree
+    cents = _face_centres(mesh.node_xyz, mesh.elem_nodes[b0:b1], mesh.dim, mesh.q)
+    auto = np.argwhere(mesh.face_bc[b0:b1] == fi.FACE_AUTO)
+    pts = cents[auto[:, 0], auto[:, 1]]
+    scale = float(np.ptp(mesh.node_xyz[np.unique(mesh.elem_nodes[b0:b1])], axis=0).max())
+    tree = cKDTree(pts)
+    nbr = [[] for _ in range(b1 - b0)]
+    for a, b in tree.query_pairs(1e-9 * scale):
+        ea, eb = auto[a, 0], auto[b, 0]
+        nbr[ea].append(b0 + eb)
+        nbr[eb].append(b0 + ea)
+    return nbr
+
+
+def _rings(nbr, b0, e, n):
+    """Elements within n face steps of element e, in increasing index: the patch keeps the
+    elements' relative order, so every pair keeps its L side (the smaller element, face), which
+    decides the one-sided LDG flux."""
+    seen, front = {e}, [e]
+    for _ in range(n):
+        nxt = []
+        for x in front:
+            for y in nbr[x - b0]:
+                if y not in seen:
+                    seen.add(y)
+                    nxt.append(y)
+        front = nxt
+    return np.array(sorted(seen), dtype=np.int64)
+
+
+def _submesh(mesh, sel):
+    used = np.unique(mesh.elem_nodes[sel])
+    remap = -np.ones(mesh.node_xyz.shape[0], dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    return fi.MeshDesc(dim=mesh.dim, q=mesh.q, node_xyz=mesh.node_xyz[used], elem_nodes=remap[mesh.elem_nodes[sel]],
+                       face_bc=mesh.face_bc[sel].copy(), periodic_vec=mesh.periodic_vec.copy(),
+                       mesh_elem_begin=np.array([0, len(sel)], dtype=np.int64))
+
+
+def test_batched_cavities_full_size_sampled(gpu):
+    """The bench's batched poll at full size (16 cavities, 367k quads, p = 4, one solver): sampled
+    elements (next to a wall, next to the far field, interior) of three cavities.  FP64: the
+    residual against the oracle on the two-step neighbourhood (exact, as above).  FP32, at the
+    autotuned tiles the bench times: one RK4 step against the oracle's FP64 step on the ten-step
+    neighbourhood (a stage's residual reaches two face steps, so the four stages of a step leave
+    the centre untouched by the patch's outer boundary), per element: density and energy per
+    variable, momentum as a vector (its cross-stream part is 1e-3 noise)."""
+    import dataclasses
+
+    import bench
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    bm, bfp, bprobes, counts = bench.cavity_batch()
+    s64 = Solver(bm, 4, bfp, equations="ns", precision="fp64")
+    u = bench.initial_state(s64, bfp, bm, 5)
+    R = s64.rhs(u.to(gpu)).cpu()
+    xs = s64.solpt_coords()
+    dt = 1e-5
+    dtg = torch.full((bm.n_mesh,), dt, dtype=torch.float64, device=gpu)
+    s32 = Solver(bm, 4, bfp, equations="ns", precision="fp32", probes=bprobes, probe_mesh=np.arange(bm.n_mesh),
+                 max_samples=8, forces=True)
+    u32 = u.float().to(gpu)
+    tiles = s32.autotune(u32, dtg, reps=2, kinds=bench.FORWARD_KINDS)
+    s32.rk_step(u32, dtg, 1, sample_every=1)
+    u1 = u32.double().cpu()
+    d = bm.dim
+    rng = np.random.default_rng(1)
+    for m in (0, 7, 15):
+        b0, b1 = int(bm.mesh_elem_begin[m]), int(bm.mesh_elem_begin[m + 1])
+        nbr = _neighbours(bm, b0, b1)
+        fb = bm.face_bc[b0:b1]
+        walls = np.nonzero((fb == fi.BC_WALL).any(axis=1))[0]
+        far = np.nonzero((fb == fi.BC_FARFIELD).any(axis=1))[0]
+        picks = [b0 + int(walls[len(walls) // 2]), b0 + int(far[len(far) // 3]), b0 + int(rng.integers(0, b1 - b0))]
+        fp_m = dataclasses.replace(bfp, rho_inf=bfp.rho_inf[m:m + 1], vel_inf=bfp.vel_inf[m:m + 1],
+                                   p_inf=bfp.p_inf[m:m + 1], mu=bfp.mu[m:m + 1])
+        for e in picks:
+            sel = _rings(nbr, b0, e, 2)
+            le = int(np.nonzero(sel == e)[0][0])
+            s = _close_patch(_submesh(bm, sel), OracleSystem, 4, fp_m)
+            np.testing.assert_allclose(s.solpt_coords()[le], xs[e], atol=1e-12)
+            err = _rel(R[e].numpy(), s.residual(u[sel])[le].numpy())
+            sel10 = _rings(nbr, b0, e, 10)
+            le10 = int(np.nonzero(sel10 == e)[0][0])
+            s10 = _close_patch(_submesh(bm, sel10), OracleSystem, 4, fp_m)
+            ref = s10.rk4_step(u[sel10], torch.tensor([dt], dtype=torch.float64))[le10]
+            diff = (u1[e] - ref) ** 2
+            e_rho = float(diff[0].sum().sqrt() / (ref[0] ** 2).sum().sqrt())
+            e_en = float(diff[-1].sum().sqrt() / (ref[-1] ** 2).sum().sqrt())
+            e_mom = float(diff[1:1 + d].sum().sqrt() / (ref[1:1 + d] ** 2).sum().sqrt())
+            print(f"cavity {m} element {e} (patches {len(sel)} / {len(sel10)}): FP64 residual rel L2 {err:.3e}; "
+                  f"FP32 step rho {e_rho:.2e} energy {e_en:.2e} momentum {e_mom:.2e}")
+            assert err <= FULL_SIZE_TOL, err
+            assert max(e_rho, e_en, e_mom) <= 5e-7, (e_rho, e_en, e_mom)  # 10x the measured 5.5e-8
+    print("FP32 tiles", {k: (v["elements_per_workgroup"], v["waves_per_simd_bound"]) for k, v in tiles.items()})
