@@ -384,3 +384,47 @@ def test_batched_cavities_full_size_sampled(gpu):
             assert err <= FULL_SIZE_TOL, err
             assert max(e_rho, e_en, e_mom) <= 5e-7, (e_rho, e_en, e_mom)  # 10x the measured 5.5e-8
     print("FP32 tiles", {k: (v["elements_per_workgroup"], v["waves_per_simd_bound"]) for k, v in tiles.items()})
+
+
+def test_naca_cgrid_full_size_fp32_step(gpu):
+    """The FP32 form at the headline size in the launch configuration the bench times (192k
+    hexes, autotuned tiles, FP64 probe and force sampling): one RK4 step from the bench's start
+    against the oracle's FP64 step on the index-space box of radius 10 around sampled elements (a
+    stage's residual reaches two face steps, so four stages leave the centre untouched by the
+    box's outer boundary; the whole span, periodic).  Per element: density and energy per
+    variable, momentum as a vector (its cross-stream part is 1e-3 noise)."""
+    import bench
+    from oracle import OracleSystem
+    from paper_2312_14167_amd import Solver
+    mesh, fp, _ = bench.naca_workload(scale=1.0)
+    s32 = Solver(mesh, 4, fp, equations="ns", precision="fp32", probes=mesh.info["probe"][None, :], max_samples=8,
+                 forces=True)
+    u = bench.initial_state(s32, fp, mesh, 5)
+    dt = 5e-7
+    dtg = torch.full((1,), dt, dtype=torch.float64, device=gpu)
+    u32 = u.float().to(gpu)
+    tiles = s32.autotune(u32, dtg, reps=2, kinds=bench.FORWARD_KINDS)
+    s32.rk_step(u32, dtg, 1, sample_every=1)
+    u1 = u32.double().cpu()
+    gi = mesh.info["grid_index"]
+    na, nn, nz = gi[:, 0].max() + 1, gi[:, 1].max() + 1, gi[:, 2].max() + 1
+    rng = np.random.default_rng(3)
+    # wall of the section, outer boundary, interior (boxes clear of the wake cut)
+    picks = [(100, 0, 11), (150, 79, 6), (int(rng.integers(60, 140)), int(rng.integers(11, 69)), int(rng.integers(0, nz)))]
+    d = mesh.dim
+    for (i, j, k) in picks:
+        e = int(np.nonzero((gi[:, 0] == i) & (gi[:, 1] == j) & (gi[:, 2] == k))[0][0])
+        ib = [x for x in range(i - 10, i + 11) if 0 <= x < na]
+        jb = [x for x in range(j - 10, j + 11) if 0 <= x < nn]
+        sel, sub = _patch(mesh, e, [[ib, jb, list(range(nz))]])
+        s = _close_patch(sub, OracleSystem, 4, fp)
+        le = int(np.nonzero(sel == e)[0][0])
+        ref = s.rk4_step(u[sel], torch.tensor([dt], dtype=torch.float64))[le]
+        diff = (u1[e] - ref) ** 2
+        e_rho = float(diff[0].sum().sqrt() / (ref[0] ** 2).sum().sqrt())
+        e_en = float(diff[-1].sum().sqrt() / (ref[-1] ** 2).sum().sqrt())
+        e_mom = float(diff[1:1 + d].sum().sqrt() / (ref[1:1 + d] ** 2).sum().sqrt())
+        print(f"C-grid element {(i, j, k)} (box of {len(sel)}): FP32 step rho {e_rho:.2e} energy {e_en:.2e} "
+              f"momentum {e_mom:.2e}")
+        assert max(e_rho, e_en, e_mom) <= 5e-7, (e_rho, e_en, e_mom)  # about 10x the measured 3.6e-8
+    print("FP32 tiles", {k: (v["elements_per_workgroup"], v["waves_per_simd_bound"], v["engine"]) for k, v in tiles.items()})
