@@ -442,3 +442,68 @@ def test_naca_cgrid_full_size_fp32_step(gpu):
     box's outer boundary; the whole span, periodic).  Per element: density and energy per
     variable, momentum as a vector (its cross-stream part is 1e-3 noise)."""
     _cgrid_step_check(gpu, "fp32", 5e-7)  # about 10x the measured 3.6e-8
+
+
+def test_naca_sponge_full_size_fp32_step(gpu):
+    """The sponge's FP32 step at full size as the bench runs it (192k hexes, degrees 4 -> 0, FP64
+    probe and force sampling): one RK4 step from the bench's start against the variable-degree
+    oracle's FP64 step on the index box of radius 10 (whole span) around elements next to a 3/4
+    and a 0/1 degree jump (boxes clear of the wake cut).  Per element: density and energy per
+    variable, momentum as a vector."""
+    import bench
+    from oracle.vardeg import VarDegreeOracle
+    from paper_2312_14167_amd.vardeg import VarDegreeSolver
+    mesh, fp, _ = bench.naca_workload(scale=1.0)
+    deg = fi.sponge_degrees(mesh, radii=bench.SPONGE_RADII)
+    sol = VarDegreeSolver(mesh, deg, fp, precision="fp32", probes=mesh.info["probe"][None, :], max_samples=8,
+                          forces=True)
+    parts = []
+    for g, x in enumerate(sol.solpt_coords()):
+        ug = fi.freestream_state(x, fp)
+        ug[..., 1:-1] += fi.noise_like(ug.shape, 5 + g, 1e-3)[..., 1:-1]
+        parts.append(torch.tensor(ug).permute(0, 2, 1).contiguous())
+    dt = 5e-7
+    u32 = sol.join([p_.float() for p_ in parts])
+    sol.rk_step(u32, torch.full((1,), dt, dtype=torch.float64, device=gpu), 1, sample_every=1)
+    U1 = [x.double().cpu() for x in sol.split(u32)]
+    where = {}
+    for g, el in enumerate(sol.elems):
+        for l, e in enumerate(el):
+            where[int(e)] = (g, l)
+    gi = mesh.info["grid_index"]
+    na, nn, nz = gi[:, 0].max() + 1, gi[:, 1].max() + 1, gi[:, 2].max() + 1
+    index = {tuple(int(v) for v in gi[e]): e for e in range(mesh.n_elem)}
+
+    def jump(e, lo, hi):
+        i, j, k = (int(v) for v in gi[e])
+        if deg[e] != hi or not (11 <= j <= nn - 12 and 10 <= i <= na - 11):
+            return False
+        for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            n = index.get((i + di, j + dj, k))
+            if n is not None and deg[n] == lo:
+                return True
+        return False
+    d = mesh.dim
+    for lo, hi in ((3, 4), (0, 1)):
+        e = next(e for e in range(0, mesh.n_elem, 3) if jump(e, lo, hi))
+        i, j, k = (int(v) for v in gi[e])
+        ib = [x for x in range(i - 10, i + 11) if 0 <= x < na]
+        jb = [x for x in range(j - 10, j + 11) if 0 <= x < nn]
+        sel, sub = _patch(mesh, e, [[ib, jb, list(range(nz))]])
+        v = _close_patch(sub, lambda m_, p_, f_, equations: VarDegreeOracle(m_, deg[sel], f_, equations=equations),
+                         None, fp)
+        up = []
+        for G in v.groups:
+            rows = [parts[where[int(sel[le])][0]][where[int(sel[le])][1]] for le in G.elems]
+            up.append(torch.stack(rows))
+        ref_all = v.rk4_step(up, torch.tensor([dt], dtype=torch.float64))
+        le = int(np.nonzero(sel == e)[0][0])
+        ref = ref_all[int(v.gidx[le])][int(v.lidx[le])]
+        g, l = where[e]
+        diff = (U1[g][l] - ref) ** 2
+        e_rho = float(diff[0].sum().sqrt() / (ref[0] ** 2).sum().sqrt())
+        e_en = float(diff[-1].sum().sqrt() / (ref[-1] ** 2).sum().sqrt())
+        e_mom = float(diff[1:1 + d].sum().sqrt() / (ref[1:1 + d] ** 2).sum().sqrt())
+        print(f"sponge FP32 element {(i, j, k)} degree {deg[e]} next to {lo} (box of {len(sel)}): step rho "
+              f"{e_rho:.2e} energy {e_en:.2e} momentum {e_mom:.2e}", flush=True)
+        assert max(e_rho, e_en, e_mom) <= 5e-7, (e_rho, e_en, e_mom)  # about 10x the measured 3.1e-8
