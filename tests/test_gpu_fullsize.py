@@ -44,25 +44,9 @@ def _patch(mesh, centre, nbr_boxes):
 def _close_patch(sub, oracle_cls, p, fp):
     """Tag AUTO faces of the patch without a partner inside it (they lie >= 3 faces from the
     centre) as far field, then build the oracle on the patch."""
-    import itertools
-
     from scipy.spatial import cKDTree
-    d, q = sub.dim, sub.q
-    nf = 2 * d
-    cents = np.zeros((sub.n_elem, nf, d))
-    for f in range(nf):
-        k, side = f // 2, f % 2
-        corners = []
-        for bits in itertools.product([0, q], repeat=d - 1):
-            idx, b = [0] * d, 0
-            for m in range(d):
-                if m == k:
-                    idx[m] = q * side
-                else:
-                    idx[m] = bits[b]
-                    b += 1
-            corners.append(sum(idx[m] * (q + 1) ** m for m in range(d)))
-        cents[:, f] = sub.node_xyz[sub.elem_nodes[:, corners]].mean(axis=1)
+    d = sub.dim
+    cents = _face_centres(sub.node_xyz, sub.elem_nodes, d, sub.q)
     auto = np.argwhere(sub.face_bc == fi.FACE_AUTO)
     pts = cents[auto[:, 0], auto[:, 1]]
     tree = cKDTree(pts)
