@@ -615,6 +615,12 @@ def main():
             log(f"  {pr}: {rs_['gdofs']:.2f} GDoF-stage/s, {rs_['ms_per_step']:.2f} ms/step "
                 f"({rs_['step_time_vs_uniform_p4']:.2f} of uniform p=4)")
         result["variants"]["sponge_p4_to_p0"] = {"radii_chords": list(SPONGE_RADII), **sp}
+        log("interface kernel forms: two-sided LDG and Euler on the same C-grid (FP64)")
+        itf = interface_forms(mesh, fp, K, W)
+        for name, r_ in itf.items():
+            log(f"  {name}: {r_['gdofs']:.2f} GDoF-stage/s; face kernel "
+                f"{r_['kernels']['face_flux']['frac']:.3f} of the HBM roofline")
+        result["variants"]["interface_forms_fp64"] = itf
         del mesh
         log("batched poll: 16 cavities, FP32, one launch per kernel over all meshes")
         bm, bfp, bprobes, counts = cavity_batch()
