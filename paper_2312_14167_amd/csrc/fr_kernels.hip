@@ -1003,17 +1003,19 @@ __global__ __launch_bounds__(64) void k_wall_force_sum(const double *__restrict_
 // k_probe_vjp_coef (one workgroup per probe, fixed reduction trees) forms each probe's
 // coefficients p_bar dp/du_v and p_bar dp/dxi_k; k_probe_vjp_scatter (one workgroup) adds them into
 // u_bar and x_bar probe by probe, so probes that share an element or nodes add in a fixed order.
+// One probe: k_probe_vjp_one does both in one workgroup (one launch instead of two).
+
+// coefficients of probe a into out[NV + D] (thread 0 writes; every thread of the workgroup calls)
 template <int D, int P, typename T>
-__global__ __launch_bounds__(PROBE_BS) void k_probe_vjp_coef(const T *__restrict__ u, const int64_t *__restrict__ pelem,
-                                                             const double *__restrict__ pw,
-                                                             const double *__restrict__ pdw, double gm1,
-                                                             const double *__restrict__ pbar, bool geo,
-                                                             double *__restrict__ coef) {
+__device__ __forceinline__ void probe_vjp_coef_body(const T *__restrict__ u, const int64_t *__restrict__ pelem,
+                                                    const double *__restrict__ pw, const double *__restrict__ pdw,
+                                                    double gm1, const double *__restrict__ pbar, bool geo, int a,
+                                                    double *out) {
   using S = Shape<D, P>;
   constexpr int NV = S::NV, Ns = S::Ns;
   __shared__ double red[NV][PROBE_BS];
   __shared__ double dpdu[NV];
-  const int a = blockIdx.x, i = threadIdx.x;
+  const int i = threadIdx.x;
   const int64_t e = pelem[a];
   double uv[NV];
   for (int v = 0; v < NV; ++v) uv[v] = i < Ns ? (double)u[(e * NV + v) * Ns + i] : 0.0;
@@ -1033,7 +1035,7 @@ __global__ __launch_bounds__(PROBE_BS) void k_probe_vjp_coef(const T *__restrict
     dpdu[0] = gm1 * 0.5 * m2 / (red[0][0] * red[0][0]);
     for (int j = 0; j < D; ++j) dpdu[1 + j] = -gm1 * red[1 + j][0] / red[0][0];
     dpdu[D + 1] = gm1;
-    for (int v = 0; v < NV; ++v) coef[(int64_t)a * (NV + D) + v] = pb * dpdu[v];
+    for (int v = 0; v < NV; ++v) out[v] = pb * dpdu[v];
   }
   if (!geo) return;
   __syncthreads();
@@ -1053,7 +1055,39 @@ __global__ __launch_bounds__(PROBE_BS) void k_probe_vjp_coef(const T *__restrict
     __syncthreads();
   }
   if (i == 0)
-    for (int k = 0; k < D; ++k) coef[(int64_t)a * (NV + D) + NV + k] = pb * red[k][0];
+    for (int k = 0; k < D; ++k) out[NV + k] = pb * red[k][0];
+}
+
+// probe a's coefficients c added into u_bar and (xbar != nullptr) x_bar by one workgroup
+template <int D, int P, typename T>
+__device__ __forceinline__ void probe_vjp_scatter_one(const int64_t *__restrict__ pelem, const double *__restrict__ pw,
+                                                      const double *__restrict__ pdxi,
+                                                      const int64_t *__restrict__ pnodes, int nn, int a,
+                                                      const double *c, T *ubar, double *xbar) {
+  using S = Shape<D, P>;
+  constexpr int NV = S::NV, Ns = S::Ns;
+  const int64_t e = pelem[a];
+  for (int idx = threadIdx.x; idx < NV * Ns; idx += blockDim.x) {
+    const int v = idx / Ns, i = idx % Ns;
+    ubar[(e * NV + v) * Ns + i] += (T)(c[v] * pw[(int64_t)a * Ns + i]);
+  }
+  if (xbar)
+    for (int idx = threadIdx.x; idx < nn * D; idx += blockDim.x) {
+      const int n = idx / D, j = idx % D;
+      double sx = 0.0;
+      for (int k = 0; k < D; ++k) sx += pdxi[(((int64_t)a * nn + n) * D + j) * D + k] * c[NV + k];
+      xbar[pnodes[(int64_t)a * nn + n] * D + j] += sx;
+    }
+}
+
+template <int D, int P, typename T>
+__global__ __launch_bounds__(PROBE_BS) void k_probe_vjp_coef(const T *__restrict__ u, const int64_t *__restrict__ pelem,
+                                                             const double *__restrict__ pw,
+                                                             const double *__restrict__ pdw, double gm1,
+                                                             const double *__restrict__ pbar, bool geo,
+                                                             double *__restrict__ coef) {
+  constexpr int NC = Shape<D, P>::NV + D;
+  probe_vjp_coef_body<D, P, T>(u, pelem, pw, pdw, gm1, pbar, geo, (int)blockIdx.x, coef + (int64_t)blockIdx.x * NC);
 }
 
 template <int D, int P, typename T>
@@ -1062,24 +1096,25 @@ __global__ __launch_bounds__(256) void k_probe_vjp_scatter(const int64_t *__rest
                                                            const double *__restrict__ pdxi,
                                                            const int64_t *__restrict__ pnodes, int nn, int n_probe,
                                                            const double *__restrict__ coef, T *ubar, double *xbar) {
-  using S = Shape<D, P>;
-  constexpr int NV = S::NV, Ns = S::Ns;
+  constexpr int NC = Shape<D, P>::NV + D;
   for (int a = 0; a < n_probe; ++a) {
-    const int64_t e = pelem[a];
-    const double *c = coef + (int64_t)a * (NV + D);
-    for (int idx = threadIdx.x; idx < NV * Ns; idx += blockDim.x) {
-      const int v = idx / Ns, i = idx % Ns;
-      ubar[(e * NV + v) * Ns + i] += (T)(c[v] * pw[(int64_t)a * Ns + i]);
-    }
-    if (xbar)
-      for (int idx = threadIdx.x; idx < nn * D; idx += blockDim.x) {
-        const int n = idx / D, j = idx % D;
-        double sx = 0.0;
-        for (int k = 0; k < D; ++k) sx += pdxi[(((int64_t)a * nn + n) * D + j) * D + k] * c[NV + k];
-        xbar[pnodes[(int64_t)a * nn + n] * D + j] += sx;
-      }
+    probe_vjp_scatter_one<D, P, T>(pelem, pw, pdxi, pnodes, nn, a, coef + (int64_t)a * NC, ubar, xbar);
     __syncthreads();  // the next probe may share this element or its nodes
   }
+}
+
+template <int D, int P, typename T>
+__global__ __launch_bounds__(PROBE_BS) void k_probe_vjp_one(const T *__restrict__ u, const int64_t *__restrict__ pelem,
+                                                            const double *__restrict__ pw,
+                                                            const double *__restrict__ pdw, double gm1,
+                                                            const double *__restrict__ pbar,
+                                                            const double *__restrict__ pdxi,
+                                                            const int64_t *__restrict__ pnodes, int nn, T *ubar,
+                                                            double *xbar) {
+  __shared__ double c[Shape<D, P>::NV + D];
+  probe_vjp_coef_body<D, P, T>(u, pelem, pw, pdw, gm1, pbar, xbar != nullptr, 0, c);
+  __syncthreads();
+  probe_vjp_scatter_one<D, P, T>(pelem, pw, pdxi, pnodes, nn, 0, c, ubar, xbar);
 }
 
 // RK4 adjoint combination.  init (z == nullptr): a = ub; kb = dt ca ub; zz = 0.
@@ -1427,7 +1462,11 @@ Dispatch make_dispatch() {
                             residuals ? (T *)residuals + 4 * nb * k : nullptr);
   };
   d.probe_vjp = [](const fr_solver *s, const void *u, const double *pbar, void *ub, double *xbar, hipStream_t st) {
-    if (s->n_probe > 0) {
+    if (s->n_probe == 1) {
+      k_probe_vjp_one<D, P, T><<<1, PROBE_BS, 0, st>>>((const T *)u, s->probe_elem, s->probe_w, s->probe_dw,
+                                                       s->gamma - 1.0, pbar, s->probe_dxi, s->probe_nodes,
+                                                       s->geo_nn, (T *)ub, xbar);
+    } else if (s->n_probe > 1) {
       k_probe_vjp_coef<D, P, T><<<(unsigned)s->n_probe, PROBE_BS, 0, st>>>(
           (const T *)u, s->probe_elem, s->probe_w, s->probe_dw, s->gamma - 1.0, pbar, xbar != nullptr, s->probe_coef);
       k_probe_vjp_scatter<D, P, T><<<1, 256, 0, st>>>(s->probe_elem, s->probe_w, s->probe_dxi, s->probe_nodes,
